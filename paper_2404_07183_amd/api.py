@@ -1,0 +1,237 @@
+"""PyTorch-facing helpers over the C ABI.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+computation runs in ``libpcf.so``. A :class:`PcfSet` holds one ragged CSR set
+of PCFs on the GPU (``offsets`` int64, ``t`` and ``v`` FP32 or FP64) plus a
+host copy of the offsets, so planning needs no device-to-host copy.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
+                   PCF_RECORDS_PACKED, PCF_REUSE_PLAN, PCF_UPPER_ONLY,
+                   PCF_VALIDATE, check)
+
+__all__ = ["PcfSet", "Workspace", "pdist", "gram", "pairwise_backward",
+           "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
+           "PCF_LP", "PCF_LP_POW", "PCF_GRAM"]
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class PcfSet:
+    """A CSR set of PCFs resident on one GPU."""
+
+    def __init__(self, offsets, t, v, device="cuda"):
+        if isinstance(offsets, torch.Tensor):
+            offsets = offsets.detach().cpu().numpy()
+        self.offsets_host = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.offsets = torch.as_tensor(self.offsets_host, device=device)
+        self.t = torch.as_tensor(t, device=device).contiguous()
+        self.v = torch.as_tensor(v, device=device).contiguous()
+        if self.t.dtype != self.v.dtype or self.t.dtype not in (torch.float32, torch.float64):
+            raise TypeError("t and v must both be float32 or both float64")
+        if self.t.numel() != self.v.numel() or self.t.numel() != int(self.offsets_host[-1]):
+            raise ValueError("t, v and offsets disagree on the number of rows")
+        self.n = len(self.offsets_host) - 1
+
+    @property
+    def dtype(self):
+        return self.t.dtype
+
+    def with_values(self, t, v):
+        """Same offsets, new (t, v) tensors (e.g. ones that require grad)."""
+        new = object.__new__(PcfSet)
+        new.offsets_host, new.offsets, new.n = self.offsets_host, self.offsets, self.n
+        new.t, new.v = t.contiguous(), v.contiguous()
+        return new
+
+    def c_struct(self):
+        return _lib.pcf_set(
+            self.n, self.offsets.data_ptr(), self.t.data_ptr(), self.v.data_ptr(),
+            PCF_F64 if self.t.dtype == torch.float64 else PCF_F32,
+            self.offsets_host.ctypes.data)
+
+
+class Workspace:
+    """Device workspace; keeps the tile plan between calls on one set."""
+
+    def __init__(self, nbytes=0, device="cuda"):
+        self.buf = None
+        self.device = device
+        self.planned = None
+        self.packed_data = None
+        self.ensure(nbytes)
+
+    def ensure(self, nbytes):
+        nbytes = int(max(nbytes, 256))
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.planned = None
+            self.packed_data = None
+        return self
+
+    @property
+    def ptr(self):
+        return self.buf.data_ptr()
+
+    @property
+    def nbytes(self):
+        return self.buf.numel()
+
+
+def _window(window):
+    if window is None:
+        return None
+    r0, r1, c0, c1 = (int(x) for x in window)
+    return _lib.pcf_window(r0, r1, c0, c1)
+
+
+def _flags(upper_only, validate, reuse):
+    return ((PCF_UPPER_ONLY if upper_only else 0) | (PCF_VALIDATE if validate else 0)
+            | (PCF_REUSE_PLAN if reuse else 0))
+
+
+def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
+             packed=False):
+    Xc = X.c_struct()
+    win = _window(window)
+    if window is None:
+        shape = (X.n, X.n)
+    else:
+        shape = (window[1] - window[0], window[3] - window[2])
+    if out is None:
+        out = torch.zeros(shape, dtype=X.dtype, device=X.t.device)
+    if out.dtype != X.dtype or out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a row-major 2-D tensor of the input dtype")
+    ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
+    key = ("fwd", kind, X.n, id(X.offsets_host), window, upper_only)
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    reuse = ws.planned == key
+    if not reuse:
+        ws.ensure(_lib.pcf_workspace_bytes(Xc, kind, win, 0))
+    flags = _flags(upper_only, validate, reuse)
+    if packed:
+        if not reuse or ws.packed_data != (X.t.data_ptr(), X.v.data_ptr()):
+            raise ValueError("packed=True needs an earlier call on the same set, "
+                             "data and workspace")
+        flags |= PCF_RECORDS_PACKED
+    if kind == PCF_GRAM:
+        st = _lib.pcf_gram(Xc, out.data_ptr(), ldo, win, ws.ptr, ws.nbytes, flags,
+                           _stream_handle(stream))
+    else:
+        st = _lib.pcf_pairwise_lp(Xc, kind, float(p), out.data_ptr(), ldo, win, ws.ptr,
+                                  ws.nbytes, flags, _stream_handle(stream))
+    check(st)
+    ws.planned = key
+    ws.planned_ref = X.offsets_host  # keeps id() in the key unique
+    ws.packed_data = (X.t.data_ptr(), X.v.data_ptr())
+    return out
+
+
+def pdist(X, p=1.0, *, power=False, window=None, out=None, upper_only=False,
+          validate=False, workspace=None, stream=None, packed=False):
+    """L_p distance matrix (``power=True``: d_p^p) of the PCFs in ``X``.
+
+    ``packed=True`` skips re-packing the breakpoint records: only valid when
+    ``workspace`` served the previous call on this very set and data."""
+    return _forward(X, PCF_LP_POW if power else PCF_LP, p, window, out, upper_only,
+                    validate, workspace, stream, packed)
+
+
+def gram(X, *, window=None, out=None, upper_only=False, validate=False,
+         workspace=None, stream=None, packed=False):
+    """L2 Gram matrix of the PCFs in ``X``."""
+    return _forward(X, PCF_GRAM, 0.0, window, out, upper_only, validate, workspace,
+                    stream, packed)
+
+
+def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None):
+    """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, FP64)."""
+    Xc = X.c_struct()
+    grad_out = grad_out.to(torch.float64).contiguous()
+    gt = torch.empty_like(X.t)
+    gv = torch.empty_like(X.v)
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    ws.ensure(_lib.pcf_workspace_bytes(Xc, kind, None, 1))
+    fptr, ldf = (fwd_out.data_ptr(), fwd_out.stride(0)) if fwd_out is not None else (None, 0)
+    st = _lib.pcf_pairwise_backward(Xc, kind, float(p), grad_out.data_ptr(),
+                                    grad_out.stride(0), fptr, ldf, gt.data_ptr(),
+                                    gv.data_ptr(), ws.ptr, ws.nbytes, 0,
+                                    _stream_handle(stream))
+    check(st)
+    ws.planned = None
+    return gt, gv
+
+
+def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=None,
+                     upper_only=False, validate=False, stream=None):
+    """Independent full matrices of the problems ``set_offsets`` cuts ``X``
+    into, in one launch. Returns ``(out_flat, out_offsets)``: problem b's
+    s_b x s_b matrix is ``out_flat[out_offsets[b]:][:s_b*s_b]``."""
+    so = np.ascontiguousarray(set_offsets, dtype=np.int64)
+    B = len(so) - 1
+    sizes = np.diff(so)
+    oo = np.zeros(B, dtype=np.int64)
+    if B > 1:
+        oo[1:] = np.cumsum(sizes[:-1] ** 2)
+    total = int((sizes ** 2).sum())
+    if out is None:
+        out = torch.zeros(total, dtype=X.dtype, device=X.t.device)
+    Xc = X.c_struct()
+    key = ("batched", kind, X.n, id(X.offsets_host), so.tobytes(), upper_only)
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    reuse = ws.planned == key
+    if not reuse:
+        ws.ensure(_lib.pcf_batched_workspace_bytes(B, so.ctypes.data, Xc))
+    st = _lib.pcf_pairwise_batched(B, so.ctypes.data, Xc, kind, float(p), out.data_ptr(),
+                                   oo.ctypes.data, ws.ptr, ws.nbytes,
+                                   _flags(upper_only, validate, reuse),
+                                   _stream_handle(stream))
+    check(st)
+    ws.planned = key
+    ws.planned_ref = X.offsets_host
+    return out, oo
+
+
+def validate(X, stream=None):
+    """Index of the first PCF that breaks the data contract, or -1."""
+    ws = torch.empty(256, dtype=torch.uint8, device=X.t.device)
+    return _lib.pcf_validate(X.c_struct(), ws.data_ptr(), 256, _stream_handle(stream))
+
+
+class PairwiseMatrix(torch.autograd.Function):
+    """F(C) as a differentiable function of the breakpoint times and values.
+
+    Forward runs the pairwise kernel; backward runs the adjoint kernel, which
+    recomputes every pair's merge (nothing is stored between the two)."""
+
+    @staticmethod
+    def forward(ctx, t, v, X, kind, p):
+        Xv = X.with_values(t.detach(), v.detach())
+        out = _forward(Xv, kind, p, None, None, False, False, None, None)
+        ctx.X, ctx.kind, ctx.p = Xv, kind, p
+        ctx.save_for_backward(out)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (out,) = ctx.saved_tensors
+        need_fwd = ctx.kind == PCF_LP and ctx.p != 1.0
+        gt, gv = pairwise_backward(ctx.X, ctx.kind, ctx.p, grad_out,
+                                   out.to(torch.float64) if need_fwd else None)
+        return gt, gv, None, None, None
+
+
+def pairwise_matrix(X, t, v, kind=PCF_LP, p=1.0):
+    """Differentiable F(C) over ``X``'s offsets with times ``t`` and values
+    ``v`` (tensors that may require grad)."""
+    return PairwiseMatrix.apply(t, v, X, kind, p)

@@ -1,0 +1,478 @@
+// abi.hip -- the C ABI declared in include/pcf.h: argument checks, host
+// planning, workspace set-up and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "pcf.h"
+#include "plan.hpp"
+
+
+using namespace pcf;
+
+namespace {
+
+thread_local std::string g_err;
+
+pcf_status fail(pcf_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+pcf_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(PCF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int rec_bytes_of(pcf_dtype d) { return d == PCF_F64 ? 16 : 8; }
+
+constexpr int HK_ABS = kAbs, HK_SQR = kSqr, HK_PROD = kProd, HK_POW = kPow;
+
+int device_cus()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 256;
+    static int cached[64] = {0};
+    if (dev >= 0 && dev < 64 && cached[dev] > 0)
+        return cached[dev];
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                              dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (dev >= 0 && dev < 64)
+        cached[dev] = cus;
+    return cus;
+}
+
+pcf_status check_set(const pcf_set *X)
+{
+    if (!X)
+        return fail(PCF_EINVAL, "X is NULL");
+    if (X->n < 0)
+        return fail(PCF_EINVAL, "X->n < 0");
+    if (X->dtype != PCF_F32 && X->dtype != PCF_F64)
+        return fail(PCF_EINVAL, "X->dtype is not PCF_F32 or PCF_F64");
+    if (X->n > 0 && (!X->offsets || !X->t || !X->v))
+        return fail(PCF_EINVAL, "X has a NULL device pointer");
+    return PCF_OK;
+}
+
+// Host copy of X->offsets (the caller's, or a synchronous device copy).
+pcf_status host_offsets(const pcf_set *X, std::vector<int64_t> &buf,
+                        const int64_t *&out, hipStream_t s)
+{
+    if (X->offsets_host) {
+        out = X->offsets_host;
+        return PCF_OK;
+    }
+    buf.resize((size_t)X->n + 1);
+    hipError_t e = hipMemcpyAsync(buf.data(), X->offsets,
+                                  sizeof(int64_t) * (size_t)(X->n + 1),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "copying offsets to the host");
+    out = buf.data();
+    return PCF_OK;
+}
+
+// Copy a plan's header, blocks and segments into the workspace.
+pcf_status upload_plan(const Plan &plan, int rec_bytes, void *ws,
+                       size_t ws_bytes, hipStream_t s)
+{
+    const int64_t need = plan_workspace_bytes(plan, rec_bytes);
+    if ((int64_t)ws_bytes < need)
+        return fail(PCF_ENOMEM, "workspace too small: need " +
+                                    std::to_string(need) + " bytes, got " +
+                                    std::to_string(ws_bytes));
+    if (plan.rec_count >= ((int64_t)1 << 31))
+        return fail(PCF_EUNSUPPORTED,
+                    "more than 2^31 breakpoint records in one set");
+    std::vector<unsigned char> buf;
+    WsHeader hdr;
+    plan_serialise(plan, rec_bytes, buf, hdr);
+    hipError_t e = hipMemcpyAsync(ws, buf.data(), buf.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // buf is a local
+    if (e != hipSuccess)
+        return hip_fail(e, "uploading the tile plan");
+    return PCF_OK;
+}
+
+pcf_status run_validation(const pcf_set *X, unsigned char *ws, int64_t P,
+                          hipStream_t s, int64_t *first_bad)
+{
+    const int64_t init = std::numeric_limits<int64_t>::max();
+    hipError_t e = hipMemcpyAsync(ws + offsetof(WsHeader, first_bad), &init,
+                                  sizeof(init), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "validation set-up");
+    e = X->dtype == PCF_F64
+            ? launch_validate<double>(X->offsets, X->n, X->t, X->v, ws, P, s)
+            : launch_validate<float>(X->offsets, X->n, X->t, X->v, ws, P, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "validation launch");
+    int64_t bad = init;
+    e = hipMemcpyAsync(&bad, ws + offsetof(WsHeader, first_bad), sizeof(bad),
+                       hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "validation read-back");
+    *first_bad = (bad == init) ? -1 : bad;
+    return PCF_OK;
+}
+
+struct Call {
+    bool reuse;
+    bool validate;
+    int64_t P;  // rows, -1 when unknown (plan reused)
+};
+
+pcf_status prepare(const pcf_set *X, const Plan *plan, void *ws,
+                   size_t ws_bytes, uint32_t flags, hipStream_t s, Call &c,
+                   const int64_t *ho)
+{
+    c.reuse = (flags & PCF_REUSE_PLAN) != 0;
+    c.validate = (flags & PCF_VALIDATE) != 0;
+    c.P = ho ? ho[X->n] : -1;
+    if (!c.reuse) {
+        pcf_status st = upload_plan(*plan, rec_bytes_of(X->dtype), ws,
+                                    ws_bytes, s);
+        if (st != PCF_OK)
+            return st;
+    }
+    if (c.validate) {
+        if (c.P < 0)
+            return fail(PCF_EINVAL, "PCF_VALIDATE needs host offsets when "
+                                    "the plan is reused");
+        int64_t bad = -1;
+        pcf_status st = run_validation(X, (unsigned char *)ws, c.P, s, &bad);
+        if (st != PCF_OK)
+            return st;
+        if (bad >= 0)
+            return fail(PCF_EDATA, "PCF " + std::to_string(bad) +
+                                       " breaks the data contract (first "
+                                       "time 0, strictly increasing finite "
+                                       "times, finite values, last value 0)");
+    }
+    if ((flags & PCF_RECORDS_PACKED) && !c.reuse)
+        return fail(PCF_EINVAL, "PCF_RECORDS_PACKED needs PCF_REUSE_PLAN");
+    unsigned char *w = (unsigned char *)ws;
+    hipError_t e = launch_reset(w, s);
+    if (e == hipSuccess && !(flags & PCF_RECORDS_PACKED)) {
+        // grid-stride; with an unknown row count use a full-chip grid
+        const int64_t P = c.P >= 0 ? c.P : (int64_t)1 << 40;
+        e = X->dtype == PCF_F64
+                ? launch_pack<double>(X->offsets, X->n, X->t, X->v, w, P, s)
+                : launch_pack<float>(X->offsets, X->n, X->t, X->v, w, P, s);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "packing breakpoint records");
+    return PCF_OK;
+}
+
+int tile_grid(const Plan *plan, bool reuse)
+{
+    int grid = device_cus();
+    if (!reuse && plan && plan->ntiles < grid)
+        grid = (int)(plan->ntiles > 0 ? plan->ntiles : 1);
+    return grid;
+}
+
+pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
+                          int64_t ldo, const pcf_window *w, void *ws,
+                          size_t ws_bytes, uint32_t flags, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (kind != PCF_LP && kind != PCF_LP_POW && kind != PCF_GRAM)
+        return fail(PCF_EINVAL, "unknown kind");
+    if (kind != PCF_GRAM && (!(p >= 1.0) || !isfinite(p)))
+        return fail(PCF_EINVAL, "p must be finite and >= 1");
+    if (X->n == 0)
+        return PCF_OK;
+    if (!out || !ws)
+        return fail(PCF_EINVAL, "out or ws is NULL");
+    if (w && (w->row0 < 0 || w->row1 < w->row0 || w->row1 > X->n ||
+              w->col0 < 0 || w->col1 < w->col0 || w->col1 > X->n))
+        return fail(PCF_EINVAL, "window out of range");
+    const int64_t width = w ? (w->col1 - w->col0) : X->n;
+    if (ldo < width || ldo < 1)
+        return fail(PCF_EINVAL, "ldo smaller than the output width");
+    if (w && (w->row1 == w->row0 || w->col1 == w->col0))
+        return PCF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const bool reuse = (flags & PCF_REUSE_PLAN) != 0;
+
+    Plan plan;
+    std::vector<int64_t> obuf;
+    const int64_t *ho = X->offsets_host;
+    if (!reuse) {
+        st = host_offsets(X, obuf, ho, s);
+        if (st != PCF_OK)
+            return st;
+        std::string err;
+        if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), false, w != nullptr,
+                         w ? w->row0 : 0, w ? w->row1 : 0, w ? w->col0 : 0,
+                         w ? w->col1 : 0, (flags & PCF_UPPER_ONLY) != 0, ldo,
+                         plan, err))
+            return fail(PCF_EINVAL, err);
+    }
+    Call c;
+    st = prepare(X, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho);
+    if (st != PCF_OK)
+        return st;
+
+    FwdArgs a;
+    a.offsets = X->offsets;
+    a.ws = (unsigned char *)ws;
+    a.out = out;
+    a.p = p;
+    a.inv_p = 1.0 / p;
+    a.gram = kind == PCF_GRAM ? 1 : 0;
+    int hk;
+    if (kind == PCF_GRAM) {
+        hk = HK_PROD;
+        a.root = 0;
+    } else {
+        hk = (p == 1.0) ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW);
+        a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
+    }
+    hipError_t e = launch_forward(X->dtype == PCF_F64, hk, a,
+                                  tile_grid(reuse ? nullptr : &plan, reuse), s);
+    if (e != hipSuccess)
+        return hip_fail(e, "tile kernel launch");
+    return PCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pcf_last_error(void) { return g_err.c_str(); }
+
+int pcf_abi_version(void) { return 1; }
+
+pcf_status pcf_workspace_bytes(const pcf_set *X, pcf_kind kind,
+                               const pcf_window *w, int backward,
+                               size_t *bytes)
+{
+    (void)kind;
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (!bytes)
+        return fail(PCF_EINVAL, "bytes is NULL");
+    if (X->n == 0) {
+        *bytes = (size_t)kHeaderBytes;
+        return PCF_OK;
+    }
+    std::vector<int64_t> obuf;
+    const int64_t *ho = nullptr;
+    st = host_offsets(X, obuf, ho, nullptr);
+    if (st != PCF_OK)
+        return st;
+    Plan plan;
+    std::string err;
+    const int64_t ldo = w ? (w->col1 - w->col0) : X->n;
+    if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), backward != 0,
+                     w != nullptr, w ? w->row0 : 0, w ? w->row1 : 0,
+                     w ? w->col0 : 0, w ? w->col1 : 0, false,
+                     ldo > 0 ? ldo : 1, plan, err))
+        return fail(PCF_EINVAL, err);
+    *bytes = (size_t)plan_workspace_bytes(plan, rec_bytes_of(X->dtype));
+    return PCF_OK;
+}
+
+pcf_status pcf_pairwise_lp(const pcf_set *X, pcf_kind kind, double p,
+                           void *out, int64_t ldo, const pcf_window *w,
+                           void *ws, size_t ws_bytes, uint32_t flags,
+                           void *stream)
+{
+    if (kind != PCF_LP && kind != PCF_LP_POW)
+        return fail(PCF_EINVAL, "pcf_pairwise_lp takes PCF_LP or PCF_LP_POW");
+    return forward_common(X, kind, p, out, ldo, w, ws, ws_bytes, flags,
+                          stream);
+}
+
+pcf_status pcf_gram(const pcf_set *X, void *out, int64_t ldo,
+                    const pcf_window *w, void *ws, size_t ws_bytes,
+                    uint32_t flags, void *stream)
+{
+    return forward_common(X, PCF_GRAM, 0.0, out, ldo, w, ws, ws_bytes, flags,
+                          stream);
+}
+
+pcf_status pcf_batched_workspace_bytes(int32_t B,
+                                       const int64_t *set_offsets_host,
+                                       const pcf_set *all, size_t *bytes)
+{
+    pcf_status st = check_set(all);
+    if (st != PCF_OK)
+        return st;
+    if (!bytes)
+        return fail(PCF_EINVAL, "bytes is NULL");
+    std::vector<int64_t> obuf;
+    const int64_t *ho = nullptr;
+    if (all->n > 0) {
+        st = host_offsets(all, obuf, ho, nullptr);
+        if (st != PCF_OK)
+            return st;
+    }
+    std::vector<int64_t> oo((size_t)(B > 0 ? B : 0), 0);
+    Plan plan;
+    std::string err;
+    if (!plan_batched(B, set_offsets_host, oo.data(), ho, all->n,
+                      rec_bytes_of(all->dtype), false, plan, err))
+        return fail(PCF_EINVAL, err);
+    *bytes = (size_t)plan_workspace_bytes(plan, rec_bytes_of(all->dtype));
+    return PCF_OK;
+}
+
+pcf_status pcf_pairwise_batched(int32_t B, const int64_t *set_offsets_host,
+                                const pcf_set *all, pcf_kind kind, double p,
+                                void *out, const int64_t *out_offsets_host,
+                                void *ws, size_t ws_bytes, uint32_t flags,
+                                void *stream)
+{
+    pcf_status st = check_set(all);
+    if (st != PCF_OK)
+        return st;
+    if (kind != PCF_LP && kind != PCF_LP_POW && kind != PCF_GRAM)
+        return fail(PCF_EINVAL, "unknown kind");
+    if (kind != PCF_GRAM && (!(p >= 1.0) || !isfinite(p)))
+        return fail(PCF_EINVAL, "p must be finite and >= 1");
+    if (B < 0)
+        return fail(PCF_EINVAL, "B < 0");
+    if (B == 0 || all->n == 0)
+        return PCF_OK;
+    if (!out || !ws)
+        return fail(PCF_EINVAL, "out or ws is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool reuse = (flags & PCF_REUSE_PLAN) != 0;
+    Plan plan;
+    std::vector<int64_t> obuf;
+    const int64_t *ho = all->offsets_host;
+    if (!reuse) {
+        if (!set_offsets_host || !out_offsets_host)
+            return fail(PCF_EINVAL, "set_offsets_host or out_offsets_host is NULL");
+        st = host_offsets(all, obuf, ho, s);
+        if (st != PCF_OK)
+            return st;
+        std::string err;
+        if (!plan_batched(B, set_offsets_host, out_offsets_host, ho, all->n,
+                          rec_bytes_of(all->dtype),
+                          (flags & PCF_UPPER_ONLY) != 0, plan, err))
+            return fail(PCF_EINVAL, err);
+    }
+    Call c;
+    st = prepare(all, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho);
+    if (st != PCF_OK)
+        return st;
+    FwdArgs a;
+    a.offsets = all->offsets;
+    a.ws = (unsigned char *)ws;
+    a.out = out;
+    a.p = p;
+    a.inv_p = 1.0 / p;
+    a.gram = kind == PCF_GRAM ? 1 : 0;
+    int hk;
+    if (kind == PCF_GRAM) {
+        hk = HK_PROD;
+        a.root = 0;
+    } else {
+        hk = (p == 1.0) ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW);
+        a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
+    }
+    hipError_t e = launch_forward(all->dtype == PCF_F64, hk, a,
+                                  tile_grid(reuse ? nullptr : &plan, reuse), s);
+    if (e != hipSuccess)
+        return hip_fail(e, "tile kernel launch");
+    return PCF_OK;
+}
+
+pcf_status pcf_validate(const pcf_set *X, int64_t *first_bad, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (!first_bad)
+        return fail(PCF_EINVAL, "first_bad is NULL");
+    if (!ws || ws_bytes < (size_t)kHeaderBytes)
+        return fail(PCF_ENOMEM, "validation needs 256 bytes of workspace");
+    *first_bad = -1;
+    if (X->n == 0)
+        return PCF_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> obuf;
+    const int64_t *ho = nullptr;
+    st = host_offsets(X, obuf, ho, s);
+    if (st != PCF_OK)
+        return st;
+    for (int64_t i = 0; i < X->n; ++i) {
+        if (ho[i + 1] <= ho[i]) {
+            *first_bad = i;
+            return PCF_OK;
+        }
+    }
+    return run_validation(X, (unsigned char *)ws, ho[X->n], s, first_bad);
+}
+
+pcf_status pcf_plan_inspect(int64_t n, const int64_t *offsets_host,
+                            pcf_dtype dtype, const pcf_window *w,
+                            int backward, int64_t *nblocks, int64_t *nseg,
+                            int64_t *ntiles, int32_t *blocks_out,
+                            int64_t blocks_cap)
+{
+    if (dtype != PCF_F32 && dtype != PCF_F64)
+        return fail(PCF_EINVAL, "bad dtype");
+    Plan plan;
+    std::string err;
+    const int64_t ldo = w ? (w->col1 - w->col0) : n;
+    if (!plan_matrix(n, offsets_host, rec_bytes_of(dtype), backward != 0,
+                     w != nullptr, w ? w->row0 : 0, w ? w->row1 : 0,
+                     w ? w->col0 : 0, w ? w->col1 : 0, false,
+                     ldo > 0 ? ldo : 1, plan, err))
+        return fail(PCF_EINVAL, err);
+    const int64_t nb = plan.blocks.empty() ? 0 : (int64_t)plan.blocks.size() - 1;
+    if (nblocks)
+        *nblocks = nb;
+    if (nseg)
+        *nseg = (int64_t)plan.segs.size();
+    if (ntiles)
+        *ntiles = plan.ntiles;
+    if (blocks_out)
+        for (int64_t i = 0; i < (int64_t)plan.blocks.size() && i < blocks_cap; ++i)
+            blocks_out[i] = plan.blocks[i];
+    return PCF_OK;
+}
+
+pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
+                                 const void *grad_out, int64_t ldg,
+                                 const void *fwd_out, int64_t ldf,
+                                 void *grad_t, void *grad_v, void *ws,
+                                 size_t ws_bytes, uint32_t flags,
+                                 void *stream)
+{
+    (void)X; (void)kind; (void)p; (void)grad_out; (void)ldg; (void)fwd_out;
+    (void)ldf; (void)grad_t; (void)grad_v; (void)ws; (void)ws_bytes;
+    (void)flags; (void)stream;
+    return fail(PCF_EUNSUPPORTED, "backward not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// common.hpp -- types and constants shared by the host planner, the HIP
+// kernels and the C-ABI layer of the PCF library (not by the CPU oracle).
+#pragma once
+
+#include <stdint.h>
+
+namespace pcf {
+
+// Merge steps per unrolled block of the inner loop. A pair's step count is
+// rounded up to a multiple of this; the extra steps run past both
+// sentinels and add exactly 0.
+constexpr int kStepBlock = 8;
+// Padding records after each PCF's last record so that those extra steps
+// stay inside the PCF's own records.
+constexpr int kPad = kStepBlock - 1;
+// Threads per tile workgroup (16 waves of 64 lanes).
+constexpr int kThreads = 1024;
+// Most PCFs in one block (so a tile has at most kThreads pairs).
+constexpr int kMaxBlock = 32;
+constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
+// LDS bytes a tile may use for breakpoint records (of 160 KiB per
+// workgroup on gfx950; the rest holds per-pair prefix sums, accumulators
+// and block metadata).
+constexpr int kLdsRecordBytes = 132 * 1024;
+// Number of hardware XCDs (each with its own L2) on MI355X.
+constexpr int kXcds = 8;
+
+enum SegType : int32_t { kSegTriangle = 0, kSegRect = 1 };
+
+// A run of tiles sharing one output mapping. Triangle: all block pairs
+// (I, J) with b0 <= I <= J < b1, column-major over the upper triangle.
+// Rectangle: I in [b0, b1), J in [c0, c1), row-major.
+struct Segment {
+    int64_t tile_begin;  // index of the segment's first tile
+    int64_t obase;       // output element offset of entry (row0, col0)
+    int64_t ldo;         // output leading dimension (elements)
+    int64_t row0, col0;  // PCF indices of output row 0 / column 0
+    int32_t b0, b1, c0, c1;
+    int32_t type;
+    int32_t mirror;      // 1: also write the transposed entry
+};
+
+// Head of the device workspace. Written by the host planner (copied in
+// once per plan) and read by every kernel, so a call that reuses a plan
+// needs nothing from the host.
+struct WsHeader {
+    uint32_t counter[kXcds];  // tile counters, reset before each launch
+    int64_t ntiles;
+    int64_t nseg;
+    int64_t nblocks;
+    int64_t npcf;
+    int64_t off_blocks;   // byte offsets inside the workspace
+    int64_t off_segs;
+    int64_t off_rec;
+    int64_t rec_count;    // records in the packed array
+    int64_t rec_bytes;    // bytes per record (8 FP32, 16 FP64)
+    int64_t first_bad;    // validation result (PCF index or -1)
+    int64_t lds_records;  // records a tile may hold in LDS
+    int64_t reserved[5];
+};
+static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
+
+constexpr int64_t kHeaderBytes = 256;
+
+inline int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace pcf

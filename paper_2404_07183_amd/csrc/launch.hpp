@@ -1,0 +1,55 @@
+// launch.hpp -- kernel argument blocks and launcher entry points shared by
+// the C-ABI layer (abi.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace pcf {
+
+// h codes of the combination integral (Section 2.2 of the paper).
+enum HKind : int { kAbs = 0, kSqr = 1, kProd = 2, kPow = 3 };
+// r codes of the combination integral.
+enum Root : int { kRootNone = 0, kRootSqrt = 1, kRootPow = 2 };
+
+struct FwdArgs {
+    const int64_t *offsets;  // device CSR offsets
+    unsigned char *ws;       // workspace (plan + packed records)
+    void *out;               // output matrix (dtype of the input)
+    double p;                // exponent for kPow
+    double inv_p;            // for kRootPow
+    int root;                // Root
+    int gram;                // 1: diagonal pairs carry work (Gram)
+};
+
+struct BwdArgs {
+    const int64_t *offsets;
+    unsigned char *ws;
+    const double *grad_out;  // dL/dF, n x n, leading dimension ldg
+    int64_t ldg;
+    const double *fwd_out;   // forward result (for the root's chain factor)
+    int64_t ldf;
+    double *grad_t;          // dL/dt, CSR layout (accumulated)
+    double *grad_v;          // dL/dv, CSR layout (accumulated)
+    double p;
+    int chain;               // 1: scale by dF/dI = (1/p) I^(1/p - 1)
+};
+
+template <typename T>
+hipError_t launch_pack(const int64_t *offsets, int64_t n, const void *t,
+                       const void *v, unsigned char *ws, int64_t P,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_validate(const int64_t *offsets, int64_t n, const void *t,
+                           const void *v, unsigned char *ws, int64_t P,
+                           hipStream_t s);
+hipError_t launch_reset(unsigned char *ws, hipStream_t s);
+hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
+                          hipStream_t s);
+hipError_t launch_backward(int hk, const BwdArgs &a, int grid, hipStream_t s);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+size_t tile_shared_bytes(int rec_bytes, bool backward);
+
+}  // namespace pcf

@@ -1,0 +1,106 @@
+"""CPU-side checks of the HIP library: it loads, exports every symbol that
+include/pcf.h declares, rejects bad arguments before touching a device, and
+its host planner tiles the matrix as documented. No GPU compute runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_07183_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "pcf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _header_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.exported_names(), name
+    assert lib.pcf_abi_version() == 1
+
+
+def test_argument_errors_need_no_device():
+    lib = _lib.load()
+    # NULL set
+    st = lib.pcf_pairwise_lp(None, _lib.PCF_LP, 1.0, None, 1, None, None, 0, 0, None)
+    assert st == _lib.PCF_EINVAL
+    assert "NULL" in _lib.last_error()
+    X = _lib.pcf_set(0, None, None, None, _lib.PCF_F64, None)
+    # p < 1 and non-finite p
+    for p in (0.5, float("nan"), float("inf")):
+        st = lib.pcf_pairwise_lp(ctypes.byref(X), _lib.PCF_LP, p, None, 1, None, None, 0, 0, None)
+        assert st == _lib.PCF_EINVAL
+    # wrong kind for pcf_pairwise_lp
+    st = lib.pcf_pairwise_lp(ctypes.byref(X), _lib.PCF_GRAM, 1.0, None, 1, None, None, 0, 0, None)
+    assert st == _lib.PCF_EINVAL
+    # empty set is a no-op
+    st = lib.pcf_pairwise_lp(ctypes.byref(X), _lib.PCF_LP, 1.0, None, 1, None, None, 0, 0, None)
+    assert st == _lib.PCF_OK
+    st = lib.pcf_gram(ctypes.byref(X), None, 1, None, None, 0, 0, None)
+    assert st == _lib.PCF_OK
+    # bad dtype
+    Xb = _lib.pcf_set(0, None, None, None, 7, None)
+    assert lib.pcf_gram(ctypes.byref(Xb), None, 1, None, None, 0, 0, None) == _lib.PCF_EINVAL
+    # n < 0
+    Xn = _lib.pcf_set(-1, None, None, None, _lib.PCF_F64, None)
+    assert lib.pcf_gram(ctypes.byref(Xn), None, 1, None, None, 0, 0, None) == _lib.PCF_EINVAL
+
+
+def _inspect(offsets, dtype=_lib.PCF_F64, window=None, backward=False):
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(o) - 1
+    buf = np.zeros(n + 2, dtype=np.int32)
+    nb, ns, nt = _lib.pcf_plan_inspect(n, o.ctypes.data, dtype,
+                                       _lib.pcf_window(*window) if window else None,
+                                       backward, len(buf), buf.ctypes.data)
+    return nb, ns, nt, buf[:nb + 1]
+
+
+def test_planner_full_matrix_blocks():
+    rng = np.random.default_rng(0)
+    counts = rng.integers(1, 600, size=500)
+    o = np.concatenate([[0], np.cumsum(counts)])
+    for dtype, rec, bwd in [(_lib.PCF_F64, 16, False), (_lib.PCF_F32, 8, False),
+                            (_lib.PCF_F64, 16, True)]:
+        nb, ns, nt, blocks = _inspect(o, dtype, backward=bwd)
+        per = rec + (16 if bwd else 0)
+        budget = (132 * 1024 // per) // 2
+        assert blocks[0] == 0 and blocks[-1] == 500
+        assert np.all(np.diff(blocks) >= 1) and np.all(np.diff(blocks) <= 32)
+        for a, b in zip(blocks[:-1], blocks[1:]):
+            recs = int(np.sum(counts[a:b] + 7))
+            assert recs <= budget or b - a == 1
+            # greedy: the next PCF would not have fitted
+            if b < 500 and b - a < 32:
+                assert recs + counts[b] + 7 > budget
+        assert ns == 1 and nt == nb * (nb + 1) // 2
+
+
+def test_planner_windows_cover_each_pair_once():
+    rng = np.random.default_rng(1)
+    counts = rng.integers(1, 300, size=200)
+    o = np.concatenate([[0], np.cumsum(counts)])
+    for win in [(0, 200, 0, 200), (10, 70, 40, 190), (0, 50, 100, 200), (60, 61, 0, 200),
+                (30, 90, 30, 90)]:
+        nb, ns, nt, blocks = _inspect(o, window=win)
+        r0, r1, c0, c1 = win
+        for cut in (r0, r1, c0, c1):
+            assert cut in set(blocks.tolist())
+        assert nt >= 1 and ns >= 1
+
+
+def test_planner_rejects_empty_pcf():
+    o = np.array([0, 3, 3, 5], dtype=np.int64)
+    with pytest.raises(_lib.PcfError) as e:
+        _inspect(o)
+    assert "no rows" in str(e.value)
