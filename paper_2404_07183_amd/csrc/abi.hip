@@ -469,10 +469,68 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
                                  size_t ws_bytes, uint32_t flags,
                                  void *stream)
 {
-    (void)X; (void)kind; (void)p; (void)grad_out; (void)ldg; (void)fwd_out;
-    (void)ldf; (void)grad_t; (void)grad_v; (void)ws; (void)ws_bytes;
-    (void)flags; (void)stream;
-    return fail(PCF_EUNSUPPORTED, "backward not built yet");
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (kind != PCF_LP && kind != PCF_LP_POW && kind != PCF_GRAM)
+        return fail(PCF_EINVAL, "unknown kind");
+    if (kind != PCF_GRAM && (!(p >= 1.0) || !isfinite(p)))
+        return fail(PCF_EINVAL, "p must be finite and >= 1");
+    if (X->dtype != PCF_F64)
+        return fail(PCF_EUNSUPPORTED, "the adjoint is implemented for FP64 only");
+    if (X->n == 0)
+        return PCF_OK;
+    const bool chain = kind == PCF_LP && p != 1.0;
+    if (!grad_out || !grad_t || !grad_v || !ws)
+        return fail(PCF_EINVAL, "grad_out, grad_t, grad_v or ws is NULL");
+    if (chain && !fwd_out)
+        return fail(PCF_EINVAL, "PCF_LP with p != 1 needs the forward result");
+    if (ldg < X->n || (chain && ldf < X->n))
+        return fail(PCF_EINVAL, "leading dimension smaller than n");
+    hipStream_t s = (hipStream_t)stream;
+    const bool reuse = (flags & PCF_REUSE_PLAN) != 0;
+    Plan plan;
+    std::vector<int64_t> obuf;
+    const int64_t *ho = X->offsets_host;
+    if (!reuse) {
+        st = host_offsets(X, obuf, ho, s);
+        if (st != PCF_OK)
+            return st;
+        std::string err;
+        if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), true, false, 0, 0,
+                         0, 0, false, X->n, plan, err))
+            return fail(PCF_EINVAL, err);
+    }
+    Call c;
+    st = prepare(X, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho);
+    if (st != PCF_OK)
+        return st;
+    const int64_t P = ho ? ho[X->n] : -1;
+    if (P < 0)
+        return fail(PCF_EINVAL, "the adjoint needs host offsets");
+    hipError_t e = launch_zero((double *)grad_t, P, s);
+    if (e == hipSuccess)
+        e = launch_zero((double *)grad_v, P, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "clearing the gradients");
+    BwdArgs a;
+    a.offsets = X->offsets;
+    a.ws = (unsigned char *)ws;
+    a.grad_out = (const double *)grad_out;
+    a.ldg = ldg;
+    a.fwd_out = (const double *)fwd_out;
+    a.ldf = ldf;
+    a.grad_t = (double *)grad_t;
+    a.grad_v = (double *)grad_v;
+    a.p = p;
+    a.chain = chain ? 1 : 0;
+    a.gram = kind == PCF_GRAM ? 1 : 0;
+    const int hk = kind == PCF_GRAM ? HK_PROD
+                                    : (p == 1.0 ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW));
+    e = launch_backward(hk, a, tile_grid(reuse ? nullptr : &plan, reuse), s);
+    if (e != hipSuccess)
+        return hip_fail(e, "adjoint kernel launch");
+    return PCF_OK;
 }
 
 }  // extern "C"

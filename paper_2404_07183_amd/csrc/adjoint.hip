@@ -1,0 +1,307 @@
+// adjoint.hip -- the backward pass of the pairwise matrix: dL/dt and dL/dv
+// of every breakpoint for a loss L with dL/dF_ij = G_ij.
+//
+// The paper only remarks (Section 3, after Algorithm "CombineIntegrate")
+// that the integral's parameter derivatives are analytic. Differentiating
+// I = sum over cells of h(a, b) * width:
+//   dI/dv_f[k] = sum over cells where f takes value v_f[k] of
+//                (dh/da)(a, b) * width;
+//   dI/dt_f[k] = h(v_f[k-1], g(t_k)) - h(v_f[k], g(t_k))   (k >= 1), with
+//                g(t_k) taken just after / just before t_k for the right /
+//                left derivative; where g also breaks at t_k the mean of
+//                the two one-sided derivatives is used.
+// The g side follows from the symmetry of h. The first time and the last
+// value of each PCF are fixed parameters (gradient 0). For the L_p distance
+// the chain factor dF/dI = (1/p) F^(1-p) is applied (0 when F = 0).
+//
+// Each pair's merge is recomputed -- the same tiles, the same even split of
+// a tile's steps over the lanes and the same merge-path starts as the
+// forward kernel -- so nothing is stored between forward and backward. A
+// lane keeps the value gradient of its current two pieces in registers and
+// adds it to an LDS accumulator (one per breakpoint record of the tile) when
+// the piece ends; time gradients go to LDS at each breakpoint. The tile then
+// adds its LDS accumulators to dL/dt, dL/dv in HBM with atomics.
+#include <hip/hip_runtime.h>
+
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+#include "tile.hpp"
+
+namespace pcf {
+
+// dh/da at (a, b) for h in {|a-b|, (a-b)^2, ab, |a-b|^p}; sign(0) = 0.
+template <int HK>
+__device__ __forceinline__ double dhda(double a, double b, double p)
+{
+    if constexpr (HK == kProd) {
+        return b;
+    } else {
+        const double d = a - b;
+        const double s = (d > 0.0) ? 1.0 : ((d < 0.0) ? -1.0 : 0.0);
+        if constexpr (HK == kAbs)
+            return s;
+        else if constexpr (HK == kSqr)
+            return 2.0 * d;
+        else
+            return p * pow(fabs(d), p - 1.0) * s;
+    }
+}
+
+// Gradient accumulators of one side of a pair: slot q holds (dL/dt, dL/dv)
+// of record q -- record q is (t_{k+1}, v_k) of the PCF, so the value
+// gradient of piece k goes to slot k and the time gradient of breakpoint
+// t_{k+1} goes to slot k + 1. In LDS mode the slots are in LDS next to the
+// records; in global mode they are the output arrays themselves, reached
+// through the PCF's row base.
+struct GradSink {
+    double *gt;  // indexed by record index
+    double *gv;
+    int32_t last;  // record index of the PCF's last row (fixed value)
+};
+
+__device__ __forceinline__ void sink_add_t(const GradSink &s, int32_t q, double x)
+{
+    atomicAdd(&s.gt[q], x);
+}
+__device__ __forceinline__ void sink_add_v(const GradSink &s, int32_t q, double x)
+{
+    if (q < s.last)
+        atomicAdd(&s.gv[q], x);
+}
+
+// Steps [d, d + m) of pair (A, B) with weight W; records from `src` (LDS or
+// global), gradients to the two sinks. m is a multiple of kStepBlock.
+template <int HK, typename Src>
+__device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
+                                             int32_t B, int32_t nb, int64_t d,
+                                             int64_t m, double W, double p,
+                                             const GradSink &sa,
+                                             const GradSink &sb)
+{
+    const double S = sentinel<double>();
+    int32_t ia, ib;
+    double x;
+    pair_start<double>(src, A, na, B, nb, d, ia, ib, x);
+    Rec<double> ra = src[ia], rb = src[ib];
+    double gva = 0.0, gvb = 0.0;  // value gradients of the current pieces
+    for (int64_t q = 0; q < m; ++q) {
+        const double y = ra.t <= rb.t ? ra.t : rb.t;
+        const double w = y - x;
+        gva += dhda<HK>(ra.v, rb.v, p) * w;
+        gvb += dhda<HK>(rb.v, ra.v, p) * w;
+        if (ra.t <= rb.t) {
+            // the row side's breakpoint at y
+            const Rec<double> na_ = src[ia + 1];
+            if (y < S) {
+                double dta;
+                if (rb.t == y) {
+                    // the column side breaks at y too: mean of the one-sided
+                    // derivatives, for both breakpoints (the column side's
+                    // own step at y, next, has width 0 and adds nothing)
+                    const double bn = src[ib + 1].v;
+                    dta = 0.5 * (hval<double, HK>(ra.v, bn, p) - hval<double, HK>(na_.v, bn, p) +
+                                 hval<double, HK>(ra.v, rb.v, p) - hval<double, HK>(na_.v, rb.v, p));
+                    const double dtb =
+                        0.5 * (hval<double, HK>(na_.v, rb.v, p) - hval<double, HK>(na_.v, bn, p) +
+                               hval<double, HK>(ra.v, rb.v, p) - hval<double, HK>(ra.v, bn, p));
+                    sink_add_t(sb, ib + 1, W * dtb);
+                } else {
+                    dta = hval<double, HK>(ra.v, rb.v, p) - hval<double, HK>(na_.v, rb.v, p);
+                }
+                sink_add_t(sa, ia + 1, W * dta);
+            }
+            sink_add_v(sa, ia, W * gva);
+            gva = 0.0;
+            ++ia;
+            ra = na_;
+        } else {
+            // the column side's breakpoint at y (strictly before the row
+            // side's next one); a width-0 step is the second half of a tie
+            // already handled above
+            const Rec<double> nb_ = src[ib + 1];
+            if (y < S && y > x) {
+                const double dtb =
+                    hval<double, HK>(ra.v, rb.v, p) - hval<double, HK>(ra.v, nb_.v, p);
+                sink_add_t(sb, ib + 1, W * dtb);
+            }
+            sink_add_v(sb, ib, W * gvb);
+            gvb = 0.0;
+            ++ib;
+            rb = nb_;
+        }
+        x = y;
+    }
+    sink_add_v(sa, ia, W * gva);
+    sink_add_v(sb, ib, W * gvb);
+}
+
+template <int HK>
+__global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    TileShared &sh = *reinterpret_cast<TileShared *>(smem);
+    const WsHeader &h = hdr_of(args.ws);
+    Rec<double> *lrec = reinterpret_cast<Rec<double> *>(smem + kSharedHead);
+    // gradient slots (gt, gv) follow the record slots
+    double *lg = reinterpret_cast<double *>(lrec + h.lds_records);
+    const Rec<double> *grec = reinterpret_cast<const Rec<double> *>(args.ws + h.off_rec);
+    const int64_t *offsets = args.offsets;
+    const int tid = threadIdx.x;
+    const double p = args.p;
+
+    for (;;) {
+        if (!tile_setup<double>(sh, lrec, args.ws, offsets, args.gram))
+            break;
+        const int32_t R = sh.R, C = sh.C, npairs = sh.npairs;
+        const bool diag = sh.diag != 0, gmode = sh.global_mode != 0;
+        const int64_t total = sh.pw[npairs];
+        const int64_t nslots = diag ? sh.rrecs : sh.rrecs + sh.crecs;
+        if (!gmode)
+            for (int64_t q = tid; q < 2 * nslots; q += kThreads)
+                lg[q] = 0.0;
+        // pair weights: W = (G_ij + G_ji) * chain for i != j, G_ii on the
+        // diagonal; stored in the partial-sum slots (unused here)
+        if (tid < npairs) {
+            const int r = tid / C, c = tid - (tid / C) * C;
+            const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
+            double W = 0.0;
+            if (sh.pw[tid + 1] > sh.pw[tid]) {
+                W = args.grad_out[i * args.ldg + j];
+                if (i != j)
+                    W += args.grad_out[j * args.ldg + i];
+                if (args.chain) {
+                    const double F = args.fwd_out[i * args.ldf + j];
+                    W = F > 0.0 ? W * (1.0 / p) * pow(F, 1.0 - p) : 0.0;
+                }
+            }
+            sh.part[tid] = W;
+        }
+        __syncthreads();
+
+        const int64_t per = steps_per_virtual_lane(total);
+        for (int q = 0; q < 2; ++q) {
+            int64_t s = (int64_t)(2 * tid + q) * per;
+            const int64_t e = (s + per < total) ? s + per : total;
+            if (s >= e)
+                continue;
+            int32_t k = pair_of_step(sh, s);
+            int64_t d = s - sh.pw[k];
+            while (s < e) {
+                const int r = k / C, c = k - (k / C) * C;
+                const int64_t len = sh.pw[k + 1] - sh.pw[k];
+                const int64_t m = (len - d < e - s) ? len - d : e - s;
+                const int32_t A = sh.rb[r], B = sh.cb[c];
+                GradSink sa, sb;
+                sa.last = A + sh.rn[r] - 1;
+                sb.last = B + sh.cn[c] - 1;
+                if (gmode) {
+                    // global record index -> CSR row: row = record - i * kPad
+                    const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
+                    sa.gt = args.grad_t - i * kPad;
+                    sa.gv = args.grad_v - i * kPad;
+                    sb.gt = args.grad_t - j * kPad;
+                    sb.gv = args.grad_v - j * kPad;
+                    adjoint_pair<HK>(grec, A, sh.rn[r], B, sh.cn[c], d, m,
+                                     sh.part[k], p, sa, sb);
+                } else {
+                    sa.gt = lg;
+                    sa.gv = lg + nslots;
+                    sb.gt = lg;
+                    sb.gv = lg + nslots;
+                    adjoint_pair<HK>(lrec, A, sh.rn[r], B, sh.cn[c], d, m,
+                                     sh.part[k], p, sa, sb);
+                }
+                s += m;
+                d = 0;
+                ++k;
+                while (k < npairs && sh.pw[k + 1] == sh.pw[k])
+                    ++k;
+            }
+        }
+        __syncthreads();
+
+        // add the tile's accumulators to the outputs; slot 0 of a PCF's
+        // time gradient (t_0) and the last value stay untouched (fixed)
+        if (!gmode) {
+            for (int64_t q = tid; q < nslots; q += kThreads) {
+                const bool in_rows = q < sh.rrecs;
+                const int64_t base = in_rows ? sh.rrec0 : sh.crec0;
+                const int64_t lq = in_rows ? q : q - sh.rrecs;
+                const int64_t rec = base + lq;           // global record index
+                // PCF of this record: the block's PCF whose record range
+                // holds it (blocks are short: linear scan over <= 32)
+                const int32_t nb = in_rows ? R : C;
+                const int32_t *bs = in_rows ? sh.rb : sh.cb;
+                const int32_t *ns = in_rows ? sh.rn : sh.cn;
+                const int64_t pcf0 = in_rows ? sh.r_lo : sh.c_lo;
+                int32_t which = 0;
+                for (int32_t u = 1; u < nb; ++u)
+                    if (bs[u] <= q)
+                        which = u;
+                const int64_t kk = q - bs[which];  // record within the PCF
+                if (kk >= ns[which])
+                    continue;                      // padding
+                const int64_t row = rec - (pcf0 + which) * kPad;
+                const double gtv = lg[q], gvv = lg[nslots + q];
+                if (kk >= 1 && gtv != 0.0)
+                    atomicAdd(&args.grad_t[row], gtv);
+                if (kk + 1 < ns[which] && gvv != 0.0)
+                    atomicAdd(&args.grad_v[row], gvv);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Zero a double array (a kernel, so that captured graphs replay it).
+__global__ void zero_doubles(double *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(zero_doubles, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <int HK>
+static hipError_t launch_bwd_t(const BwdArgs &a, int grid, hipStream_t s)
+{
+    const size_t shm = tile_shared_bytes(16, true);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&pairwise_adjoint_tiles<HK>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((pairwise_adjoint_tiles<HK>), dim3(grid), dim3(kThreads),
+                       shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(int hk, const BwdArgs &a, int grid, hipStream_t s)
+{
+    switch (hk) {
+    case kAbs: return launch_bwd_t<kAbs>(a, grid, s);
+    case kSqr: return launch_bwd_t<kSqr>(a, grid, s);
+    case kProd: return launch_bwd_t<kProd>(a, grid, s);
+    default: return launch_bwd_t<kPow>(a, grid, s);
+    }
+}
+
+}  // namespace pcf

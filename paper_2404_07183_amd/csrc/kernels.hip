@@ -33,56 +33,9 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "tile.hpp"
 
 namespace pcf {
-
-template <typename T>
-struct alignas(2 * sizeof(T)) Rec {
-    T t;  // end time of the piece (sentinel for the last piece)
-    T v;  // value on the piece
-};
-
-template <typename T> __device__ __forceinline__ T sentinel();
-template <> __device__ __forceinline__ float sentinel<float>() { return FLT_MAX; }
-template <> __device__ __forceinline__ double sentinel<double>() { return DBL_MAX; }
-
-template <typename T, int HK>
-__device__ __forceinline__ T hval(T a, T b, T p)
-{
-    if constexpr (HK == kAbs) {
-        return fabs(a - b);
-    } else if constexpr (HK == kSqr) {
-        T d = a - b;
-        return d * d;
-    } else if constexpr (HK == kProd) {
-        return a * b;
-    } else {
-        return pow(fabs(a - b), p);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Workspace access
-
-__device__ __forceinline__ const WsHeader &hdr_of(const unsigned char *ws)
-{
-    return *reinterpret_cast<const WsHeader *>(ws);
-}
-
-// Largest i in [0, n) with offsets[i] <= k.
-__device__ __forceinline__ int64_t pcf_of_row(const int64_t *__restrict__ offsets,
-                                              int64_t n, int64_t k)
-{
-    int64_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (offsets[mid] <= k)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
 
 // ---------------------------------------------------------------------------
 // Reset the tile counters (a kernel, not a memset, so that a captured
@@ -155,117 +108,6 @@ __global__ void validate_rows(const int64_t *__restrict__ offsets, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernel
-
-struct TileShared {
-    int64_t pw[kMaxPairs + 1];  // exclusive prefix of padded pair steps
-    // partial sums: lane l's share of pair k lands in slot k + l (distinct
-    // for all (k, l) because both the pairs and the lanes' step ranges are
-    // ordered); each pair then adds its slots in lane order, so the result
-    // does not depend on timing
-    double part[kMaxPairs + kThreads];
-    double acc[kMaxPairs];      // finished results
-    int32_t rn[kMaxBlock], rb[kMaxBlock];  // row PCF rows / record base
-    int32_t cn[kMaxBlock], cb[kMaxBlock];  // column PCF rows / record base
-    int64_t wsum[kThreads / 64];
-    int64_t tile;
-    int64_t r_lo, c_lo, rrec0, crec0;
-    int64_t obase, ldo, row0, col0;
-    int32_t R, C, diag, mirror, global_mode, npairs;
-};
-
-constexpr int kSharedHead = (int)((sizeof(TileShared) + 255) / 256 * 256);
-
-// Exclusive block-wide scan of one int64 per thread; returns the exclusive
-// prefix and writes the total to *total (all threads).
-__device__ __forceinline__ int64_t block_scan(int64_t x, int64_t *wsum,
-                                              int64_t *total)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t inc = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int64_t y = __shfl_up(inc, o, 64);
-        if (lane >= o)
-            inc += y;
-    }
-    if (lane == 63)
-        wsum[wave] = inc;
-    __syncthreads();
-    if (wave == 0) {
-        int64_t s = (lane < kThreads / 64) ? wsum[lane] : 0;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int64_t y = __shfl_up(s, o, 64);
-            if (lane >= o)
-                s += y;
-        }
-        if (lane < kThreads / 64)
-            wsum[lane] = s;  // inclusive over waves
-    }
-    __syncthreads();
-    const int64_t before = (wave > 0 ? wsum[wave - 1] : 0);
-    *total = wsum[kThreads / 64 - 1];
-    return before + inc - x;
-}
-
-// Decode a tile index into (segment, I, J); thread 0 only.
-__device__ __forceinline__ void locate_tile(const WsHeader &h,
-                                            const unsigned char *ws,
-                                            int64_t tile, const Segment *&seg,
-                                            int32_t &I, int32_t &J)
-{
-    const Segment *segs = reinterpret_cast<const Segment *>(ws + h.off_segs);
-    int64_t lo = 0, hi = h.nseg - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (segs[mid].tile_begin <= tile)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    seg = &segs[lo];
-    const int64_t t = tile - seg->tile_begin;
-    if (seg->type == kSegTriangle) {
-        // t = Jl (Jl + 1) / 2 + Il with 0 <= Il <= Jl
-        int64_t Jl = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while (Jl * (Jl + 1) / 2 > t)
-            --Jl;
-        while ((Jl + 1) * (Jl + 2) / 2 <= t)
-            ++Jl;
-        const int64_t Il = t - Jl * (Jl + 1) / 2;
-        I = seg->b0 + (int32_t)Il;
-        J = seg->b0 + (int32_t)Jl;
-    } else {
-        const int64_t nJ = seg->c1 - seg->c0;
-        I = seg->b0 + (int32_t)(t / nJ);
-        J = seg->c0 + (int32_t)(t % nJ);
-    }
-}
-
-// Merge-path split: number of row-side breakpoints among the first d steps
-// of the pair's merge (row side first on equal times). A and B are record
-// indices of the two PCFs' first records in `src`; na, nb their row counts.
-template <typename T, typename Src>
-__device__ __forceinline__ int32_t merge_path(Src src, int32_t A, int32_t na,
-                                              int32_t B, int32_t nb, int64_t d)
-{
-    int64_t lo = d - (nb - 1);
-    lo = lo < 0 ? 0 : lo;
-    int64_t hi = d < (na - 1) ? d : (na - 1);
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        const T ta = src[A + mid].t;          // breakpoint mid+1 of the row PCF
-        const T tb = src[B + (d - 1 - mid)].t;  // breakpoint d-mid of the column
-        if (ta <= tb)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return (int32_t)lo;
-}
-
-// ---------------------------------------------------------------------------
 // The merge step in CDNA assembly (LDS records, h in {|a-b|, (a-b)^2, ab}).
 //
 // One step: y = min(next_f, next_g); acc += h(a, b) * (y - x); then, with
@@ -292,13 +134,27 @@ template <> struct RecVec<float> { typedef f2v type; };
     "s_andn2_b64 exec, %[sv], vcc\n\t"                              \
     "v_add_u32 %[ib], " STRIDE ", %[ib]\n\t"                        \
     "ds_read_b" PCF_RECBITS_##RD " %[rb], %[ib]\n\t"               \
-    "s_mov_b64 exec, %[sv]\n\t"                                     \
-    "s_waitcnt lgkmcnt(0)"
+    "s_mov_b64 exec, %[sv]"
+
+// Each step first waits until at most two LDS reads are outstanding: the
+// two issued by the other chain's step in between (LDS reads complete in
+// issue order). The caller ends every block with pcf_lds_drain(), so no
+// read is in flight outside a block of steps.
+#define PCF_STEP_HEAD "s_waitcnt lgkmcnt(2)\n\t"
+
+__device__ __forceinline__ void pcf_lds_drain()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
 
 #define PCF_RECBITS_f64 "128"
 #define PCF_RECBITS_f32 "64"
 
 template <typename T, int HK> struct AsmStep;
+
+// Head of a step for a chain that runs alone (no other chain's reads in
+// flight): wait for all outstanding LDS reads.
+#define PCF_STEP_HEAD_SOLO "s_waitcnt lgkmcnt(0)\n\t"
 
 #define PCF_ASM_OPERANDS                                                      \
     : [ra] "+v"(ra), [rb] "+v"(rb), [ia] "+v"(ia), [ib] "+v"(ib),           \
@@ -309,13 +165,22 @@ template <typename T, int HK> struct AsmStep;
     : "vcc", "scc", "memory"
 
 template <> struct AsmStep<double, kAbs> {
+    template <bool SOLO>
     __device__ __forceinline__ static void run(d2v &ra, d2v &rb, uint32_t &ia,
                                                uint32_t &ib, double x, double &y,
                                                double &acc)
     {
         double d, dv;
         uint64_t sv;
-        asm volatile("v_min_f64 %[y], %[nf], %[ng]\n\t"
+        if constexpr (SOLO)
+            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f64 %[y], %[nf], %[ng]\n\t"
+                     "v_add_f64 %[d], %[y], -%[x]\n\t"
+                     "v_add_f64 %[dv], %[a], -%[b]\n\t"
+                     "v_fma_f64 %[acc], |%[dv]|, %[d], %[acc]\n\t"
+                     PCF_STEP_TAIL(f64, "16")
+                     PCF_ASM_OPERANDS);
+        else
+            asm volatile(PCF_STEP_HEAD "v_min_f64 %[y], %[nf], %[ng]\n\t"
                      "v_add_f64 %[d], %[y], -%[x]\n\t"
                      "v_add_f64 %[dv], %[a], -%[b]\n\t"
                      "v_fma_f64 %[acc], |%[dv]|, %[d], %[acc]\n\t"
@@ -324,13 +189,23 @@ template <> struct AsmStep<double, kAbs> {
     }
 };
 template <> struct AsmStep<double, kSqr> {
+    template <bool SOLO>
     __device__ __forceinline__ static void run(d2v &ra, d2v &rb, uint32_t &ia,
                                                uint32_t &ib, double x, double &y,
                                                double &acc)
     {
         double d, dv;
         uint64_t sv;
-        asm volatile("v_min_f64 %[y], %[nf], %[ng]\n\t"
+        if constexpr (SOLO)
+            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f64 %[y], %[nf], %[ng]\n\t"
+                     "v_add_f64 %[d], %[y], -%[x]\n\t"
+                     "v_add_f64 %[dv], %[a], -%[b]\n\t"
+                     "v_mul_f64 %[d], %[dv], %[d]\n\t"
+                     "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
+                     PCF_STEP_TAIL(f64, "16")
+                     PCF_ASM_OPERANDS);
+        else
+            asm volatile(PCF_STEP_HEAD "v_min_f64 %[y], %[nf], %[ng]\n\t"
                      "v_add_f64 %[d], %[y], -%[x]\n\t"
                      "v_add_f64 %[dv], %[a], -%[b]\n\t"
                      "v_mul_f64 %[d], %[dv], %[d]\n\t"
@@ -340,13 +215,22 @@ template <> struct AsmStep<double, kSqr> {
     }
 };
 template <> struct AsmStep<double, kProd> {
+    template <bool SOLO>
     __device__ __forceinline__ static void run(d2v &ra, d2v &rb, uint32_t &ia,
                                                uint32_t &ib, double x, double &y,
                                                double &acc)
     {
         double d, dv;
         uint64_t sv;
-        asm volatile("v_min_f64 %[y], %[nf], %[ng]\n\t"
+        if constexpr (SOLO)
+            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f64 %[y], %[nf], %[ng]\n\t"
+                     "v_add_f64 %[d], %[y], -%[x]\n\t"
+                     "v_mul_f64 %[dv], %[a], %[b]\n\t"
+                     "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
+                     PCF_STEP_TAIL(f64, "16")
+                     PCF_ASM_OPERANDS);
+        else
+            asm volatile(PCF_STEP_HEAD "v_min_f64 %[y], %[nf], %[ng]\n\t"
                      "v_add_f64 %[d], %[y], -%[x]\n\t"
                      "v_mul_f64 %[dv], %[a], %[b]\n\t"
                      "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
@@ -355,13 +239,22 @@ template <> struct AsmStep<double, kProd> {
     }
 };
 template <> struct AsmStep<float, kAbs> {
+    template <bool SOLO>
     __device__ __forceinline__ static void run(f2v &ra, f2v &rb, uint32_t &ia,
                                                uint32_t &ib, float x, float &y,
                                                float &acc)
     {
         float d, dv;
         uint64_t sv;
-        asm volatile("v_min_f32 %[y], %[nf], %[ng]\n\t"
+        if constexpr (SOLO)
+            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f32 %[y], %[nf], %[ng]\n\t"
+                     "v_sub_f32 %[d], %[y], %[x]\n\t"
+                     "v_sub_f32 %[dv], %[a], %[b]\n\t"
+                     "v_fma_f32 %[acc], |%[dv]|, %[d], %[acc]\n\t"
+                     PCF_STEP_TAIL(f32, "8")
+                     PCF_ASM_OPERANDS);
+        else
+            asm volatile(PCF_STEP_HEAD "v_min_f32 %[y], %[nf], %[ng]\n\t"
                      "v_sub_f32 %[d], %[y], %[x]\n\t"
                      "v_sub_f32 %[dv], %[a], %[b]\n\t"
                      "v_fma_f32 %[acc], |%[dv]|, %[d], %[acc]\n\t"
@@ -370,13 +263,23 @@ template <> struct AsmStep<float, kAbs> {
     }
 };
 template <> struct AsmStep<float, kSqr> {
+    template <bool SOLO>
     __device__ __forceinline__ static void run(f2v &ra, f2v &rb, uint32_t &ia,
                                                uint32_t &ib, float x, float &y,
                                                float &acc)
     {
         float d, dv;
         uint64_t sv;
-        asm volatile("v_min_f32 %[y], %[nf], %[ng]\n\t"
+        if constexpr (SOLO)
+            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f32 %[y], %[nf], %[ng]\n\t"
+                     "v_sub_f32 %[d], %[y], %[x]\n\t"
+                     "v_sub_f32 %[dv], %[a], %[b]\n\t"
+                     "v_mul_f32 %[d], %[dv], %[d]\n\t"
+                     "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
+                     PCF_STEP_TAIL(f32, "8")
+                     PCF_ASM_OPERANDS);
+        else
+            asm volatile(PCF_STEP_HEAD "v_min_f32 %[y], %[nf], %[ng]\n\t"
                      "v_sub_f32 %[d], %[y], %[x]\n\t"
                      "v_sub_f32 %[dv], %[a], %[b]\n\t"
                      "v_mul_f32 %[d], %[dv], %[d]\n\t"
@@ -386,13 +289,22 @@ template <> struct AsmStep<float, kSqr> {
     }
 };
 template <> struct AsmStep<float, kProd> {
+    template <bool SOLO>
     __device__ __forceinline__ static void run(f2v &ra, f2v &rb, uint32_t &ia,
                                                uint32_t &ib, float x, float &y,
                                                float &acc)
     {
         float d, dv;
         uint64_t sv;
-        asm volatile("v_min_f32 %[y], %[nf], %[ng]\n\t"
+        if constexpr (SOLO)
+            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f32 %[y], %[nf], %[ng]\n\t"
+                     "v_sub_f32 %[d], %[y], %[x]\n\t"
+                     "v_mul_f32 %[dv], %[a], %[b]\n\t"
+                     "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
+                     PCF_STEP_TAIL(f32, "8")
+                     PCF_ASM_OPERANDS);
+        else
+            asm volatile(PCF_STEP_HEAD "v_min_f32 %[y], %[nf], %[ng]\n\t"
                      "v_sub_f32 %[d], %[y], %[x]\n\t"
                      "v_mul_f32 %[dv], %[a], %[b]\n\t"
                      "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
@@ -401,87 +313,180 @@ template <> struct AsmStep<float, kProd> {
     }
 };
 
-typedef __attribute__((address_space(3))) unsigned char lds_byte;
+// One merge chain: a contiguous run of the tile's steps, possibly over
+// several pairs. Its partial sum of pair k goes to sh.part[k + vl].
+template <typename T>
+struct Chain {
+    typename RecVec<T>::type ra, rb;  // current (end time, value) records
+    uint32_t ia, ib;                  // their LDS byte addresses
+    T x0, x1;                         // start of the current cell (alternating)
+    double acc;
+    int64_t left;                     // steps left in pair k
+    int32_t k, vl;
+};
 
-__device__ __forceinline__ uint32_t lds_address(const void *p)
+template <typename T, typename Shared>
+__device__ __forceinline__ void chain_begin(Chain<T> &ch, Shared &sh,
+                                            const Rec<T> *lrec, int64_t s,
+                                            int32_t vl, int32_t C)
 {
-    return (uint32_t)(uintptr_t)(const lds_byte *)p;
-}
-
-// Starting state of steps [d, ...) of pair (A, B): record indices and x.
-template <typename T, typename Src>
-__device__ __forceinline__ void pair_start(Src src, int32_t A, int32_t na,
-                                           int32_t B, int32_t nb, int64_t d,
-                                           int32_t &ia, int32_t &ib, T &x)
-{
-    ia = A;
-    ib = B;
-    x = T(0);
-    if (d > 0) {
-        const int32_t i = merge_path<T>(src, A, na, B, nb, d);
-        const int32_t j = (int32_t)(d - i);
-        const T xa = (i > 0) ? src[A + i - 1].t : T(0);
-        const T xb = (j > 0) ? src[B + j - 1].t : T(0);
-        x = xa > xb ? xa : xb;
-        ia = A + i;
-        ib = B + j;
-    }
-}
-
-// Steps [d, d + m) of pair (A, B) with records in LDS; m is a multiple of
-// kStepBlock. Returns the partial sum of h * width.
-template <typename T, int HK>
-__device__ __forceinline__ double run_pair_lds(const Rec<T> *lrec, int32_t A,
-                                               int32_t na, int32_t B,
-                                               int32_t nb, int64_t d,
-                                               int64_t m, T p)
-{
+    typedef typename RecVec<T>::type V;
+    const V *lv = reinterpret_cast<const V *>(lrec);
+    const int32_t k = pair_of_step(sh, s);
+    const int64_t d = s - sh.pw[k];
+    const int r = k / C, c = k - (k / C) * C;
     int32_t i0, j0;
     T x;
-    pair_start<T>(lrec, A, na, B, nb, d, i0, j0, x);
-    double acc = 0.0;
-    if constexpr (HK == kPow) {
-        int32_t ia = i0, ib = j0;
-        Rec<T> ra = lrec[ia], rb = lrec[ib];
-        T nf = ra.t, a = ra.v, ng = rb.t, b = rb.v;
-        for (int64_t blk = 0; blk < m; blk += kStepBlock) {
-            T part = T(0);
+    pair_start<T>(lrec, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, i0, j0, x);
+    ch.ra = lv[i0];
+    ch.rb = lv[j0];
+    ch.ia = lds_address(&lrec[i0]);
+    ch.ib = lds_address(&lrec[j0]);
+    ch.x0 = x;
+    ch.acc = 0.0;
+    ch.left = sh.pw[k + 1] - sh.pw[k] - d;
+    ch.k = k;
+    ch.vl = vl;
+}
+
+// Between blocks: a chain that finished its pair records it and moves to
+// the next pair with steps (a rare, divergent branch).
+template <typename T, typename Shared>
+__device__ __forceinline__ void chain_advance(Chain<T> &ch, Shared &sh,
+                                              const Rec<T> *lrec, int32_t C)
+{
+    if (ch.left != 0)
+        return;
+    typedef typename RecVec<T>::type V;
+    const V *lv = reinterpret_cast<const V *>(lrec);
+    sh.part[ch.k + ch.vl] = ch.acc;
+    ch.acc = 0.0;
+    int32_t k = ch.k + 1;
+    while (k < sh.npairs && sh.pw[k + 1] == sh.pw[k])
+        ++k;
+    ch.k = k;
+    ch.left = sh.pw[k + 1] - sh.pw[k];
+    const int r = k / C, c = k - (k / C) * C;
+    const int32_t A = sh.rb[r], B = sh.cb[c];
+    ch.ra = lv[A];
+    ch.rb = lv[B];
+    ch.ia = lds_address(&lrec[A]);
+    ch.ib = lds_address(&lrec[B]);
+    ch.x0 = T(0);
+}
+
+// Two chains of one lane, steps interleaved so that each chain's record
+// reads are in flight while the other chain computes.
+template <typename T, int HK>
+__device__ __forceinline__ void block_pair(Chain<T> &c0, Chain<T> &c1)
+{
+    T p0 = T(0), p1 = T(0);
 #pragma unroll
-            for (int u = 0; u < kStepBlock; ++u) {
-                const T y = nf <= ng ? nf : ng;
-                part = fma(hval<T, HK>(a, b, p), y - x, part);
-                x = y;
-                if (nf <= ng) {
-                    ++ia;
-                    const Rec<T> r = lrec[ia];
-                    nf = r.t;
-                    a = r.v;
-                } else {
-                    ++ib;
-                    const Rec<T> r = lrec[ib];
-                    ng = r.t;
-                    b = r.v;
-                }
-            }
-            acc += (double)part;
-        }
-    } else {
-        typedef typename RecVec<T>::type V;
-        const V *lv = reinterpret_cast<const V *>(lrec);
-        V ra = lv[i0], rb = lv[j0];
-        uint32_t ia = lds_address(&lrec[i0]), ib = lds_address(&lrec[j0]);
-        T x0 = x, x1;
-        for (int64_t blk = 0; blk < m; blk += kStepBlock) {
-            T part = T(0);
-#pragma unroll
-            for (int u = 0; u < kStepBlock; u += 2) {
-                AsmStep<T, HK>::run(ra, rb, ia, ib, x0, x1, part);
-                AsmStep<T, HK>::run(ra, rb, ia, ib, x1, x0, part);
-            }
-            acc += (double)part;
-        }
+    for (int u = 0; u < kStepBlock; u += 2) {
+        AsmStep<T, HK>::template run<false>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x0, c0.x1, p0);
+        AsmStep<T, HK>::template run<false>(c1.ra, c1.rb, c1.ia, c1.ib, c1.x0, c1.x1, p1);
+        AsmStep<T, HK>::template run<false>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x1, c0.x0, p0);
+        AsmStep<T, HK>::template run<false>(c1.ra, c1.rb, c1.ia, c1.ib, c1.x1, c1.x0, p1);
     }
-    return acc;
+    pcf_lds_drain();
+    c0.acc += (double)p0;
+    c1.acc += (double)p1;
+    c0.left -= kStepBlock;
+    c1.left -= kStepBlock;
+}
+
+template <typename T, int HK>
+__device__ __forceinline__ void block_solo(Chain<T> &c0)
+{
+    T p0 = T(0);
+#pragma unroll
+    for (int u = 0; u < kStepBlock; u += 2) {
+        AsmStep<T, HK>::template run<true>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x0, c0.x1, p0);
+        AsmStep<T, HK>::template run<true>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x1, c0.x0, p0);
+    }
+    pcf_lds_drain();
+    c0.acc += (double)p0;
+    c0.left -= kStepBlock;
+}
+
+// This lane's two chains: virtual lanes 2*lane and 2*lane+1 of the tile's
+// even split, steps [s0, e0) and [s1, e1) with e0 == s1 (e1 - s1 <= e0 - s0,
+// only the tile's last lanes are short). Both run in one block loop.
+template <typename T, int HK, typename Shared>
+__device__ __forceinline__ void lane_chains_lds(Shared &sh, const Rec<T> *lrec,
+                                                int64_t s0, int64_t e0,
+                                                int64_t s1, int64_t e1,
+                                                int32_t lane, int32_t C)
+{
+    const int64_t nb0 = (e0 - s0) / kStepBlock;
+    const int64_t nb1 = (e1 > s1) ? (e1 - s1) / kStepBlock : 0;
+    Chain<T> c0, c1;
+    chain_begin(c0, sh, lrec, s0, 2 * lane, C);
+    if (nb1 > 0)
+        chain_begin(c1, sh, lrec, s1, 2 * lane + 1, C);
+    int64_t blk = 0;
+    for (; blk < nb1; ++blk) {
+        chain_advance(c0, sh, lrec, C);
+        chain_advance(c1, sh, lrec, C);
+        block_pair<T, HK>(c0, c1);
+    }
+    for (; blk < nb0; ++blk) {
+        chain_advance(c0, sh, lrec, C);
+        block_solo<T, HK>(c0);
+    }
+    sh.part[c0.k + c0.vl] = c0.acc;
+    if (nb1 > 0)
+        sh.part[c1.k + c1.vl] = c1.acc;
+}
+
+// Single-chain C++ loop (h = |a-b|^p, whose step is not hand-written).
+template <typename T, int HK, typename Shared>
+__device__ __forceinline__ void chain_cpp(Shared &sh, const Rec<T> *lrec,
+                                          int64_t s, int64_t e, int32_t vl,
+                                          int32_t C, T p)
+{
+    int32_t k = pair_of_step(sh, s);
+    int64_t d = s - sh.pw[k];
+    int64_t left = sh.pw[k + 1] - sh.pw[k] - d;
+    int32_t ia, ib;
+    T x;
+    {
+        const int r = k / C, c = k - (k / C) * C;
+        pair_start<T>(lrec, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, ia, ib, x);
+    }
+    Rec<T> ra = lrec[ia], rb = lrec[ib];
+    double acc = 0.0;
+    const int64_t nblk = (e - s) / kStepBlock;
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        if (left == 0) {
+            sh.part[k + vl] = acc;
+            acc = 0.0;
+            ++k;
+            while (k < sh.npairs && sh.pw[k + 1] == sh.pw[k])
+                ++k;
+            left = sh.pw[k + 1] - sh.pw[k];
+            const int r = k / C, c = k - (k / C) * C;
+            ia = sh.rb[r];
+            ib = sh.cb[c];
+            ra = lrec[ia];
+            rb = lrec[ib];
+            x = T(0);
+        }
+        T part = T(0);
+#pragma unroll
+        for (int u = 0; u < kStepBlock; ++u) {
+            const T y = ra.t <= rb.t ? ra.t : rb.t;
+            part = fma(hval<T, HK>(ra.v, rb.v, p), y - x, part);
+            x = y;
+            if (ra.t <= rb.t)
+                ra = lrec[++ia];
+            else
+                rb = lrec[++ib];
+        }
+        acc += (double)part;
+        left -= kStepBlock;
+    }
+    sh.part[k + vl] = acc;
 }
 
 // Same from global memory (tiles too large for LDS): plain loads.
@@ -529,132 +534,52 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     const int tid = threadIdx.x;
     const unsigned char *ws = args.ws;
     const WsHeader &h = hdr_of(ws);
-    const int32_t *blocks = reinterpret_cast<const int32_t *>(ws + h.off_blocks);
     const Rec<T> *grec = reinterpret_cast<const Rec<T> *>(ws + h.off_rec);
     const int64_t *offsets = args.offsets;
     const T p = (T)args.p;
-    uint32_t *counter = reinterpret_cast<WsHeader *>(args.ws)->counter;
 
     for (;;) {
-        if (tid == 0) {
-            const int64_t tile = (int64_t)atomicAdd(&counter[0], 1u);
-            sh.tile = tile;
-            if (tile < h.ntiles) {
-                const Segment *seg;
-                int32_t I, J;
-                locate_tile(h, ws, tile, seg, I, J);
-                const int64_t r_lo = blocks[I], r_hi = blocks[I + 1];
-                const int64_t c_lo = blocks[J], c_hi = blocks[J + 1];
-                sh.r_lo = r_lo;
-                sh.c_lo = c_lo;
-                sh.R = (int32_t)(r_hi - r_lo);
-                sh.C = (int32_t)(c_hi - c_lo);
-                sh.diag = (seg->type == kSegTriangle && I == J) ? 1 : 0;
-                sh.mirror = seg->mirror;
-                sh.obase = seg->obase;
-                sh.ldo = seg->ldo;
-                sh.row0 = seg->row0;
-                sh.col0 = seg->col0;
-                sh.rrec0 = offsets[r_lo] + r_lo * kPad;
-                sh.crec0 = offsets[c_lo] + c_lo * kPad;
-                const int64_t rrecs = offsets[r_hi] + r_hi * kPad - sh.rrec0;
-                const int64_t crecs = offsets[c_hi] + c_hi * kPad - sh.crec0;
-                const int64_t need = sh.diag ? rrecs : rrecs + crecs;
-                sh.global_mode = need > h.lds_records ? 1 : 0;
-                sh.npairs = sh.R * sh.C;
-            }
-        }
-        __syncthreads();
-        if (sh.tile >= h.ntiles)
+        if (!tile_setup<T>(sh, lrec, ws, offsets, args.gram))
             break;
         const int32_t R = sh.R, C = sh.C, npairs = sh.npairs;
         const bool diag = sh.diag != 0, gmode = sh.global_mode != 0;
-        const int64_t rrecs_end =
-            offsets[sh.r_lo + R] + (sh.r_lo + R) * kPad - sh.rrec0;
+        const int64_t total = sh.pw[npairs];
 
-        // block metadata: rows of each PCF and base of its records (LDS
-        // index, or global index in global mode)
-        if (tid < R) {
-            const int64_t i = sh.r_lo + tid;
-            const int64_t roff = offsets[i] + i * kPad;
-            sh.rn[tid] = (int32_t)(offsets[i + 1] - offsets[i]);
-            sh.rb[tid] = (int32_t)(gmode ? roff : roff - sh.rrec0);
-        } else if (tid >= 64 && tid < 64 + C) {
-            const int c = tid - 64;
-            const int64_t j = sh.c_lo + c;
-            const int64_t roff = offsets[j] + j * kPad;
-            sh.cn[c] = (int32_t)(offsets[j + 1] - offsets[j]);
-            sh.cb[c] = (int32_t)(gmode ? roff
-                                       : (diag ? roff - sh.rrec0
-                                               : rrecs_end + (roff - sh.crec0)));
-        }
-        // stage both blocks' records into LDS
-        if (!gmode) {
-            for (int64_t q = tid; q < rrecs_end; q += kThreads)
-                lrec[q] = grec[sh.rrec0 + q];
-            if (!diag) {
-                const int64_t crecs_end =
-                    offsets[sh.c_lo + C] + (sh.c_lo + C) * kPad - sh.crec0;
-                for (int64_t q = tid; q < crecs_end; q += kThreads)
-                    lrec[rrecs_end + q] = grec[sh.crec0 + q];
-            }
-        }
-        __syncthreads();
-
-        // padded step count of every pair, prefix-summed
-        int64_t wp = 0;
-        if (tid < npairs) {
-            const int r = tid / C, c = tid - (tid / C) * C;
-            bool live = true;
-            if (diag)
-                live = args.gram ? (r <= c) : (r < c);
-            if (live) {
-                const int64_t w = (int64_t)sh.rn[r] + sh.cn[c] - 2;
-                wp = (w + kStepBlock - 1) / kStepBlock * kStepBlock;
-            }
-        }
-        int64_t total;
-        const int64_t excl = block_scan(wp, sh.wsum, &total);
-        if (tid < npairs)
-            sh.pw[tid] = excl;
-        if (tid == 0)
-            sh.pw[npairs] = total;
-        __syncthreads();
-
-        // this lane's share of the tile's steps
-        const int64_t per = ((total + kThreads - 1) / kThreads + kStepBlock - 1) /
-                            kStepBlock * kStepBlock;
-        int64_t s = (int64_t)tid * per;
-        const int64_t e = (s + per < total) ? s + per : total;
-        if (s < e) {
-            // pair containing step s: largest k with pw[k] <= s
-            int32_t lo = 0, hi = npairs - 1;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (sh.pw[mid] <= s)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            int32_t k = lo;
-            int64_t d = s - sh.pw[k];
-            while (s < e) {
-                const int r = k / C, c = k - (k / C) * C;
-                const int64_t len = sh.pw[k + 1] - sh.pw[k];
-                const int64_t m = (len - d < e - s) ? len - d : e - s;
-                double part;
-                if (gmode)
-                    part = run_pair_global<T, HK>(grec, sh.rb[r], sh.rn[r],
-                                                  sh.cb[c], sh.cn[c], d, m, p);
-                else
-                    part = run_pair_lds<T, HK>(lrec, sh.rb[r], sh.rn[r],
-                                               sh.cb[c], sh.cn[c], d, m, p);
-                sh.part[k + tid] = part;
-                s += m;
-                d = 0;
-                ++k;
-                while (k < npairs && sh.pw[k + 1] == sh.pw[k])
-                    ++k;
+        // the tile's steps split evenly over 2 * kThreads virtual lanes, two
+        // per lane (see lane_chains_lds)
+        const int64_t per = steps_per_virtual_lane(total);
+        const int64_t s0 = (int64_t)(2 * tid) * per;
+        const int64_t e0 = (s0 + per < total) ? s0 + per : total;
+        const int64_t s1 = e0;
+        const int64_t e1 = (s1 + per < total) ? s1 + per : total;
+        if (s0 < e0) {
+            if (gmode) {
+                for (int q = 0; q < 2; ++q) {
+                    int64_t s = q ? s1 : s0;
+                    const int64_t e = q ? e1 : e0;
+                    if (s >= e)
+                        continue;
+                    int32_t k = pair_of_step(sh, s);
+                    int64_t d = s - sh.pw[k];
+                    while (s < e) {
+                        const int r = k / C, c = k - (k / C) * C;
+                        const int64_t len = sh.pw[k + 1] - sh.pw[k];
+                        const int64_t m = (len - d < e - s) ? len - d : e - s;
+                        sh.part[k + 2 * tid + q] = run_pair_global<T, HK>(
+                            grec, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, m, p);
+                        s += m;
+                        d = 0;
+                        ++k;
+                        while (k < npairs && sh.pw[k + 1] == sh.pw[k])
+                            ++k;
+                    }
+                }
+            } else if constexpr (HK == kPow) {
+                chain_cpp<T, HK>(sh, lrec, s0, e0, 2 * tid, C, p);
+                if (s1 < e1)
+                    chain_cpp<T, HK>(sh, lrec, s1, e1, 2 * tid + 1, C, p);
+            } else {
+                lane_chains_lds<T, HK>(sh, lrec, s0, e0, s1, e1, tid, C);
             }
         }
         __syncthreads();
@@ -681,7 +606,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
                 val = sqrt(val);
             else if (args.root == kRootPow)
                 val = pow(val, args.inv_p);
-            sh.acc[k] = val;
+            sh.part[k + b0 / per] = val;
             const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
             T *out = reinterpret_cast<T *>(args.out);
             out[sh.obase + (i - sh.row0) * sh.ldo + (j - sh.col0)] = (T)val;
@@ -692,7 +617,8 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
                 const int c = q / R, r = q - (q / R) * R;
                 if (diag && r >= c)
                     continue;
-                const double val = sh.acc[r * C + c];
+                const int kk = r * C + c;
+                const double val = sh.part[kk + sh.pw[kk] / per];
                 const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
                 T *out = reinterpret_cast<T *>(args.out);
                 out[sh.obase + (j - sh.row0) * sh.ldo + (i - sh.col0)] = (T)val;

@@ -35,6 +35,7 @@ struct BwdArgs {
     double *grad_v;          // dL/dv, CSR layout (accumulated)
     double p;
     int chain;               // 1: scale by dF/dI = (1/p) I^(1/p - 1)
+    int gram;                // 1: diagonal pairs carry work (Gram)
 };
 
 template <typename T>

@@ -225,3 +225,19 @@ def test_plain_full_size_sampled():
     Mh = M[torch.as_tensor(I, device=DEV), torch.as_tensor(J, device=DEV)].cpu().numpy()
     ref = oracle.entries(oracle.LP, 1.0, o, t, v, I, J)
     assert np.all(np.abs(Mh - ref) <= 1e-12 * ref)
+
+
+@pytest.mark.parametrize("n", [2, 5, 9, 13, 17, 40])
+def test_tiny_tiles_few_active_lanes(n):
+    # a tile with a handful of steps: most lanes idle, one lane may run both
+    # of its chains with a single active lane in its wave
+    rng = np.random.default_rng(n)
+    for N in (2, 3):
+        counts = np.full(N, n)
+        o = np.concatenate([[0], np.cumsum(counts)])
+        t = np.concatenate([np.concatenate([[0.0], np.cumsum(rng.exponential(1.0, n - 1))])
+                            for _ in range(N)])
+        v = rng.standard_normal(N * n)
+        v[o[1:] - 1] = 0.0
+        for name in ("l1", "l2sq", "gram"):
+            _check_full(name, o, t, v, 1e-12)
