@@ -153,6 +153,110 @@ def run_plain(args):
     return res
 
 
+def _events_ms(fn, steps, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_batched(steps, warmup, plain_steps_per_s=None):
+    """512 independent L2 distance matrices (FP64) in one persistent launch,
+    tile shape picked by the autotuner, replayed as a HIP graph."""
+    import torch
+
+    from paper_2404_07183_amd import api, workloads
+
+    so, o, t, v = workloads.config_batched()
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    sizes = np.diff(so)
+    out = torch.empty(int((sizes ** 2).sum()), dtype=torch.float64, device="cuda:0")
+    ws = api.Workspace(device="cuda:0")
+    stream = torch.cuda.current_stream()
+    shape, times = api.autotune(
+        lambda sh: api.pairwise_batched(so, X, api.PCF_LP, 2.0, out=out, workspace=ws, shape=sh),
+        key=("batched", X.n, int(o[-1])))
+    call = lambda: api.pairwise_batched(so, X, api.PCF_LP, 2.0, out=out, workspace=ws,
+                                        shape=shape)
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    ms_eager = _events_ms(call, steps, stream)
+    # the same call captured once and replayed
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            call()
+    stream.wait_stream(s)
+    torch.cuda.synchronize()
+    ms_graph = _events_ms(g.replay, steps, stream)
+    pairs = float(np.sum(sizes * (sizes - 1) / 2))
+    n = np.diff(o).astype(np.float64)
+    msteps = 0.0
+    for b in range(len(sizes)):
+        nb = n[so[b]:so[b + 1]]
+        msteps += (len(nb) - 1) * np.sum(nb - 1)
+    ms = min(ms_eager, ms_graph)
+    res = {"workload": "512 independent L2 distance matrices, sizes round(exp(U(ln16,ln2048))), "
+                       "counts Geometric(1/200) capped 5000, FP64",
+           "problems": int(len(sizes)), "pcfs": int(X.n), "pairs": pairs, "merge_steps": msteps,
+           "ms_per_step_eager": ms_eager, "ms_per_step_graph": ms_graph,
+           "pairs_per_s": pairs / (ms * 1e-3), "merge_steps_per_s": msteps / (ms * 1e-3),
+           "tile_shape": list(shape) if shape else None,
+           "autotune_ms": {str(k): v for k, v in times.items()}}
+    if plain_steps_per_s:
+        res["vs_plain_merge_steps_per_s"] = res["merge_steps_per_s"] / plain_steps_per_s
+    return res
+
+
+def run_grad(steps, warmup, plain_steps_per_s=None):
+    """Forward + adjoint of L = sum W_ij d_2(f_i,f_j)^2 + sum U_ij <f_i,f_j>,
+    N = 4,096 PCFs, FP64 (two forward matrices, two adjoint passes)."""
+    import torch
+
+    from paper_2404_07183_amd import api, workloads
+
+    o, t, v, W, U = workloads.config_grad()
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    Wt = torch.as_tensor(W, device="cuda:0")
+    Ut = torch.as_tensor(U, device="cuda:0")
+    tt = X.t.clone().requires_grad_(True)
+    vv = X.v.clone().requires_grad_(True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tt.grad = None
+        vv.grad = None
+        M1 = api.pairwise_matrix(X, tt, vv, api.PCF_LP_POW, 2.0)
+        M2 = api.pairwise_matrix(X, tt, vv, api.PCF_GRAM)
+        L = (Wt * M1).sum() + (Ut * M2).sum()
+        L.backward()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = _events_ms(step, steps, stream)
+    N = X.n
+    n = np.diff(o).astype(np.float64)
+    fwd_steps = 2 * (N - 1) * np.sum(n - 1) + 2 * np.sum(n - 1)  # two matrices (+Gram diagonal)
+    pairs = N * (N + 1) / 2
+    res = {"workload": "loss sum W d_2^2 + sum U <,>, N=4096, counts U{20..300}, FP64; forward "
+                       "of both matrices and their adjoints (dL/dt, dL/dv)",
+           "pcfs": N, "pairs": pairs, "ms_per_step": ms,
+           "fwd_bwd_pairs_per_s": pairs / (ms * 1e-3),
+           "merge_steps_per_s_fwd_plus_bwd": 2 * fwd_steps / (ms * 1e-3)}
+    if plain_steps_per_s:
+        res["vs_plain_merge_steps_per_s"] = res["merge_steps_per_s_fwd_plus_bwd"] / plain_steps_per_s
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,12 +267,18 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and forward+adjoint measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     res = run_plain(args)
+    if not args.no_extras:
+        plain = res["merge_steps_per_s"]
+        res["batched"] = run_batched(max(2, args.steps // 2), 1, plain)
+        res["fwd_bwd"] = run_grad(max(2, args.steps // 2), 1, plain)
     print(json.dumps(res), flush=True)
 
 

@@ -103,8 +103,16 @@ enum {
                                 packing pass                                  */
 };
 
+/* Tile shape (chosen by an autotuner; 0 = default). Bits 8..13 of `flags`:
+ * most PCFs per block (1..32, default 32); bits 16..19: a block holds at most
+ * 1/d of a tile's LDS record capacity (d = 2..8, default 2). Results are the
+ * same for every shape up to rounding order. */
+#define PCF_TILE_SHAPE(max_block, budget_div) \
+    ((((uint32_t)(max_block) & 63u) << 8) | (((uint32_t)(budget_div) & 15u) << 16))
+
 /* Workspace size in bytes for pcf_pairwise_lp / pcf_gram (backward = 0) or
- * pcf_pairwise_backward (backward = 1) on X with window w (NULL = full).
+ * pcf_pairwise_backward (backward = 1) on X with window w (NULL = full),
+ * enough for every tile shape.
  * Reads X->offsets (host copy or a synchronous device-to-host copy).
  * Returns PCF_EINVAL on bad arguments. */
 pcf_status pcf_workspace_bytes(const pcf_set *X, pcf_kind kind,

@@ -19,7 +19,7 @@ from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
 
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
-           "PCF_LP", "PCF_LP_POW", "PCF_GRAM"]
+           "autotune", "TILE_SHAPES", "PCF_LP", "PCF_LP_POW", "PCF_GRAM"]
 
 
 def _stream_handle(stream=None):
@@ -95,30 +95,34 @@ def _window(window):
     return _lib.pcf_window(r0, r1, c0, c1)
 
 
-def _flags(upper_only, validate, reuse):
-    return ((PCF_UPPER_ONLY if upper_only else 0) | (PCF_VALIDATE if validate else 0)
-            | (PCF_REUSE_PLAN if reuse else 0))
+def _flags(upper_only, validate, reuse, shape=None):
+    f = ((PCF_UPPER_ONLY if upper_only else 0) | (PCF_VALIDATE if validate else 0)
+         | (PCF_REUSE_PLAN if reuse else 0))
+    if shape is not None:
+        max_block, budget_div = shape
+        f |= ((int(max_block) & 63) << 8) | ((int(budget_div) & 15) << 16)
+    return f
 
 
 def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
-             packed=False):
+             packed=False, shape=None):
     Xc = X.c_struct()
     win = _window(window)
     if window is None:
-        shape = (X.n, X.n)
+        oshape = (X.n, X.n)
     else:
-        shape = (window[1] - window[0], window[3] - window[2])
+        oshape = (window[1] - window[0], window[3] - window[2])
     if out is None:
-        out = torch.zeros(shape, dtype=X.dtype, device=X.t.device)
+        out = torch.zeros(oshape, dtype=X.dtype, device=X.t.device)
     if out.dtype != X.dtype or out.dim() != 2 or out.stride(1) != 1:
         raise ValueError("out must be a row-major 2-D tensor of the input dtype")
     ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
-    key = ("fwd", kind, X.n, id(X.offsets_host), window, upper_only)
+    key = ("fwd", kind, X.n, id(X.offsets_host), window, upper_only, shape)
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
     reuse = ws.planned == key
     if not reuse:
         ws.ensure(_lib.pcf_workspace_bytes(Xc, kind, win, 0))
-    flags = _flags(upper_only, validate, reuse)
+    flags = _flags(upper_only, validate, reuse, shape)
     if packed:
         if not reuse or ws.packed_data != (X.t.data_ptr(), X.v.data_ptr()):
             raise ValueError("packed=True needs an earlier call on the same set, "
@@ -138,20 +142,20 @@ def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
 
 
 def pdist(X, p=1.0, *, power=False, window=None, out=None, upper_only=False,
-          validate=False, workspace=None, stream=None, packed=False):
+          validate=False, workspace=None, stream=None, packed=False, shape=None):
     """L_p distance matrix (``power=True``: d_p^p) of the PCFs in ``X``.
 
     ``packed=True`` skips re-packing the breakpoint records: only valid when
     ``workspace`` served the previous call on this very set and data."""
     return _forward(X, PCF_LP_POW if power else PCF_LP, p, window, out, upper_only,
-                    validate, workspace, stream, packed)
+                    validate, workspace, stream, packed, shape)
 
 
 def gram(X, *, window=None, out=None, upper_only=False, validate=False,
-         workspace=None, stream=None, packed=False):
+         workspace=None, stream=None, packed=False, shape=None):
     """L2 Gram matrix of the PCFs in ``X``."""
     return _forward(X, PCF_GRAM, 0.0, window, out, upper_only, validate, workspace,
-                    stream, packed)
+                    stream, packed, shape)
 
 
 def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None):
@@ -173,7 +177,7 @@ def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream
 
 
 def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=None,
-                     upper_only=False, validate=False, stream=None):
+                     upper_only=False, validate=False, stream=None, shape=None):
     """Independent full matrices of the problems ``set_offsets`` cuts ``X``
     into, in one launch. Returns ``(out_flat, out_offsets)``: problem b's
     s_b x s_b matrix is ``out_flat[out_offsets[b]:][:s_b*s_b]``."""
@@ -187,19 +191,52 @@ def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=
     if out is None:
         out = torch.zeros(total, dtype=X.dtype, device=X.t.device)
     Xc = X.c_struct()
-    key = ("batched", kind, X.n, id(X.offsets_host), so.tobytes(), upper_only)
+    key = ("batched", kind, X.n, id(X.offsets_host), so.tobytes(), upper_only, shape)
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
     reuse = ws.planned == key
     if not reuse:
         ws.ensure(_lib.pcf_batched_workspace_bytes(B, so.ctypes.data, Xc))
     st = _lib.pcf_pairwise_batched(B, so.ctypes.data, Xc, kind, float(p), out.data_ptr(),
                                    oo.ctypes.data, ws.ptr, ws.nbytes,
-                                   _flags(upper_only, validate, reuse),
+                                   _flags(upper_only, validate, reuse, shape),
                                    _stream_handle(stream))
     check(st)
     ws.planned = key
     ws.planned_ref = X.offsets_host
     return out, oo
+
+
+# Tile shapes the autotuner tries: (most PCFs per block, block budget divisor).
+TILE_SHAPES = [(32, 2), (16, 2), (32, 3), (24, 2), (8, 2), (32, 4)]
+_TUNED = {}
+
+
+def autotune(run, key, shapes=None, reps=3):
+    """Pick the fastest tile shape for a workload.
+
+    ``run(shape)`` must launch one call with that shape (``None`` = default)
+    on the current stream. Every candidate runs once untimed (which also
+    builds its plan) and ``reps`` times between HIP events; the shape with the
+    smallest mean time wins and is remembered under ``key`` for the process.
+    Returns ``(shape, {shape: ms})``."""
+    if key in _TUNED:
+        return _TUNED[key]
+    shapes = shapes or TILE_SHAPES
+    stream = torch.cuda.current_stream()
+    times = {}
+    for shape in shapes:
+        run(shape)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run(shape)
+        e1.record(stream)
+        e1.synchronize()
+        times[shape] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    _TUNED[key] = (best, times)
+    return _TUNED[key]
 
 
 def validate(X, stream=None):

@@ -35,6 +35,18 @@ pcf_status hip_fail(hipError_t e, const char *what)
 
 int rec_bytes_of(pcf_dtype d) { return d == PCF_F64 ? 16 : 8; }
 
+TileShape shape_of(uint32_t flags)
+{
+    TileShape s;
+    const int32_t mb = (int32_t)((flags >> 8) & 63u);
+    const int32_t bd = (int32_t)((flags >> 16) & 15u);
+    if (mb >= 1 && mb <= kMaxBlock)
+        s.max_block = mb;
+    if (bd >= 2 && bd <= 8)
+        s.budget_div = bd;
+    return s;
+}
+
 constexpr int HK_ABS = kAbs, HK_SQR = kSqr, HK_PROD = kProd, HK_POW = kPow;
 
 int device_cus()
@@ -229,7 +241,7 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
         if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), false, w != nullptr,
                          w ? w->row0 : 0, w ? w->row1 : 0, w ? w->col0 : 0,
                          w ? w->col1 : 0, (flags & PCF_UPPER_ONLY) != 0, ldo,
-                         plan, err))
+                         shape_of(flags), plan, err))
             return fail(PCF_EINVAL, err);
     }
     Call c;
@@ -292,9 +304,9 @@ pcf_status pcf_workspace_bytes(const pcf_set *X, pcf_kind kind,
     if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), backward != 0,
                      w != nullptr, w ? w->row0 : 0, w ? w->row1 : 0,
                      w ? w->col0 : 0, w ? w->col1 : 0, false,
-                     ldo > 0 ? ldo : 1, plan, err))
+                     ldo > 0 ? ldo : 1, TileShape(), plan, err))
         return fail(PCF_EINVAL, err);
-    *bytes = (size_t)plan_workspace_bytes(plan, rec_bytes_of(X->dtype));
+    *bytes = (size_t)plan_workspace_bound(plan, rec_bytes_of(X->dtype));
     return PCF_OK;
 }
 
@@ -337,9 +349,9 @@ pcf_status pcf_batched_workspace_bytes(int32_t B,
     Plan plan;
     std::string err;
     if (!plan_batched(B, set_offsets_host, oo.data(), ho, all->n,
-                      rec_bytes_of(all->dtype), false, plan, err))
+                      rec_bytes_of(all->dtype), false, TileShape(), plan, err))
         return fail(PCF_EINVAL, err);
-    *bytes = (size_t)plan_workspace_bytes(plan, rec_bytes_of(all->dtype));
+    *bytes = (size_t)plan_workspace_bound(plan, rec_bytes_of(all->dtype));
     return PCF_OK;
 }
 
@@ -376,7 +388,8 @@ pcf_status pcf_pairwise_batched(int32_t B, const int64_t *set_offsets_host,
         std::string err;
         if (!plan_batched(B, set_offsets_host, out_offsets_host, ho, all->n,
                           rec_bytes_of(all->dtype),
-                          (flags & PCF_UPPER_ONLY) != 0, plan, err))
+                          (flags & PCF_UPPER_ONLY) != 0, shape_of(flags), plan,
+                          err))
             return fail(PCF_EINVAL, err);
     }
     Call c;
@@ -447,7 +460,7 @@ pcf_status pcf_plan_inspect(int64_t n, const int64_t *offsets_host,
     if (!plan_matrix(n, offsets_host, rec_bytes_of(dtype), backward != 0,
                      w != nullptr, w ? w->row0 : 0, w ? w->row1 : 0,
                      w ? w->col0 : 0, w ? w->col1 : 0, false,
-                     ldo > 0 ? ldo : 1, plan, err))
+                     ldo > 0 ? ldo : 1, TileShape(), plan, err))
         return fail(PCF_EINVAL, err);
     const int64_t nb = plan.blocks.empty() ? 0 : (int64_t)plan.blocks.size() - 1;
     if (nblocks)
@@ -498,7 +511,7 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
             return st;
         std::string err;
         if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), true, false, 0, 0,
-                         0, 0, false, X->n, plan, err))
+                         0, 0, false, X->n, shape_of(flags), plan, err))
             return fail(PCF_EINVAL, err);
     }
     Call c;

@@ -13,13 +13,14 @@ int64_t lds_record_capacity(int rec_bytes, bool backward)
     return kLdsRecordBytes / per;
 }
 
-int64_t block_budget(int rec_bytes, bool backward)
+int64_t block_budget(int rec_bytes, bool backward, const TileShape &shape)
 {
-    return lds_record_capacity(rec_bytes, backward) / 2;
+    const int32_t d = shape.budget_div >= 2 ? shape.budget_div : 2;
+    return lds_record_capacity(rec_bytes, backward) / d;
 }
 
 void build_blocks(const int64_t *offsets, int64_t lo, int64_t hi,
-                  std::vector<int64_t> cuts, int64_t budget,
+                  std::vector<int64_t> cuts, int64_t budget, int32_t max_block,
                   std::vector<int32_t> &blocks)
 {
     std::sort(cuts.begin(), cuts.end());
@@ -33,7 +34,7 @@ void build_blocks(const int64_t *offsets, int64_t lo, int64_t hi,
                 is_cut = true;
             ++ci;
         }
-        if (count == 0 || is_cut || count == kMaxBlock || recs + r > budget) {
+        if (count == 0 || is_cut || count == max_block || recs + r > budget) {
             blocks.push_back((int32_t)i);
             count = 0;
             recs = 0;
@@ -94,7 +95,7 @@ void add_segment(Plan &plan, Segment s, int64_t tiles)
 bool plan_matrix(int64_t n, const int64_t *offsets, int rec_bytes,
                  bool backward, bool windowed, int64_t r0, int64_t r1,
                  int64_t c0, int64_t c1, bool upper_only, int64_t ldo,
-                 Plan &plan, std::string &err)
+                 const TileShape &shape, Plan &plan, std::string &err)
 {
     plan = Plan();
     if (!check_offsets(n, offsets, err))
@@ -127,8 +128,8 @@ bool plan_matrix(int64_t n, const int64_t *offsets, int rec_bytes,
         cuts.push_back(d0);
         cuts.push_back(d1);
     }
-    build_blocks(offsets, lo, hi, cuts, block_budget(rec_bytes, backward),
-                 plan.blocks);
+    build_blocks(offsets, lo, hi, cuts, block_budget(rec_bytes, backward, shape),
+                 shape.max_block, plan.blocks);
     plan.blocks.push_back((int32_t)hi);
 
     Segment base{};
@@ -175,8 +176,8 @@ bool plan_matrix(int64_t n, const int64_t *offsets, int rec_bytes,
 
 bool plan_batched(int32_t B, const int64_t *set_offsets,
                   const int64_t *out_offsets, const int64_t *offsets,
-                  int64_t n, int rec_bytes, bool upper_only, Plan &plan,
-                  std::string &err)
+                  int64_t n, int rec_bytes, bool upper_only,
+                  const TileShape &shape, Plan &plan, std::string &err)
 {
     plan = Plan();
     if (B < 0 || (B > 0 && (!set_offsets || !out_offsets))) {
@@ -203,8 +204,8 @@ bool plan_batched(int32_t B, const int64_t *set_offsets,
         return true;
     const int64_t lo = set_offsets[0], hi = set_offsets[B];
     std::vector<int64_t> cuts(set_offsets, set_offsets + B + 1);
-    build_blocks(offsets, lo, hi, cuts, block_budget(rec_bytes, false),
-                 plan.blocks);
+    build_blocks(offsets, lo, hi, cuts, block_budget(rec_bytes, false, shape),
+                 shape.max_block, plan.blocks);
     plan.blocks.push_back((int32_t)hi);
 
     struct Item {
@@ -245,6 +246,15 @@ int64_t plan_workspace_bytes(const Plan &plan, int rec_bytes)
 {
     int64_t off = kHeaderBytes;
     off += align_up((int64_t)plan.blocks.size() * 4, 256);
+    off += align_up((int64_t)plan.segs.size() * (int64_t)sizeof(Segment), 256);
+    off += align_up(plan.rec_count * rec_bytes, 256);
+    return off;
+}
+
+int64_t plan_workspace_bound(const Plan &plan, int rec_bytes)
+{
+    int64_t off = kHeaderBytes;
+    off += align_up((plan.npcf + 1) * 4, 256);
     off += align_up((int64_t)plan.segs.size() * (int64_t)sizeof(Segment), 256);
     off += align_up(plan.rec_count * rec_bytes, 256);
     return off;

@@ -27,15 +27,22 @@ struct Plan {
     int64_t lds_records = 0;
 };
 
-// Records a block may hold: half of what one tile can stage in LDS.
-int64_t block_budget(int rec_bytes, bool backward);
+// Tile shape: at most `max_block` PCFs per block and at most 1/`budget_div`
+// of a tile's LDS record capacity per block (2: any two blocks fit).
+struct TileShape {
+    int32_t max_block = kMaxBlock;
+    int32_t budget_div = 2;
+};
+
+// Records a block may hold.
+int64_t block_budget(int rec_bytes, bool backward, const TileShape &shape);
 // Records a tile may stage in LDS.
 int64_t lds_record_capacity(int rec_bytes, bool backward);
 
 // Greedy blocks over PCFs [lo, hi) with forced boundaries at `cuts`.
 // Appends block starts (not the final end) to `blocks`.
 void build_blocks(const int64_t *offsets, int64_t lo, int64_t hi,
-                  std::vector<int64_t> cuts, int64_t budget,
+                  std::vector<int64_t> cuts, int64_t budget, int32_t max_block,
                   std::vector<int32_t> &blocks);
 
 // Plan for one n x n matrix, or the window [r0,r1) x [c0,c1) of it.
@@ -43,16 +50,19 @@ void build_blocks(const int64_t *offsets, int64_t lo, int64_t hi,
 bool plan_matrix(int64_t n, const int64_t *offsets, int rec_bytes,
                  bool backward, bool windowed, int64_t r0, int64_t r1,
                  int64_t c0, int64_t c1, bool upper_only, int64_t ldo,
-                 Plan &plan, std::string &err);
+                 const TileShape &shape, Plan &plan, std::string &err);
 
 // Plan for B independent full matrices in one launch.
 bool plan_batched(int32_t B, const int64_t *set_offsets,
                   const int64_t *out_offsets, const int64_t *offsets,
-                  int64_t n, int rec_bytes, bool upper_only, Plan &plan,
-                  std::string &err);
+                  int64_t n, int rec_bytes, bool upper_only,
+                  const TileShape &shape, Plan &plan, std::string &err);
 
 // Bytes of workspace a plan needs (header, blocks, segments, records).
 int64_t plan_workspace_bytes(const Plan &plan, int rec_bytes);
+// Upper bound of plan_workspace_bytes over all tile shapes (every PCF its
+// own block).
+int64_t plan_workspace_bound(const Plan &plan, int rec_bytes);
 
 // Serialise the plan's header/blocks/segments into a host buffer laid out
 // exactly like the workspace prefix (records region excluded).

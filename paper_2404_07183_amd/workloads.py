@@ -145,25 +145,26 @@ def config_grad(seed=4, N=4096):
 
 def stable_rank_like(N, nmin, nmax, seed, dtype=np.float32, lam=50.0):
     """Nonincreasing, nonnegative integer-valued PCFs: counts U{nmin..nmax},
-    Exp(1) gaps, v_0 ~ Poisson(lam), v_1..v_{n-2} i.i.d. uniform on
-    {0..v_0} sorted descending, v_{n-1} = 0. Many consecutive equal values,
-    i.e. discretizations that are not minimal."""
+    Exp(1) gaps, v_0 ~ Poisson(lam), then v_k = floor((1 - S_k / S_n) *
+    (v_0 + 1)) capped at v_0, with S_k partial sums of Exp(1) draws (sorted
+    uniforms, descending), and v_{n-1} = 0. Many consecutive equal values, i.e.
+    discretizations that are not minimal."""
     rng = _rng(seed)
     counts = rng.integers(nmin, nmax + 1, size=N)
     P = int(counts.sum())
     gaps = rng.exponential(1.0, size=P)
-    v0 = rng.poisson(lam, size=N)
-    u = rng.random(size=P)
+    v0 = rng.poisson(lam, size=N).astype(np.float64)
+    e = rng.exponential(1.0, size=P)
     offsets = np.zeros(N + 1, dtype=np.int64)
     np.cumsum(counts, out=offsets[1:])
+    cs = np.cumsum(e)
+    seg_before = np.concatenate([[0.0], cs[offsets[1:-1] - 1]])
     pcf = np.repeat(np.arange(N), counts)
-    vals = np.floor(u * (v0[pcf] + 1)).astype(np.float64)
-    # sort each PCF's draws descending, keep v_0 first
-    key = pcf.astype(np.float64) * 1e6 - vals
-    order = np.argsort(key, kind="stable")
-    vals = vals[order]
-    first = offsets[:-1]
-    vals[first] = v0.astype(np.float64)
+    S = cs - seg_before[pcf]
+    T = S[offsets[1:] - 1][pcf]
+    vals = np.minimum(np.floor((1.0 - S / T) * (v0[pcf] + 1.0)), v0[pcf])
+    vals[offsets[:-1]] = v0
+    del cs, S, T, pcf, e
     o, t, v = _assemble(counts, gaps, vals)
     return to_dtype(o, t, v, dtype)
 
