@@ -31,6 +31,38 @@ PEAK_FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 OPS_PER_STEP = {"l1": 4, "l2sq": 5, "l2": 5, "gram": 4}  # algorithmic FP64 ops
 
 
+def kernel_source_digest():
+    """SHA-256 over the library's device and host sources (file names and
+    contents, sorted by name): identifies the kernel build that counters
+    were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2404_07183_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the tile kernel for workload `key`, from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    same counter's reading for a copy of known size); None when there is no
+    entry or the sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = data.get("entries", {}).get(key)
+    if not entry or entry.get("source_sha256") != kernel_source_digest():
+        return None
+    return entry.get("bytes_per_launch")
+
+
 def merge_steps_full(o):
     """sum over pairs i<j of (n_i - 1) + (n_j - 1): finite cells without ties."""
     n = np.diff(o).astype(np.float64)
@@ -137,7 +169,7 @@ def run_plain(args):
             "peak": PEAK_FP64_LANE_OPS / 1e12,
             "unit": "TOP/s",
             "frac": achieved / PEAK_FP64_LANE_OPS,
-            "traffic": None,
+            "traffic": measured_traffic("plain-%s-%s-n%d" % (args.kind, args.dtype, N)),
             "kernel": "pairwise_tiles<%s,%s>" % ("double" if args.dtype == "f64" else "float",
                                                   args.kind),
             "kernel_ms": ms_kernel,
@@ -257,16 +289,89 @@ def run_grad(steps, warmup, plain_steps_per_s=None):
     return res
 
 
+def run_strip(args):
+    """One GPU's share of the 500,000-PCF stress run: the 62,500 x 500,000
+    strip of the L1 matrix (FP32), computed in column chunks into a ring of two
+    device buffers, each chunk copied to pinned host memory on a second stream
+    while the next one is computed."""
+    import torch
+
+    from paper_2404_07183_amd import api, workloads
+
+    t_gen = time.perf_counter()
+    o, t, v = workloads.config_strip()
+    t_gen = time.perf_counter() - t_gen
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    N = X.n
+    rows = N // 8
+    # chunk 0 is the rows x rows diagonal block (a symmetric window: each pair
+    # once, written twice); chunks 1.. are rectangles right of it
+    cw = rows
+    nchunks = min(args.strip_chunks, (N + cw - 1) // cw)
+    bufs = [torch.empty((rows, cw), dtype=torch.float32, device="cuda:0") for _ in range(2)]
+    host = [torch.empty((rows, cw), dtype=torch.float32, pin_memory=True) for _ in range(2)]
+    wss = [api.Workspace(device="cuda:0") for _ in range(2)]
+    compute = torch.cuda.current_stream()
+    copy = torch.cuda.Stream()
+    done = [torch.cuda.Event() for _ in range(2)]
+    copied = [torch.cuda.Event() for _ in range(2)]
+    # warm-up: plan both buffers' first windows
+    api.pdist(X, 1.0, window=(0, rows, 0, cw), out=bufs[0], workspace=wss[0])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(compute)
+    for c in range(nchunks):
+        k = c % 2
+        c0, c1 = c * cw, min((c + 1) * cw, N)
+        if c >= 2:
+            compute.wait_event(copied[k])
+        out = bufs[k][:, :c1 - c0]
+        api.pdist(X, 1.0, window=(0, rows, c0, c1), out=out, workspace=wss[k])
+        done[k].record(compute)
+        with torch.cuda.stream(copy):
+            copy.wait_event(done[k])
+            host[k][:, :c1 - c0].copy_(out, non_blocking=True)
+            copied[k].record(copy)
+    e1.record(compute)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cols = min(nchunks * cw, N)
+    # distinct pair integrals computed: rows x cols minus the mirrored half and
+    # the diagonal of the rows x rows block
+    d = min(rows, cols)
+    integrals = rows * cols - d * (d + 1) / 2.0
+    return {
+        "metric": "PCF pair-integrals/sec (L1, F32, strip)",
+        "value": integrals / (ms * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": nchunks, "warmup": 1, "ms_per_step": ms / nchunks,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "strip of the L1 matrix of 500,000 stable-rank-like PCFs: rows "
+                               "0..%d x columns 0..%d, FP32, %d-column chunks streamed to "
+                               "pinned host memory" % (rows - 1, cols - 1, cw),
+                   "pcfs": N, "rows_in_strip": rows, "columns_done": cols,
+                   "generation_s": t_gen},
+        "wall_ms": ms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="plain", choices=["plain"])
+    ap.add_argument("--config", default="plain", choices=["plain", "strip"])
+    ap.add_argument("--strip-chunks", type=int, default=8,
+                    help="column chunks of the strip to compute (8 = all)")
     ap.add_argument("--kind", default="l1", choices=["l1", "l2", "l2sq", "gram"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (a reference "
+                         "for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+adjoint measurements")
     args = ap.parse_args()
@@ -274,6 +379,16 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calibration_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.config == "strip":
+        print(json.dumps(run_strip(args)), flush=True)
+        return
     res = run_plain(args)
     if not args.no_extras:
         plain = res["merge_steps_per_s"]

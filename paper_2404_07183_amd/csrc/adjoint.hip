@@ -153,13 +153,17 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     const int tid = threadIdx.x;
     const double p = args.p;
 
-    for (;;) {
-        if (!tile_setup<double>(sh, lrec, args.ws, offsets, args.gram))
-            break;
-        const int32_t R = sh.R, C = sh.C, npairs = sh.npairs;
-        const bool diag = sh.diag != 0, gmode = sh.global_mode != 0;
+    TileLoop loop;
+    loop.start<double>(sh, args.ws, offsets, lrec, grec);
+    while (loop.live(sh, args.ws)) {
+        const TileDesc &D = sh.desc[loop.cur];
+        const bool gmode = D.global_mode != 0;
+        tile_scan<double>(sh, D, args.gram, gmode ? grec : lrec);
+        const int32_t R = D.R, C = D.C, npairs = sh.npairs;
+        const bool diag = D.diag != 0;
         const int64_t total = sh.pw[npairs];
-        const int64_t nslots = diag ? sh.rrecs : sh.rrecs + sh.crecs;
+        const int64_t per = sh.per;
+        const int64_t nslots = diag ? D.rrecs : D.rrecs + D.crecs;
         if (!gmode)
             for (int64_t q = tid; q < 2 * nslots; q += kThreads)
                 lg[q] = 0.0;
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         // diagonal; stored in the partial-sum slots (unused here)
         if (tid < npairs) {
             const int r = tid / C, c = tid - (tid / C) * C;
-            const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
+            const int64_t i = D.r_lo + r, j = D.c_lo + c;
             double W = 0.0;
             if (sh.pw[tid + 1] > sh.pw[tid]) {
                 W = args.grad_out[i * args.ldg + j];
@@ -180,15 +184,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             }
             sh.part[tid] = W;
         }
-        __syncthreads();
+        sync_lds();
+        loop.take_next(args.ws);
 
-        const int64_t per = steps_per_virtual_lane(total);
-        for (int q = 0; q < 2; ++q) {
-            int64_t s = (int64_t)(2 * tid + q) * per;
-            const int64_t e = (s + per < total) ? s + per : total;
-            if (s >= e)
-                continue;
-            int32_t k = pair_of_step(sh, s);
+        // this lane's share: steps [tid * per, (tid + 1) * per)
+        int64_t s = (int64_t)tid * per;
+        const int64_t e = (s + per < total) ? s + per : total;
+        if (s < e) {
+            int32_t k = sh.pairof[tid];
             int64_t d = s - sh.pw[k];
             while (s < e) {
                 const int r = k / C, c = k - (k / C) * C;
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 sb.last = B + sh.cn[c] - 1;
                 if (gmode) {
                     // global record index -> CSR row: row = record - i * kPad
-                    const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
+                    const int64_t i = D.r_lo + r, j = D.c_lo + c;
                     sa.gt = args.grad_t - i * kPad;
                     sa.gv = args.grad_v - i * kPad;
                     sb.gt = args.grad_t - j * kPad;
@@ -222,22 +225,23 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                     ++k;
             }
         }
-        __syncthreads();
+        sync_lds();
+        loop.decode_next(sh, args.ws, offsets);
 
         // add the tile's accumulators to the outputs; slot 0 of a PCF's
         // time gradient (t_0) and the last value stay untouched (fixed)
         if (!gmode) {
             for (int64_t q = tid; q < nslots; q += kThreads) {
-                const bool in_rows = q < sh.rrecs;
-                const int64_t base = in_rows ? sh.rrec0 : sh.crec0;
-                const int64_t lq = in_rows ? q : q - sh.rrecs;
+                const bool in_rows = q < D.rrecs;
+                const int64_t base = in_rows ? D.rrec0 : D.crec0;
+                const int64_t lq = in_rows ? q : q - D.rrecs;
                 const int64_t rec = base + lq;           // global record index
                 // PCF of this record: the block's PCF whose record range
                 // holds it (blocks are short: linear scan over <= 32)
                 const int32_t nb = in_rows ? R : C;
                 const int32_t *bs = in_rows ? sh.rb : sh.cb;
                 const int32_t *ns = in_rows ? sh.rn : sh.cn;
-                const int64_t pcf0 = in_rows ? sh.r_lo : sh.c_lo;
+                const int64_t pcf0 = in_rows ? D.r_lo : D.c_lo;
                 int32_t which = 0;
                 for (int32_t u = 1; u < nb; ++u)
                     if (bs[u] <= q)
@@ -253,7 +257,9 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                     atomicAdd(&args.grad_v[row], gvv);
             }
         }
-        __syncthreads();
+        // (the accumulator flush reads the block metadata)
+        loop.stage_next<double>(sh, args.ws, grec, offsets, lrec, true);
+        loop.advance();
     }
 }
 

@@ -21,7 +21,7 @@ constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
 // LDS bytes a tile may use for breakpoint records (of 160 KiB per
 // workgroup on gfx950; the rest holds per-pair prefix sums, accumulators
 // and block metadata).
-constexpr int kLdsRecordBytes = 124 * 1024;
+constexpr int kLdsRecordBytes = 128 * 1024;
 // Number of hardware XCDs (each with its own L2) on MI355X.
 constexpr int kXcds = 8;
 

@@ -12,17 +12,24 @@
 //    finite sentinel S (largest finite value of the type), followed by
 //    kPad copies of (S, v_last). A step then needs one record load, of the
 //    side that advances.
-//  * Ties. On equal next times only the row-side PCF advances; the column
-//    side advances in the following step, whose cell has width 0 and adds
-//    exactly 0. Every pair therefore takes exactly (n_f - 1) + (n_g - 1)
-//    steps -- known before the loop, so work can be split exactly.
+//  * Ties. On equal next times only one side advances; the other advances
+//    in the following step, whose cell has width 0 and adds exactly 0.
+//    Every pair therefore takes exactly (n_f - 1) + (n_g - 1) steps (padded
+//    to a multiple of kStepBlock with sentinel steps that add 0) -- known
+//    before the loop, so work can be split exactly. The merge-path split
+//    lets the row side go first; the loop lets the piece loaded last go
+//    first. Both orders give the same cells of positive width, and a lane's
+//    share starts after a whole number of merged breakpoints, whose last
+//    time does not depend on the order, so the shares fit together.
 //  * Tiles and LDS. A workgroup takes a tile (row block x column block) from
 //    a persistent queue, copies both blocks' records into LDS and splits the
-//    tile's total step count evenly over its 1024 lanes. A lane's share may
-//    start inside a pair: its starting pointers come from a merge-path
-//    binary search on the pair's diagonal (the same tie order as the loop),
-//    and partial sums of one pair meet in an LDS accumulator. No lane waits
-//    for a longer pair, whatever the length mix.
+//    tile's total step count evenly over its 1024 lanes, one contiguous run
+//    of steps per lane. A run may start inside a pair: its starting
+//    pointers come from a merge-path binary search on the pair's diagonal,
+//    and partial sums of one pair meet in LDS slots, added in lane order
+//    (deterministic). No lane waits for a longer pair, whatever the length
+//    mix.
+//  * The step (see Chain): one full-wave LDS read per step, no divergence.
 //  * Output. Results are finished (root, unbounded-tail rule) in LDS and
 //    written row by row, then transposed, both coalesced.
 #include <hip/hip_runtime.h>
@@ -108,421 +115,133 @@ __global__ void validate_rows(const int64_t *__restrict__ offsets, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
-// The merge step in CDNA assembly (LDS records, h in {|a-b|, (a-b)^2, ab}).
+// The merge chain.
 //
-// One step: y = min(next_f, next_g); acc += h(a, b) * (y - x); then, with
-// exec masked to the lanes whose row side ends first (ties included), move
-// that side to its next record with one ds_read_b128/b64, and with exec
-// masked to the other lanes move the column side. Written by hand because
-// the compiler turns the two-armed update into register copies on both
-// arms. The s_waitcnt at the end keeps the compiler's view of the loaded
-// registers valid between statements. 7 VALU per step for |a-b| and ab,
-// 8 for (a-b)^2.
+// h is symmetric in its two arguments, so a chain does not track which PCF
+// a piece belongs to: P holds the piece loaded last, Q the other one, each
+// as (end time, value) plus a pointer to its record. One step closes the
+// cell [x, y), y = min(P.t, Q.t); the piece that ends there (P on equal
+// times) is replaced by its successor, which is always loaded into P (the
+// piece that goes on becomes Q). Every lane of a wave loads one record per
+// step: one full-wave LDS read, no divergent branch. The end time of the
+// piece that goes on is max(P.t, Q.t), which saves two selects.
 
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f2v __attribute__((ext_vector_type(2)));
+// Record pointers: LDS (32-bit addresses) or global memory.
+template <typename T> struct LdsSrc {
+    typedef const __attribute__((address_space(3))) typename RecVec<T>::type *ptr;
+    __device__ __forceinline__ static ptr at(const Rec<T> *base, int32_t i)
+    {
+        return (ptr)(size_t)lds_address(base + i);
+    }
+};
+template <typename T> struct GlobalSrc {
+    typedef const typename RecVec<T>::type *ptr;
+    __device__ __forceinline__ static ptr at(const Rec<T> *base, int32_t i)
+    {
+        return reinterpret_cast<ptr>(base + i);
+    }
+};
 
-template <typename T> struct RecVec;
-template <> struct RecVec<double> { typedef d2v type; };
-template <> struct RecVec<float> { typedef f2v type; };
-
-#define PCF_STEP_TAIL(RD, STRIDE)                                   \
-    "v_cmp_le_" #RD " vcc, %[nf], %[ng]\n\t"                      \
-    "s_and_saveexec_b64 %[sv], vcc\n\t"                             \
-    "v_add_u32 %[ia], " STRIDE ", %[ia]\n\t"                        \
-    "ds_read_b" PCF_RECBITS_##RD " %[ra], %[ia]\n\t"               \
-    "s_andn2_b64 exec, %[sv], vcc\n\t"                              \
-    "v_add_u32 %[ib], " STRIDE ", %[ib]\n\t"                        \
-    "ds_read_b" PCF_RECBITS_##RD " %[rb], %[ib]\n\t"               \
-    "s_mov_b64 exec, %[sv]"
-
-// Each step first waits until at most two LDS reads are outstanding: the
-// two issued by the other chain's step in between (LDS reads complete in
-// issue order). The caller ends every block with pcf_lds_drain(), so no
-// read is in flight outside a block of steps.
-#define PCF_STEP_HEAD "s_waitcnt lgkmcnt(2)\n\t"
-
-__device__ __forceinline__ void pcf_lds_drain()
+// v_min / v_max without the quieting of signalling NaNs that fmin/fmax
+// would add (the data contract excludes NaN).
+__device__ __forceinline__ double min_raw(double a, double b)
 {
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float min_raw(float a, float b)
+{
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double max_raw(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float max_raw(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
-#define PCF_RECBITS_f64 "128"
-#define PCF_RECBITS_f32 "64"
-
-template <typename T, int HK> struct AsmStep;
-
-// Head of a step for a chain that runs alone (no other chain's reads in
-// flight): wait for all outstanding LDS reads.
-#define PCF_STEP_HEAD_SOLO "s_waitcnt lgkmcnt(0)\n\t"
-
-#define PCF_ASM_OPERANDS                                                      \
-    : [ra] "+v"(ra), [rb] "+v"(rb), [ia] "+v"(ia), [ib] "+v"(ib),           \
-      [acc] "+v"(acc), [y] "=&v"(y), [d] "=&v"(d), [dv] "=&v"(dv),          \
-      [sv] "=&s"(sv)                                                        \
-    : [nf] "v"(ra.x), [ng] "v"(rb.x), [a] "v"(ra.y), [b] "v"(rb.y),         \
-      [x] "v"(x)                                                            \
-    : "vcc", "scc", "memory"
-
-template <> struct AsmStep<double, kAbs> {
-    template <bool SOLO>
-    __device__ __forceinline__ static void run(d2v &ra, d2v &rb, uint32_t &ia,
-                                               uint32_t &ib, double x, double &y,
-                                               double &acc)
-    {
-        double d, dv;
-        uint64_t sv;
-        if constexpr (SOLO)
-            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f64 %[y], %[nf], %[ng]\n\t"
-                     "v_add_f64 %[d], %[y], -%[x]\n\t"
-                     "v_add_f64 %[dv], %[a], -%[b]\n\t"
-                     "v_fma_f64 %[acc], |%[dv]|, %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f64, "16")
-                     PCF_ASM_OPERANDS);
-        else
-            asm volatile(PCF_STEP_HEAD "v_min_f64 %[y], %[nf], %[ng]\n\t"
-                     "v_add_f64 %[d], %[y], -%[x]\n\t"
-                     "v_add_f64 %[dv], %[a], -%[b]\n\t"
-                     "v_fma_f64 %[acc], |%[dv]|, %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f64, "16")
-                     PCF_ASM_OPERANDS);
-    }
-};
-template <> struct AsmStep<double, kSqr> {
-    template <bool SOLO>
-    __device__ __forceinline__ static void run(d2v &ra, d2v &rb, uint32_t &ia,
-                                               uint32_t &ib, double x, double &y,
-                                               double &acc)
-    {
-        double d, dv;
-        uint64_t sv;
-        if constexpr (SOLO)
-            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f64 %[y], %[nf], %[ng]\n\t"
-                     "v_add_f64 %[d], %[y], -%[x]\n\t"
-                     "v_add_f64 %[dv], %[a], -%[b]\n\t"
-                     "v_mul_f64 %[d], %[dv], %[d]\n\t"
-                     "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f64, "16")
-                     PCF_ASM_OPERANDS);
-        else
-            asm volatile(PCF_STEP_HEAD "v_min_f64 %[y], %[nf], %[ng]\n\t"
-                     "v_add_f64 %[d], %[y], -%[x]\n\t"
-                     "v_add_f64 %[dv], %[a], -%[b]\n\t"
-                     "v_mul_f64 %[d], %[dv], %[d]\n\t"
-                     "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f64, "16")
-                     PCF_ASM_OPERANDS);
-    }
-};
-template <> struct AsmStep<double, kProd> {
-    template <bool SOLO>
-    __device__ __forceinline__ static void run(d2v &ra, d2v &rb, uint32_t &ia,
-                                               uint32_t &ib, double x, double &y,
-                                               double &acc)
-    {
-        double d, dv;
-        uint64_t sv;
-        if constexpr (SOLO)
-            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f64 %[y], %[nf], %[ng]\n\t"
-                     "v_add_f64 %[d], %[y], -%[x]\n\t"
-                     "v_mul_f64 %[dv], %[a], %[b]\n\t"
-                     "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f64, "16")
-                     PCF_ASM_OPERANDS);
-        else
-            asm volatile(PCF_STEP_HEAD "v_min_f64 %[y], %[nf], %[ng]\n\t"
-                     "v_add_f64 %[d], %[y], -%[x]\n\t"
-                     "v_mul_f64 %[dv], %[a], %[b]\n\t"
-                     "v_fma_f64 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f64, "16")
-                     PCF_ASM_OPERANDS);
-    }
-};
-template <> struct AsmStep<float, kAbs> {
-    template <bool SOLO>
-    __device__ __forceinline__ static void run(f2v &ra, f2v &rb, uint32_t &ia,
-                                               uint32_t &ib, float x, float &y,
-                                               float &acc)
-    {
-        float d, dv;
-        uint64_t sv;
-        if constexpr (SOLO)
-            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f32 %[y], %[nf], %[ng]\n\t"
-                     "v_sub_f32 %[d], %[y], %[x]\n\t"
-                     "v_sub_f32 %[dv], %[a], %[b]\n\t"
-                     "v_fma_f32 %[acc], |%[dv]|, %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f32, "8")
-                     PCF_ASM_OPERANDS);
-        else
-            asm volatile(PCF_STEP_HEAD "v_min_f32 %[y], %[nf], %[ng]\n\t"
-                     "v_sub_f32 %[d], %[y], %[x]\n\t"
-                     "v_sub_f32 %[dv], %[a], %[b]\n\t"
-                     "v_fma_f32 %[acc], |%[dv]|, %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f32, "8")
-                     PCF_ASM_OPERANDS);
-    }
-};
-template <> struct AsmStep<float, kSqr> {
-    template <bool SOLO>
-    __device__ __forceinline__ static void run(f2v &ra, f2v &rb, uint32_t &ia,
-                                               uint32_t &ib, float x, float &y,
-                                               float &acc)
-    {
-        float d, dv;
-        uint64_t sv;
-        if constexpr (SOLO)
-            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f32 %[y], %[nf], %[ng]\n\t"
-                     "v_sub_f32 %[d], %[y], %[x]\n\t"
-                     "v_sub_f32 %[dv], %[a], %[b]\n\t"
-                     "v_mul_f32 %[d], %[dv], %[d]\n\t"
-                     "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f32, "8")
-                     PCF_ASM_OPERANDS);
-        else
-            asm volatile(PCF_STEP_HEAD "v_min_f32 %[y], %[nf], %[ng]\n\t"
-                     "v_sub_f32 %[d], %[y], %[x]\n\t"
-                     "v_sub_f32 %[dv], %[a], %[b]\n\t"
-                     "v_mul_f32 %[d], %[dv], %[d]\n\t"
-                     "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f32, "8")
-                     PCF_ASM_OPERANDS);
-    }
-};
-template <> struct AsmStep<float, kProd> {
-    template <bool SOLO>
-    __device__ __forceinline__ static void run(f2v &ra, f2v &rb, uint32_t &ia,
-                                               uint32_t &ib, float x, float &y,
-                                               float &acc)
-    {
-        float d, dv;
-        uint64_t sv;
-        if constexpr (SOLO)
-            asm volatile(PCF_STEP_HEAD_SOLO "v_min_f32 %[y], %[nf], %[ng]\n\t"
-                     "v_sub_f32 %[d], %[y], %[x]\n\t"
-                     "v_mul_f32 %[dv], %[a], %[b]\n\t"
-                     "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f32, "8")
-                     PCF_ASM_OPERANDS);
-        else
-            asm volatile(PCF_STEP_HEAD "v_min_f32 %[y], %[nf], %[ng]\n\t"
-                     "v_sub_f32 %[d], %[y], %[x]\n\t"
-                     "v_mul_f32 %[dv], %[a], %[b]\n\t"
-                     "v_fma_f32 %[acc], %[dv], %[d], %[acc]\n\t"
-                     PCF_STEP_TAIL(f32, "8")
-                     PCF_ASM_OPERANDS);
-    }
-};
-
-// One merge chain: a contiguous run of the tile's steps, possibly over
-// several pairs. Its partial sum of pair k goes to sh.part[k + vl].
-template <typename T>
+template <typename T, typename Src>
 struct Chain {
-    typename RecVec<T>::type ra, rb;  // current (end time, value) records
-    uint32_t ia, ib;                  // their LDS byte addresses
-    T x0, x1;                         // start of the current cell (alternating)
-    double acc;
-    int64_t left;                     // steps left in pair k
-    int32_t k, vl;
+    typename RecVec<T>::type P, Q;
+    typename Src::ptr pP, pQ;
+    T x;          // start of the current cell
+    double acc;   // sum over the current pair (FP64 for both types)
+    int64_t left; // steps left in the current pair
+    int32_t k;    // current pair of the tile
 };
 
-template <typename T, typename Shared>
-__device__ __forceinline__ void chain_begin(Chain<T> &ch, Shared &sh,
-                                            const Rec<T> *lrec, int64_t s,
-                                            int32_t vl, int32_t C)
+template <typename T, int HK, typename Src>
+__device__ __forceinline__ void chain_step(Chain<T, Src> &ch, T &part, T p)
 {
-    typedef typename RecVec<T>::type V;
-    const V *lv = reinterpret_cast<const V *>(lrec);
-    const int32_t k = pair_of_step(sh, s);
-    const int64_t d = s - sh.pw[k];
+    const T tP = ch.P.x, tQ = ch.Q.x;
+    const T y = min_raw(tP, tQ);
+    part = fma(hval<T, HK>(ch.P.y, ch.Q.y, p), y - ch.x, part);
+    ch.x = y;
+    const bool c = tP <= tQ;
+    const typename Src::ptr pN = c ? ch.pP : ch.pQ;
+    ch.pQ = c ? ch.pQ : ch.pP;
+    ch.Q.x = max_raw(tP, tQ);
+    ch.Q.y = c ? ch.Q.y : ch.P.y;
+    ch.pP = pN + 1;
+    ch.P = *ch.pP;
+}
+
+// Starting state at step d of pair k (merge-path split).
+template <typename T, typename Src, typename Shared>
+__device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
+                                            const Rec<T> *base, int32_t k,
+                                            int64_t d, int32_t C)
+{
     const int r = k / C, c = k - (k / C) * C;
     int32_t i0, j0;
     T x;
-    pair_start<T>(lrec, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, i0, j0, x);
-    ch.ra = lv[i0];
-    ch.rb = lv[j0];
-    ch.ia = lds_address(&lrec[i0]);
-    ch.ib = lds_address(&lrec[j0]);
-    ch.x0 = x;
+    pair_start<T>(base, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, i0, j0, x);
+    ch.pP = Src::at(base, i0);
+    ch.pQ = Src::at(base, j0);
+    ch.P = *ch.pP;
+    ch.Q = *ch.pQ;
+    ch.x = x;
     ch.acc = 0.0;
     ch.left = sh.pw[k + 1] - sh.pw[k] - d;
     ch.k = k;
-    ch.vl = vl;
 }
 
-// Between blocks: a chain that finished its pair records it and moves to
-// the next pair with steps (a rare, divergent branch).
-template <typename T, typename Shared>
-__device__ __forceinline__ void chain_advance(Chain<T> &ch, Shared &sh,
-                                              const Rec<T> *lrec, int32_t C)
+// This lane's share of the tile: steps [s, e) (e - s a multiple of
+// kStepBlock, pair boundaries too), starting in pair k; its partial sum of
+// pair k' goes to sh.part[k' + vl].
+template <typename T, int HK, typename Src, typename Shared>
+__device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
+                                           int64_t s, int64_t e, int32_t k,
+                                           int32_t vl, int32_t C, T p)
 {
-    if (ch.left != 0)
-        return;
-    typedef typename RecVec<T>::type V;
-    const V *lv = reinterpret_cast<const V *>(lrec);
-    sh.part[ch.k + ch.vl] = ch.acc;
-    ch.acc = 0.0;
-    int32_t k = ch.k + 1;
-    while (k < sh.npairs && sh.pw[k + 1] == sh.pw[k])
-        ++k;
-    ch.k = k;
-    ch.left = sh.pw[k + 1] - sh.pw[k];
-    const int r = k / C, c = k - (k / C) * C;
-    const int32_t A = sh.rb[r], B = sh.cb[c];
-    ch.ra = lv[A];
-    ch.rb = lv[B];
-    ch.ia = lds_address(&lrec[A]);
-    ch.ib = lds_address(&lrec[B]);
-    ch.x0 = T(0);
-}
-
-// Two chains of one lane, steps interleaved so that each chain's record
-// reads are in flight while the other chain computes.
-template <typename T, int HK>
-__device__ __forceinline__ void block_pair(Chain<T> &c0, Chain<T> &c1)
-{
-    T p0 = T(0), p1 = T(0);
-#pragma unroll
-    for (int u = 0; u < kStepBlock; u += 2) {
-        AsmStep<T, HK>::template run<false>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x0, c0.x1, p0);
-        AsmStep<T, HK>::template run<false>(c1.ra, c1.rb, c1.ia, c1.ib, c1.x0, c1.x1, p1);
-        AsmStep<T, HK>::template run<false>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x1, c0.x0, p0);
-        AsmStep<T, HK>::template run<false>(c1.ra, c1.rb, c1.ia, c1.ib, c1.x1, c1.x0, p1);
-    }
-    pcf_lds_drain();
-    c0.acc += (double)p0;
-    c1.acc += (double)p1;
-    c0.left -= kStepBlock;
-    c1.left -= kStepBlock;
-}
-
-template <typename T, int HK>
-__device__ __forceinline__ void block_solo(Chain<T> &c0)
-{
-    T p0 = T(0);
-#pragma unroll
-    for (int u = 0; u < kStepBlock; u += 2) {
-        AsmStep<T, HK>::template run<true>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x0, c0.x1, p0);
-        AsmStep<T, HK>::template run<true>(c0.ra, c0.rb, c0.ia, c0.ib, c0.x1, c0.x0, p0);
-    }
-    pcf_lds_drain();
-    c0.acc += (double)p0;
-    c0.left -= kStepBlock;
-}
-
-// This lane's two chains: virtual lanes 2*lane and 2*lane+1 of the tile's
-// even split, steps [s0, e0) and [s1, e1) with e0 == s1 (e1 - s1 <= e0 - s0,
-// only the tile's last lanes are short). Both run in one block loop.
-template <typename T, int HK, typename Shared>
-__device__ __forceinline__ void lane_chains_lds(Shared &sh, const Rec<T> *lrec,
-                                                int64_t s0, int64_t e0,
-                                                int64_t s1, int64_t e1,
-                                                int32_t lane, int32_t C)
-{
-    const int64_t nb0 = (e0 - s0) / kStepBlock;
-    const int64_t nb1 = (e1 > s1) ? (e1 - s1) / kStepBlock : 0;
-    Chain<T> c0, c1;
-    chain_begin(c0, sh, lrec, s0, 2 * lane, C);
-    if (nb1 > 0)
-        chain_begin(c1, sh, lrec, s1, 2 * lane + 1, C);
-    int64_t blk = 0;
-    for (; blk < nb1; ++blk) {
-        chain_advance(c0, sh, lrec, C);
-        chain_advance(c1, sh, lrec, C);
-        block_pair<T, HK>(c0, c1);
-    }
-    for (; blk < nb0; ++blk) {
-        chain_advance(c0, sh, lrec, C);
-        block_solo<T, HK>(c0);
-    }
-    sh.part[c0.k + c0.vl] = c0.acc;
-    if (nb1 > 0)
-        sh.part[c1.k + c1.vl] = c1.acc;
-}
-
-// Single-chain C++ loop (h = |a-b|^p, whose step is not hand-written).
-template <typename T, int HK, typename Shared>
-__device__ __forceinline__ void chain_cpp(Shared &sh, const Rec<T> *lrec,
-                                          int64_t s, int64_t e, int32_t vl,
-                                          int32_t C, T p)
-{
-    int32_t k = pair_of_step(sh, s);
-    int64_t d = s - sh.pw[k];
-    int64_t left = sh.pw[k + 1] - sh.pw[k] - d;
-    int32_t ia, ib;
-    T x;
-    {
-        const int r = k / C, c = k - (k / C) * C;
-        pair_start<T>(lrec, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, ia, ib, x);
-    }
-    Rec<T> ra = lrec[ia], rb = lrec[ib];
-    double acc = 0.0;
-    const int64_t nblk = (e - s) / kStepBlock;
-    for (int64_t blk = 0; blk < nblk; ++blk) {
-        if (left == 0) {
-            sh.part[k + vl] = acc;
-            acc = 0.0;
-            ++k;
-            while (k < sh.npairs && sh.pw[k + 1] == sh.pw[k])
-                ++k;
-            left = sh.pw[k + 1] - sh.pw[k];
-            const int r = k / C, c = k - (k / C) * C;
-            ia = sh.rb[r];
-            ib = sh.cb[c];
-            ra = lrec[ia];
-            rb = lrec[ib];
-            x = T(0);
+    Chain<T, Src> ch;
+    chain_begin(ch, sh, base, k, s - sh.pw[k], C);
+    for (int64_t blk = (e - s) / kStepBlock; blk > 0; --blk) {
+        if (ch.left == 0) {
+            // next pair with steps (a rare, divergent branch)
+            sh.part[ch.k + vl] = ch.acc;
+            int32_t kn = ch.k + 1;
+            while (kn < sh.npairs && sh.pw[kn + 1] == sh.pw[kn])
+                ++kn;
+            chain_begin(ch, sh, base, kn, 0, C);
         }
         T part = T(0);
 #pragma unroll
-        for (int u = 0; u < kStepBlock; ++u) {
-            const T y = ra.t <= rb.t ? ra.t : rb.t;
-            part = fma(hval<T, HK>(ra.v, rb.v, p), y - x, part);
-            x = y;
-            if (ra.t <= rb.t)
-                ra = lrec[++ia];
-            else
-                rb = lrec[++ib];
-        }
-        acc += (double)part;
-        left -= kStepBlock;
+        for (int u = 0; u < kStepBlock; ++u)
+            chain_step<T, HK>(ch, part, p);
+        ch.acc += (double)part;
+        ch.left -= kStepBlock;
     }
-    sh.part[k + vl] = acc;
-}
-
-// Same from global memory (tiles too large for LDS): plain loads.
-template <typename T, int HK>
-__device__ __noinline__ double run_pair_global(const Rec<T> *grec, int32_t A,
-                                               int32_t na, int32_t B,
-                                               int32_t nb, int64_t d,
-                                               int64_t m, T p)
-{
-    int32_t ia, ib;
-    T x;
-    pair_start<T>(grec, A, na, B, nb, d, ia, ib, x);
-    Rec<T> ra = grec[ia], rb = grec[ib];
-    T nf = ra.t, a = ra.v, ng = rb.t, b = rb.v;
-    double acc = 0.0;
-    for (int64_t blk = 0; blk < m; blk += kStepBlock) {
-        T part = T(0);
-        for (int u = 0; u < kStepBlock; ++u) {
-            const T y = nf <= ng ? nf : ng;
-            part = fma(hval<T, HK>(a, b, p), y - x, part);
-            x = y;
-            if (nf <= ng) {
-                ++ia;
-                const Rec<T> r = grec[ia];
-                nf = r.t;
-                a = r.v;
-            } else {
-                ++ib;
-                const Rec<T> r = grec[ib];
-                ng = r.t;
-                b = r.v;
-            }
-        }
-        acc += (double)part;
-    }
-    return acc;
+    sh.part[ch.k + vl] = ch.acc;
 }
 
 template <typename T, int HK>
@@ -537,69 +256,53 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     const Rec<T> *grec = reinterpret_cast<const Rec<T> *>(ws + h.off_rec);
     const int64_t *offsets = args.offsets;
     const T p = (T)args.p;
+    T *out = reinterpret_cast<T *>(args.out);
 
-    for (;;) {
-        if (!tile_setup<T>(sh, lrec, ws, offsets, args.gram))
-            break;
-        const int32_t R = sh.R, C = sh.C, npairs = sh.npairs;
-        const bool diag = sh.diag != 0, gmode = sh.global_mode != 0;
+    TileLoop loop;
+    loop.start<T>(sh, ws, offsets, lrec, grec);
+    while (loop.live(sh, ws)) {
+        const TileDesc &D = sh.desc[loop.cur];
+        const bool gmode = D.global_mode != 0;
+        tile_scan<T>(sh, D, args.gram, gmode ? grec : lrec);
+        const int32_t R = D.R, C = D.C, npairs = sh.npairs;
+        const bool diag = D.diag != 0;
         const int64_t total = sh.pw[npairs];
+        const int64_t per = sh.per;
 
-        // the tile's steps split evenly over 2 * kThreads virtual lanes, two
-        // per lane (see lane_chains_lds)
-        const int64_t per = steps_per_virtual_lane(total);
-        const int64_t s0 = (int64_t)(2 * tid) * per;
+        loop.take_next(ws);
+        // this lane's share: steps [tid * per, (tid + 1) * per)
+        const int64_t s0 = (int64_t)tid * per;
         const int64_t e0 = (s0 + per < total) ? s0 + per : total;
-        const int64_t s1 = e0;
-        const int64_t e1 = (s1 + per < total) ? s1 + per : total;
+        const int32_t k0 = s0 < e0 ? sh.pairof[tid] : 0;
         if (s0 < e0) {
-            if (gmode) {
-                for (int q = 0; q < 2; ++q) {
-                    int64_t s = q ? s1 : s0;
-                    const int64_t e = q ? e1 : e0;
-                    if (s >= e)
-                        continue;
-                    int32_t k = pair_of_step(sh, s);
-                    int64_t d = s - sh.pw[k];
-                    while (s < e) {
-                        const int r = k / C, c = k - (k / C) * C;
-                        const int64_t len = sh.pw[k + 1] - sh.pw[k];
-                        const int64_t m = (len - d < e - s) ? len - d : e - s;
-                        sh.part[k + 2 * tid + q] = run_pair_global<T, HK>(
-                            grec, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, m, p);
-                        s += m;
-                        d = 0;
-                        ++k;
-                        while (k < npairs && sh.pw[k + 1] == sh.pw[k])
-                            ++k;
-                    }
-                }
-            } else if constexpr (HK == kPow) {
-                chain_cpp<T, HK>(sh, lrec, s0, e0, 2 * tid, C, p);
-                if (s1 < e1)
-                    chain_cpp<T, HK>(sh, lrec, s1, e1, 2 * tid + 1, C, p);
-            } else {
-                lane_chains_lds<T, HK>(sh, lrec, s0, e0, s1, e1, tid, C);
-            }
+            if (gmode)
+                lane_chain<T, HK, GlobalSrc<T>>(sh, grec, s0, e0, k0, tid, C, p);
+            else
+                lane_chain<T, HK, LdsSrc<T>>(sh, lrec, s0, e0, k0, tid, C, p);
         }
-        __syncthreads();
+        sync_lds();
+        loop.decode_next(sh, ws, offsets);
 
         // finish: unbounded-tail rule, root; write (i, j) row-major
-        const Rec<T> *src = gmode ? grec : lrec;
         for (int k = tid; k < npairs; k += kThreads) {
             const int r = k / C, c = k - (k / C) * C;
             if (diag && r > c)
                 continue;
-            double val = 0.0;
             const int64_t b0 = sh.pw[k], b1 = sh.pw[k + 1];
+            double val = 0.0;
             if (b1 > b0) {
-                const int64_t l0 = b0 / per, l1 = (b1 - 1) / per;
-                for (int64_t l = l0; l <= l1; ++l)
+                // the pair's partial sums in lane order, loads batched
+                int64_t l = b0 / per;
+                const int64_t l1 = (b1 - 1) / per;
+                for (; l + 3 <= l1; l += 4) {
+                    const double q0 = sh.part[k + l], q1 = sh.part[k + l + 1];
+                    const double q2 = sh.part[k + l + 2], q3 = sh.part[k + l + 3];
+                    val = (((val + q0) + q1) + q2) + q3;
+                }
+                for (; l <= l1; ++l)
                     val += sh.part[k + l];
             }
-            const T la = src[sh.rb[r] + sh.rn[r] - 1].v;
-            const T lb = src[sh.cb[c] + sh.cn[c] - 1].v;
-            const T ht = hval<T, HK>(la, lb, p);
+            const T ht = hval<T, HK>((T)sh.rlast[r], (T)sh.clast[c], p);
             if (ht != T(0))
                 val = ht > T(0) ? INFINITY : -INFINITY;
             if (args.root == kRootSqrt)
@@ -607,24 +310,24 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
             else if (args.root == kRootPow)
                 val = pow(val, args.inv_p);
             sh.part[k + b0 / per] = val;
-            const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
-            T *out = reinterpret_cast<T *>(args.out);
-            out[sh.obase + (i - sh.row0) * sh.ldo + (j - sh.col0)] = (T)val;
+            const int64_t i = D.r_lo + r, j = D.c_lo + c;
+            out[D.obase + (i - D.row0) * D.ldo + (j - D.col0)] = (T)val;
         }
-        if (sh.mirror) {
-            __syncthreads();
+        if (D.mirror) {
+            sync_lds();
             for (int q = tid; q < npairs; q += kThreads) {
                 const int c = q / R, r = q - (q / R) * R;
                 if (diag && r >= c)
                     continue;
                 const int kk = r * C + c;
                 const double val = sh.part[kk + sh.pw[kk] / per];
-                const int64_t i = sh.r_lo + r, j = sh.c_lo + c;
-                T *out = reinterpret_cast<T *>(args.out);
-                out[sh.obase + (j - sh.row0) * sh.ldo + (i - sh.col0)] = (T)val;
+                const int64_t i = D.r_lo + r, j = D.c_lo + c;
+                out[D.obase + (j - D.row0) * D.ldo + (i - D.col0)] = (T)val;
             }
         }
-        __syncthreads();
+        // (finishing reads neither records nor block metadata)
+        loop.stage_next<T>(sh, ws, grec, offsets, lrec, false);
+        loop.advance();
     }
 }
 
@@ -727,3 +430,4 @@ template hipError_t launch_validate<double>(const int64_t *, int64_t,
                                             hipStream_t);
 
 }  // namespace pcf
+

@@ -66,28 +66,47 @@ __device__ __forceinline__ int64_t pcf_of_row(const int64_t *__restrict__ offset
 // ---------------------------------------------------------------------------
 // Tile kernel
 
+// A decoded tile: which blocks, where their records are, where the results
+// go. Written by the queue lane, read by all threads from LDS.
+struct TileDesc {
+    int64_t tile;          // >= ntiles: the queue is empty
+    int64_t r_lo, c_lo;    // first PCF of the row / column block
+    int64_t rrec0, crec0;  // first global record of the row / column block
+    int64_t rrecs, crecs;  // records of the row / column block
+    int64_t obase, ldo, row0, col0;  // output mapping of the segment
+    int32_t R, C, diag, mirror, global_mode, pad_;
+};
+
 struct TileShared {
     int64_t pw[kMaxPairs + 1];  // exclusive prefix of padded pair steps
-    // partial sums: virtual lane l's share of pair k lands in slot k + l (distinct
-    // for all (k, l) because both the pairs and the lanes' step ranges are
-    // ordered); each pair then adds its slots in lane order, so the result
-    // does not depend on timing
-    // (the finished result of pair k goes to slot k + pw[k] / per, also
-    // unique per pair, zero-step pairs included)
-    double part[kMaxPairs + 2 * kThreads];
+    // partial sums: virtual lane l's share of pair k lands in slot k + l
+    // (distinct for all (k, l) because both the pairs and the lanes' step
+    // ranges are ordered); each pair then adds its slots in lane order, so
+    // the result does not depend on timing. The finished result of pair k
+    // goes to slot k + pw[k] / per, also unique per pair, zero-step pairs
+    // included.
+    double part[kMaxPairs + kThreads];
+    int32_t pairof[kThreads];  // pair holding the first step of each lane
     int32_t rn[kMaxBlock], rb[kMaxBlock];  // row PCF rows / record base
     int32_t cn[kMaxBlock], cb[kMaxBlock];  // column PCF rows / record base
+    double rlast[kMaxBlock], clast[kMaxBlock];  // last values (tail rule)
     int64_t wsum[kThreads / 64];
-    int64_t tile;
-    int64_t r_lo, c_lo, rrec0, crec0;
-    int64_t obase, ldo, row0, col0;
-    int64_t rrecs, crecs;  // records of the row / column block
-    int32_t R, C, diag, mirror, global_mode, npairs;
+    TileDesc desc[3];  // ring of tile descriptors (see TileLoop)
+    int64_t per;       // steps per lane of the current tile
+    int32_t npairs;
 };
 
 constexpr int kSharedHead = (int)((sizeof(TileShared) + 255) / 256 * 256);
 static_assert(kSharedHead + kLdsRecordBytes <= 160 * 1024,
               "tile LDS must fit the 160 KiB a gfx950 workgroup can have");
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, not for its global stores (no thread of the workgroup reads
+// the output back), so writing a tile's results does not stall the next.
+__device__ __forceinline__ void sync_lds()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 // Exclusive block-wide scan of one int64 per thread; returns the exclusive
 // prefix and writes the total to *total (all threads).
@@ -104,7 +123,7 @@ __device__ __forceinline__ int64_t block_scan(int64_t x, int64_t *wsum,
     }
     if (lane == 63)
         wsum[wave] = inc;
-    __syncthreads();
+    sync_lds();
     if (wave == 0) {
         int64_t s = (lane < kThreads / 64) ? wsum[lane] : 0;
 #pragma unroll
@@ -116,7 +135,7 @@ __device__ __forceinline__ int64_t block_scan(int64_t x, int64_t *wsum,
         if (lane < kThreads / 64)
             wsum[lane] = s;  // inclusive over waves
     }
-    __syncthreads();
+    sync_lds();
     const int64_t before = (wave > 0 ? wsum[wave - 1] : 0);
     *total = wsum[kThreads / 64 - 1];
     return before + inc - x;
@@ -205,107 +224,178 @@ __device__ __forceinline__ void pair_start(Src src, int32_t A, int32_t na,
     }
 }
 
-// Largest k with pw[k] <= s (the pair holding step s of the tile).
-template <typename Shared>
-__device__ __forceinline__ int32_t pair_of_step(const Shared &sh, int64_t s)
-{
-    int32_t lo = 0, hi = sh.npairs - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (sh.pw[mid] <= s)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
+// The lane that takes tickets from the tile queue and decodes the next tile:
+// first lane of the last wave, which has no finishing work while a tile has
+// at most kThreads - 64 pairs.
+constexpr int kQueueLane = kThreads - 64;
 
-// Pops the next tile from the queue, decodes it, writes the block metadata,
-// stages both blocks' records into LDS (unless they do not fit: global
-// mode) and prefix-sums the padded step counts of its pairs into sh.pw.
-// Diagonal tiles give work to pairs r < c, and to r == c when `gram`.
-// Every thread of the workgroup calls it; returns false when the queue is
-// empty (uniformly).
-template <typename T>
-__device__ __forceinline__ bool tile_setup(TileShared &sh, Rec<T> *lrec,
-                                           const unsigned char *ws,
-                                           const int64_t *offsets, int gram)
+// Takes the next ticket from the tile queue.
+__device__ __forceinline__ int64_t tile_ticket(const unsigned char *ws)
 {
-    const int tid = threadIdx.x;
-    const WsHeader &h = hdr_of(ws);
-    const int32_t *blocks = reinterpret_cast<const int32_t *>(ws + h.off_blocks);
-    const Rec<T> *grec = reinterpret_cast<const Rec<T> *>(ws + h.off_rec);
     uint32_t *counter =
         const_cast<uint32_t *>(reinterpret_cast<const WsHeader *>(ws)->counter);
-    if (tid == 0) {
-        const int64_t tile = (int64_t)atomicAdd(&counter[0], 1u);
-        sh.tile = tile;
-        if (tile < h.ntiles) {
-            const Segment *seg;
-            int32_t I, J;
-            locate_tile(h, ws, tile, seg, I, J);
-            const int64_t r_lo = blocks[I], r_hi = blocks[I + 1];
-            const int64_t c_lo = blocks[J], c_hi = blocks[J + 1];
-            sh.r_lo = r_lo;
-            sh.c_lo = c_lo;
-            sh.R = (int32_t)(r_hi - r_lo);
-            sh.C = (int32_t)(c_hi - c_lo);
-            sh.diag = (seg->type == kSegTriangle && I == J) ? 1 : 0;
-            sh.mirror = seg->mirror;
-            sh.obase = seg->obase;
-            sh.ldo = seg->ldo;
-            sh.row0 = seg->row0;
-            sh.col0 = seg->col0;
-            sh.rrec0 = offsets[r_lo] + r_lo * kPad;
-            sh.crec0 = offsets[c_lo] + c_lo * kPad;
-            const int64_t rrecs = offsets[r_hi] + r_hi * kPad - sh.rrec0;
-            const int64_t crecs = offsets[c_hi] + c_hi * kPad - sh.crec0;
-            const int64_t need = sh.diag ? rrecs : rrecs + crecs;
-            sh.global_mode = need > h.lds_records ? 1 : 0;
-            sh.npairs = sh.R * sh.C;
-            sh.rrecs = rrecs;
-            sh.crecs = crecs;
+    return (int64_t)atomicAdd(&counter[0], 1u);
+}
+
+// Decodes ticket `tile` into d (one lane).
+__device__ __forceinline__ void tile_decode(TileDesc &d, int64_t tile,
+                                            const unsigned char *ws,
+                                            const int64_t *offsets)
+{
+    const WsHeader &h = hdr_of(ws);
+    d.tile = tile;
+    if (tile >= h.ntiles)
+        return;
+    const int32_t *blocks = reinterpret_cast<const int32_t *>(ws + h.off_blocks);
+    const Segment *seg;
+    int32_t I, J;
+    locate_tile(h, ws, tile, seg, I, J);
+    const int64_t r_lo = blocks[I], r_hi = blocks[I + 1];
+    const int64_t c_lo = blocks[J], c_hi = blocks[J + 1];
+    d.r_lo = r_lo;
+    d.c_lo = c_lo;
+    d.R = (int32_t)(r_hi - r_lo);
+    d.C = (int32_t)(c_hi - c_lo);
+    d.diag = (seg->type == kSegTriangle && I == J) ? 1 : 0;
+    d.mirror = seg->mirror;
+    d.obase = seg->obase;
+    d.ldo = seg->ldo;
+    d.row0 = seg->row0;
+    d.col0 = seg->col0;
+    d.rrec0 = offsets[r_lo] + r_lo * kPad;
+    d.crec0 = offsets[c_lo] + c_lo * kPad;
+    d.rrecs = offsets[r_hi] + r_hi * kPad - d.rrec0;
+    d.crecs = offsets[c_hi] + c_hi * kPad - d.crec0;
+    const int64_t need = d.diag ? d.rrecs : d.rrecs + d.crecs;
+    d.global_mode = need > h.lds_records ? 1 : 0;
+}
+
+// Records each thread stages: 128 bytes, so that one pass moves a full LDS
+// record area (kLdsRecordBytes <= kThreads * 128).
+template <typename T>
+constexpr int stage_unroll() { return 128 / (int)sizeof(Rec<T>); }
+static_assert(kLdsRecordBytes <= kThreads * 128, "one staging pass per tile");
+
+// One thread's part of a tile's staging, held in registers between the
+// loads (issued early) and the LDS stores: up to stage_unroll() records and,
+// for threads [0, R) and [64, 64 + C), one PCF's offsets.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <typename T> struct RecVec;
+template <> struct RecVec<double> { typedef d2v type; };
+template <> struct RecVec<float> { typedef f2v type; };
+
+template <typename T>
+struct StageRegs {
+    typename RecVec<T>::type r[stage_unroll<T>()];
+    int64_t m0, m1;
+};
+
+// Loads of tile d's staging: its records (row block, then column block
+// unless diagonal; none in global mode) and the block metadata.
+template <typename T>
+__device__ __forceinline__ void stage_load(StageRegs<T> &g, const TileDesc &d,
+                                           const Rec<T> *grec,
+                                           const int64_t *offsets)
+{
+    typedef typename RecVec<T>::type V;
+    constexpr int U = stage_unroll<T>();
+    const int tid = threadIdx.x;
+    const int64_t rrecs = d.rrecs, rrec0 = d.rrec0, crec0 = d.crec0;
+    const int64_t total = d.global_mode ? 0 : (d.diag ? rrecs : rrecs + d.crecs);
+    if (total > 0) {
+        // unconditional loads (indices past the end read record 0 of the
+        // tile again), so that the values stay in registers; a tile's LDS
+        // records number less than 2^31, so 32-bit indices
+        const V *rbase = reinterpret_cast<const V *>(grec) + rrec0;
+        const V *cbase = reinterpret_cast<const V *>(grec) + (crec0 - rrecs);
+        const int32_t tot = (int32_t)total, nr = (int32_t)rrecs;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t q = tid + u * kThreads;
+            q = q < tot ? q : 0;
+            g.r[u] = (q < nr ? rbase : cbase)[q];
         }
     }
-    __syncthreads();
-    if (sh.tile >= h.ntiles)
-        return false;
-    const int32_t R = sh.R, C = sh.C, npairs = sh.npairs;
-    const bool diag = sh.diag != 0, gmode = sh.global_mode != 0;
-    const int64_t rrecs = sh.rrecs;
-
-    // block metadata: rows of each PCF and base of its records (LDS index,
-    // or global record index in global mode)
-    if (tid < R) {
-        const int64_t i = sh.r_lo + tid;
-        const int64_t roff = offsets[i] + i * kPad;
-        sh.rn[tid] = (int32_t)(offsets[i + 1] - offsets[i]);
-        sh.rb[tid] = (int32_t)(gmode ? roff : roff - sh.rrec0);
-    } else if (tid >= 64 && tid < 64 + C) {
-        const int c = tid - 64;
-        const int64_t j = sh.c_lo + c;
-        const int64_t roff = offsets[j] + j * kPad;
-        sh.cn[c] = (int32_t)(offsets[j + 1] - offsets[j]);
-        sh.cb[c] = (int32_t)(gmode ? roff
-                                   : (diag ? roff - sh.rrec0
-                                           : rrecs + (roff - sh.crec0)));
+    const bool mrow = tid < d.R;
+    const bool mcol = tid >= 64 && tid < 64 + d.C;
+    if (mrow || mcol) {
+        const int64_t i = mrow ? d.r_lo + tid : d.c_lo + (tid - 64);
+        g.m0 = offsets[i];
+        g.m1 = offsets[i + 1];
     }
-    // stage both blocks' records into LDS
-    if (!gmode) {
-        for (int64_t q = tid; q < rrecs; q += kThreads)
-            lrec[q] = grec[sh.rrec0 + q];
-        if (!diag)
-            for (int64_t q = tid; q < sh.crecs; q += kThreads)
-                lrec[rrecs + q] = grec[sh.crec0 + q];
-    }
-    __syncthreads();
+}
 
-    // padded step count of every pair, prefix-summed
+// LDS stores of tile d's staging (after stage_load on the same thread).
+template <typename T>
+__device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T> &g,
+                                            const TileDesc &d, Rec<T> *lrec)
+{
+    constexpr int U = stage_unroll<T>();
+    const int tid = threadIdx.x;
+    const int64_t rrecs = d.rrecs;
+    const int64_t total = d.global_mode ? 0 : (d.diag ? rrecs : rrecs + d.crecs);
+    typedef typename RecVec<T>::type V;
+    V *lv = reinterpret_cast<V *>(lrec);
+    const int32_t tot = (int32_t)total;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t q = tid + u * kThreads;
+        if (q < tot)
+            lv[q] = g.r[u];
+    }
+    const bool mrow = tid < d.R;
+    const bool mcol = tid >= 64 && tid < 64 + d.C;
+    if (mrow || mcol) {
+        const bool gmode = d.global_mode != 0;
+        const int64_t i = mrow ? d.r_lo + tid : d.c_lo + (tid - 64);
+        const int64_t roff = g.m0 + i * kPad;
+        const int32_t n = (int32_t)(g.m1 - g.m0);
+        if (mrow) {
+            sh.rn[tid] = n;
+            sh.rb[tid] = (int32_t)(gmode ? roff : roff - d.rrec0);
+        } else {
+            const int c = tid - 64;
+            sh.cn[c] = n;
+            sh.cb[c] = (int32_t)(gmode ? roff
+                                       : (d.diag ? roff - d.rrec0
+                                                 : rrecs + (roff - d.crec0)));
+        }
+    }
+}
+
+// Even split of a tile's steps over the kThreads lanes: a multiple of
+// kStepBlock (pair step counts are too, so a block of steps never straddles
+// two pairs), at least one block.
+__device__ __forceinline__ int64_t steps_per_lane(int64_t total)
+{
+    int64_t per = ((total + kThreads - 1) / kThreads + kStepBlock - 1) /
+                  kStepBlock * kStepBlock;
+    return per < kStepBlock ? kStepBlock : per;
+}
+
+// Padded step count of every pair of tile d, prefix-summed into sh.pw
+// (diagonal tiles give work to pairs r < c, and to r == c when `gram`);
+// the even split of the total over the kThreads lanes (sh.per, a multiple
+// of kStepBlock) and, for each lane, the pair holding its first step
+// (sh.pairof); the last value of every PCF of the tile (sh.rlast, clast),
+// read from `src` (the LDS records, or the packed records in global mode).
+// Needs the staged tile; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
+                                          int gram, const Rec<T> *src)
+{
+    const int tid = threadIdx.x;
+    if (tid < d.R)
+        sh.rlast[tid] = (double)src[sh.rb[tid] + sh.rn[tid] - 1].v;
+    else if (tid >= 64 && tid < 64 + d.C)
+        sh.clast[tid - 64] = (double)src[sh.cb[tid - 64] + sh.cn[tid - 64] - 1].v;
+    const int32_t C = d.C, npairs = d.R * d.C;
     int64_t wp = 0;
     if (tid < npairs) {
         const int r = tid / C, c = tid - (tid / C) * C;
         bool live = true;
-        if (diag)
+        if (d.diag)
             live = gram ? (r <= c) : (r < c);
         if (live) {
             const int64_t w = (int64_t)sh.rn[r] + sh.cn[c] - 2;
@@ -314,22 +404,95 @@ __device__ __forceinline__ bool tile_setup(TileShared &sh, Rec<T> *lrec,
     }
     int64_t total;
     const int64_t excl = block_scan(wp, sh.wsum, &total);
-    if (tid < npairs)
+    const int64_t per = steps_per_lane(total);
+    if (tid < npairs) {
         sh.pw[tid] = excl;
-    if (tid == 0)
+        // lanes whose first step l * per lies in [excl, excl + wp)
+        for (int64_t l = (excl + per - 1) / per; l * per < excl + wp; ++l)
+            sh.pairof[l] = tid;
+    }
+    if (tid == 0) {
         sh.pw[npairs] = total;
-    __syncthreads();
-    return true;
+        sh.npairs = npairs;
+        sh.per = per;
+    }
+    sync_lds();
 }
 
-// Even split of a tile's steps over 2 * kThreads virtual lanes (two merge
-// chains per lane); a multiple of kStepBlock, at least one block.
-__device__ __forceinline__ int64_t steps_per_virtual_lane(int64_t total)
-{
-    constexpr int kVirtual = 2 * kThreads;
-    int64_t per = ((total + kVirtual - 1) / kVirtual + kStepBlock - 1) /
-                  kStepBlock * kStepBlock;
-    return per < kStepBlock ? kStepBlock : per;
-}
+// Persistent tile loop of one workgroup over a ring of three tile
+// descriptors in sh.desc (current, next, after next). The queue lane takes
+// the ticket of the tile after next before the merge work of the current
+// tile and decodes it while the other lanes finish the current tile, so the
+// queue's latency stays off the critical path; the next tile (decoded one
+// tile earlier) is staged right after finishing. Per tile:
+//   scan -> take_next -> merge -> decode_next, finish -> stage_next -> advance
+struct TileLoop {
+    int cur = 0;
+    int64_t ticket = 0;
+
+    __device__ __forceinline__ int nxt() const { return cur == 2 ? 0 : cur + 1; }
+    __device__ __forceinline__ int aft() const { return cur == 0 ? 2 : cur - 1; }
+
+    // decode the first two tiles, stage the first one
+    template <typename T>
+    __device__ __forceinline__ void start(TileShared &sh, const unsigned char *ws,
+                                          const int64_t *offsets, Rec<T> *lrec,
+                                          const Rec<T> *grec)
+    {
+        if (threadIdx.x == kQueueLane) {
+            tile_decode(sh.desc[0], tile_ticket(ws), ws, offsets);
+            tile_decode(sh.desc[1], tile_ticket(ws), ws, offsets);
+        }
+        sync_lds();
+        if (sh.desc[0].tile < hdr_of(ws).ntiles) {
+            StageRegs<T> g;
+            stage_load<T>(g, sh.desc[0], grec, offsets);
+            stage_store<T>(sh, g, sh.desc[0], lrec);
+        }
+        sync_lds();
+    }
+    __device__ __forceinline__ bool live(const TileShared &sh,
+                                         const unsigned char *ws) const
+    {
+        return sh.desc[cur].tile < hdr_of(ws).ntiles;
+    }
+    // before the merge work of the current tile
+    __device__ __forceinline__ void take_next(const unsigned char *ws)
+    {
+        if (threadIdx.x == kQueueLane)
+            ticket = tile_ticket(ws);
+    }
+    // after the merge work (and its barrier), before finishing
+    __device__ __forceinline__ void decode_next(TileShared &sh,
+                                                const unsigned char *ws,
+                                                const int64_t *offsets)
+    {
+        if (threadIdx.x == kQueueLane)
+            tile_decode(sh.desc[aft()], ticket, ws, offsets);
+    }
+    // staging of the next tile, after finishing the current one; `barrier`
+    // when the finishing code reads records or block metadata (otherwise a
+    // wave stages as soon as its own finishing work is done)
+    template <typename T>
+    __device__ __forceinline__ void stage_next(TileShared &sh, const unsigned char *ws,
+                                               const Rec<T> *grec,
+                                               const int64_t *offsets,
+                                               Rec<T> *lrec, bool barrier) const
+    {
+        const TileDesc &n = sh.desc[nxt()];
+        if (n.tile >= hdr_of(ws).ntiles)
+            return;
+        if (barrier)
+            sync_lds();
+        StageRegs<T> g;
+        stage_load<T>(g, n, grec, offsets);
+        stage_store<T>(sh, g, n, lrec);
+    }
+    __device__ __forceinline__ void advance()
+    {
+        sync_lds();
+        cur = nxt();
+    }
+};
 
 }  // namespace pcf
