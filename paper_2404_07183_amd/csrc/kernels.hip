@@ -176,7 +176,8 @@ struct Chain {
     T x;          // start of the current cell
     double acc;   // sum over the current pair (FP64 for both types)
     int64_t left; // steps left in the current pair
-    int32_t k;    // current pair of the tile
+    int32_t r, c;            // current pair (row, column) of the tile
+    int32_t rb, rn, cb, cn;  // record base and rows of its two PCFs
 };
 
 template <typename T, int HK, typename Src>
@@ -195,6 +196,13 @@ __device__ __forceinline__ void chain_step(Chain<T, Src> &ch, T &part, T p)
     ch.P = *ch.pP;
 }
 
+// Padded merge steps of a pair of PCFs with na and nb rows (as in the scan).
+__device__ __forceinline__ int64_t pair_steps(int32_t na, int32_t nb)
+{
+    const int64_t w = (int64_t)na + nb - 2;
+    return (w + kStepBlock - 1) / kStepBlock * kStepBlock;
+}
+
 // Starting state at step d of pair k (merge-path split).
 template <typename T, typename Src, typename Shared>
 __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
@@ -202,17 +210,65 @@ __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
                                             int64_t d, int32_t C)
 {
     const int r = k / C, c = k - (k / C) * C;
+    ch.r = r;
+    ch.c = c;
+    ch.rb = sh.rb[r];
+    ch.rn = sh.rn[r];
+    ch.cb = sh.cb[c];
+    ch.cn = sh.cn[c];
     int32_t i0, j0;
     T x;
-    pair_start<T>(base, sh.rb[r], sh.rn[r], sh.cb[c], sh.cn[c], d, i0, j0, x);
+    pair_start<T>(base, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
     ch.pP = Src::at(base, i0);
     ch.pQ = Src::at(base, j0);
     ch.P = *ch.pP;
     ch.Q = *ch.pQ;
     ch.x = x;
     ch.acc = 0.0;
-    ch.left = sh.pw[k + 1] - sh.pw[k] - d;
-    ch.k = k;
+    ch.left = pair_steps(ch.rn, ch.cn) - d;
+}
+
+// Moves a chain that finished its pair to the next pair with steps, in the
+// tile's row-major pair order. Blocks of consecutive PCFs are contiguous in
+// the record arrays, so the next PCF's records start right after this one's
+// padding; only the next PCF's row count is read. On diagonal tiles a row's
+// live pairs start at column r + 1 (r with `gram`). The caller has steps
+// left, so a next pair with steps exists and the loop ends there.
+template <typename T, typename Src, typename Shared>
+__device__ __forceinline__ void chain_next_pair(Chain<T, Src> &ch, const Shared &sh,
+                                                const Rec<T> *base, int32_t C,
+                                                bool diag, int gram)
+{
+    int32_t r = ch.r, c = ch.c, rb = ch.rb, rn = ch.rn, cb = ch.cb, cn = ch.cn;
+    do {
+        if (c + 1 < C) {
+            cb += cn + kPad;
+            ++c;
+            cn = sh.cn[c];
+        } else {
+            // next row: a row holding a later pair with steps has a live
+            // first column below C
+            rb += rn + kPad;
+            ++r;
+            rn = sh.rn[r];
+            c = diag ? (gram ? r : r + 1) : 0;
+            cb = sh.cb[c];
+            cn = sh.cn[c];
+        }
+    } while (pair_steps(rn, cn) == 0);
+    ch.r = r;
+    ch.c = c;
+    ch.rb = rb;
+    ch.rn = rn;
+    ch.cb = cb;
+    ch.cn = cn;
+    ch.pP = Src::at(base, rb);
+    ch.pQ = Src::at(base, cb);
+    ch.P = *ch.pP;
+    ch.Q = *ch.pQ;
+    ch.x = T(0);
+    ch.acc = 0.0;
+    ch.left = pair_steps(rn, cn);
 }
 
 // This lane's share of the tile: steps [s, e) (e - s a multiple of
@@ -221,18 +277,16 @@ __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
 template <typename T, int HK, typename Src, typename Shared>
 __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
                                            int64_t s, int64_t e, int32_t k,
-                                           int32_t vl, int32_t C, T p)
+                                           int32_t vl, int32_t C, bool diag,
+                                           int gram, T p)
 {
     Chain<T, Src> ch;
     chain_begin(ch, sh, base, k, s - sh.pw[k], C);
     for (int64_t blk = (e - s) / kStepBlock; blk > 0; --blk) {
         if (ch.left == 0) {
-            // next pair with steps (a rare, divergent branch)
-            sh.part[ch.k + vl] = ch.acc;
-            int32_t kn = ch.k + 1;
-            while (kn < sh.npairs && sh.pw[kn + 1] == sh.pw[kn])
-                ++kn;
-            chain_begin(ch, sh, base, kn, 0, C);
+            // next pair (a rare, divergent branch)
+            sh.part[ch.r * C + ch.c + vl] = ch.acc;
+            chain_next_pair(ch, sh, base, C, diag, gram);
         }
         T part = T(0);
 #pragma unroll
@@ -241,7 +295,7 @@ __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
         ch.acc += (double)part;
         ch.left -= kStepBlock;
     }
-    sh.part[ch.k + vl] = ch.acc;
+    sh.part[ch.r * C + ch.c + vl] = ch.acc;
 }
 
 template <typename T, int HK>
@@ -276,9 +330,11 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         const int32_t k0 = s0 < e0 ? sh.pairof[tid] : 0;
         if (s0 < e0) {
             if (gmode)
-                lane_chain<T, HK, GlobalSrc<T>>(sh, grec, s0, e0, k0, tid, C, p);
+                lane_chain<T, HK, GlobalSrc<T>>(sh, grec, s0, e0, k0, tid, C,
+                                                diag, args.gram, p);
             else
-                lane_chain<T, HK, LdsSrc<T>>(sh, lrec, s0, e0, k0, tid, C, p);
+                lane_chain<T, HK, LdsSrc<T>>(sh, lrec, s0, e0, k0, tid, C,
+                                             diag, args.gram, p);
         }
         sync_lds();
         loop.decode_next(sh, ws, offsets);
