@@ -18,6 +18,9 @@
  *                 offsets[i] .. offsets[i+1]-1;
  *   t[P], v[P]    breakpoint times and values, both FP32 or both FP64,
  *                 P = offsets[n].
+ * Every PCF has between 1 and 2^30 - 1 rows; the planner rejects other row
+ * counts with PCF_EINVAL (an empty PCF, or one so long that a pair's merge
+ * could exceed 2^31 steps).
  * PCF i is f(x) = v[k] for t[k] <= x < t[k+1] (rows k of PCF i) and
  * v[last] after the last time (paper, Section 2; its n x 2 matrix [t; f]).
  * Contract (checked only under PCF_VALIDATE): every PCF has >= 1 row, its

@@ -198,7 +198,7 @@ pcf_status prepare(const pcf_set *X, const Plan *plan, void *ws,
 
 int tile_grid(const Plan *plan, bool reuse)
 {
-    int grid = device_cus();
+    int grid = device_cus() * kWgPerCu;
     if (!reuse && plan && plan->ntiles < grid)
         grid = (int)(plan->ntiles > 0 ? plan->ntiles : 1);
     return grid;

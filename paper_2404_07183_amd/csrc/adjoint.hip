@@ -139,6 +139,182 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
     sink_add_v(sb, ib, W * gvb);
 }
 
+// ---------------------------------------------------------------------------
+// The LDS adjoint chain: the forward chain's P/Q formulation (h symmetric,
+// P the piece loaded last, Q the other one, one full-wave record read per
+// step) with each piece's value-gradient accumulator. LDS record q and its
+// two gradient slots belong together, so the slot of a piece is its record
+// index and the chain never needs to know which PCF a piece belongs to.
+// Fixed parameters (t_0, the last value) and padding slots receive terms
+// too; the flush at the end of the tile drops them.
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+struct AdjChain {
+    d2 P, Q;               // (end time, value) of the two current pieces
+    int32_t iP, iQ;        // their record indices (= gradient slots)
+    double gP, gQ;         // value gradients of the two pieces so far
+    double x;              // start of the current cell
+    double W;              // weight of the current pair
+    int32_t left;          // steps left in the current pair
+    int32_t r, c, rb, rn, cb, cn;
+};
+
+__device__ __forceinline__ double adj_min(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double adj_max(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ int32_t adj_pair_steps(int32_t na, int32_t nb)
+{
+    return (na + nb - 2 + kStepBlock - 1) & ~(kStepBlock - 1);
+}
+
+template <int HK>
+__device__ __forceinline__ void adj_step(AdjChain &ch, const d2 *lv, double *lgt,
+                                         double *lgv, double p)
+{
+    const double tP = ch.P.x, tQ = ch.Q.x, vP = ch.P.y, vQ = ch.Q.y;
+    const double y = adj_min(tP, tQ);
+    const double w = y - ch.x;
+    ch.x = y;
+    ch.gP = fma(dhda<HK>(vP, vQ, p), w, ch.gP);
+    ch.gQ = fma(dhda<HK>(vQ, vP, p), w, ch.gQ);
+    const bool c = tP <= tQ;
+    // E: the piece that ends at y, O: the one that goes on
+    const int32_t iE = c ? ch.iP : ch.iQ, iO = c ? ch.iQ : ch.iP;
+    const double vE = c ? vP : vQ, vO = c ? vQ : vP;
+    const double gE = c ? ch.gP : ch.gQ, gO = c ? ch.gQ : ch.gP;
+    const double tO = adj_max(tP, tQ);
+    const d2 N = lv[iE + 1];
+    atomicAdd(&lgv[iE], ch.W * gE);
+    // time gradient of E's breakpoint y (slot iE + 1); a zero-width step is
+    // the second half of a tie, handled at the tie
+    if (w > 0.0) {
+        const double vN = N.y;
+        double dE;
+        if (tO == y) {
+            // O breaks at y too: mean of the one-sided derivatives, for both
+            const double vON = lv[iO + 1].y;
+            dE = 0.5 * (hval<double, HK>(vE, vON, p) - hval<double, HK>(vN, vON, p) +
+                        hval<double, HK>(vE, vO, p) - hval<double, HK>(vN, vO, p));
+            const double dO =
+                0.5 * (hval<double, HK>(vO, vN, p) - hval<double, HK>(vON, vN, p) +
+                       hval<double, HK>(vO, vE, p) - hval<double, HK>(vON, vE, p));
+            atomicAdd(&lgt[iO + 1], ch.W * dO);
+        } else {
+            dE = hval<double, HK>(vE, vO, p) - hval<double, HK>(vN, vO, p);
+        }
+        atomicAdd(&lgt[iE + 1], ch.W * dE);
+    }
+    ch.P = N;
+    ch.iP = iE + 1;
+    ch.gP = 0.0;
+    ch.Q.x = tO;
+    ch.Q.y = vO;
+    ch.iQ = iO;
+    ch.gQ = gO;
+}
+
+// Starting state at step d of pair k (merge-path split), weight from sh.part.
+__device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
+                                          const Rec<double> *lrec, int32_t k,
+                                          int64_t d, int32_t C)
+{
+    const d2 *lv = reinterpret_cast<const d2 *>(lrec);
+    const int r = k / C, c = k - (k / C) * C;
+    ch.r = r;
+    ch.c = c;
+    ch.rb = sh.rb[r];
+    ch.rn = sh.rn[r];
+    ch.cb = sh.cb[c];
+    ch.cn = sh.cn[c];
+    int32_t i0, j0;
+    double x;
+    pair_start<double>(lrec, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
+    ch.iP = i0;
+    ch.iQ = j0;
+    ch.P = lv[i0];
+    ch.Q = lv[j0];
+    ch.x = x;
+    ch.gP = 0.0;
+    ch.gQ = 0.0;
+    ch.W = sh.part[k];
+    ch.left = adj_pair_steps(ch.rn, ch.cn) - (int32_t)d;
+}
+
+// Next pair with steps (row-major pair order; see chain_next_pair of the
+// forward kernel).
+__device__ __forceinline__ void adj_next_pair(AdjChain &ch, const TileShared &sh,
+                                              const Rec<double> *lrec, int32_t C,
+                                              bool diag, int gram)
+{
+    const d2 *lv = reinterpret_cast<const d2 *>(lrec);
+    int32_t r = ch.r, c = ch.c, rb = ch.rb, rn = ch.rn, cb = ch.cb, cn = ch.cn;
+    do {
+        if (c + 1 < C) {
+            cb += cn + kPad;
+            ++c;
+            cn = sh.cn[c];
+        } else {
+            rb += rn + kPad;
+            ++r;
+            rn = sh.rn[r];
+            c = diag ? (gram ? r : r + 1) : 0;
+            cb = sh.cb[c];
+            cn = sh.cn[c];
+        }
+    } while (adj_pair_steps(rn, cn) == 0);
+    ch.r = r;
+    ch.c = c;
+    ch.rb = rb;
+    ch.rn = rn;
+    ch.cb = cb;
+    ch.cn = cn;
+    ch.iP = rb;
+    ch.iQ = cb;
+    ch.P = lv[rb];
+    ch.Q = lv[cb];
+    ch.x = 0.0;
+    ch.gP = 0.0;
+    ch.gQ = 0.0;
+    ch.W = sh.part[r * C + c];
+    ch.left = adj_pair_steps(rn, cn);
+}
+
+template <int HK>
+__device__ __forceinline__ void adj_lane_chain(const TileShared &sh,
+                                               const Rec<double> *lrec, double *lgt,
+                                               double *lgv, int64_t s, int64_t e,
+                                               int32_t k, int32_t C, bool diag,
+                                               int gram, double p)
+{
+    const d2 *lv = reinterpret_cast<const d2 *>(lrec);
+    AdjChain ch;
+    adj_begin(ch, sh, lrec, k, s - sh.pw[k], C);
+    for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
+        if (ch.left == 0) {
+            atomicAdd(&lgv[ch.iP], ch.W * ch.gP);
+            atomicAdd(&lgv[ch.iQ], ch.W * ch.gQ);
+            adj_next_pair(ch, sh, lrec, C, diag, gram);
+        }
+#pragma unroll
+        for (int u = 0; u < kStepBlock; ++u)
+            adj_step<HK>(ch, lv, lgt, lgv, p);
+        ch.left -= kStepBlock;
+    }
+    // the pieces going on past this run: their gradients so far
+    atomicAdd(&lgv[ch.iP], ch.W * ch.gP);
+    atomicAdd(&lgv[ch.iQ], ch.W * ch.gQ);
+}
+
 template <int HK>
 __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
 {
@@ -162,7 +338,6 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         const int32_t R = D.R, C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = sh.pw[npairs];
-        const int64_t per = sh.per;
         const int64_t nslots = diag ? D.rrecs : D.rrecs + D.crecs;
         if (!gmode)
             for (int64_t q = tid; q < 2 * nslots; q += kThreads)
@@ -187,10 +362,13 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         sync_lds();
         loop.take_next(args.ws);
 
-        // this lane's share: steps [tid * per, (tid + 1) * per)
-        int64_t s = (int64_t)tid * per;
-        const int64_t e = (s + per < total) ? s + per : total;
-        if (s < e) {
+        // this lane's share of the tile's steps
+        int64_t s, e;
+        lane_steps(sh, tid, total, s, e);
+        if (s < e && !gmode) {
+            adj_lane_chain<HK>(sh, lrec, lg, lg + nslots, s, e, sh.pairof[tid], C,
+                               diag, args.gram, p);
+        } else if (s < e) {
             int32_t k = sh.pairof[tid];
             int64_t d = s - sh.pw[k];
             while (s < e) {

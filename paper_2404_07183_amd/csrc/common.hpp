@@ -15,13 +15,18 @@ constexpr int kStepBlock = 8;
 constexpr int kPad = kStepBlock - 1;
 // Threads per tile workgroup (16 waves of 64 lanes).
 constexpr int kThreads = 1024;
+// Tile workgroups resident per CU (they share its 160 KiB of LDS).
+constexpr int kWgPerCu = 1;
 // Most PCFs in one block (so a tile has at most kThreads pairs).
 constexpr int kMaxBlock = 32;
 constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
-// LDS bytes a tile may use for breakpoint records (of 160 KiB per
-// workgroup on gfx950; the rest holds per-pair prefix sums, accumulators
-// and block metadata).
+// LDS bytes a tile may use for breakpoint records (of 160 KiB per CU on
+// gfx950; the rest holds per-pair prefix sums, accumulators and block
+// metadata).
 constexpr int kLdsRecordBytes = 128 * 1024;
+
+// Rows a PCF may have (exclusive): keeps a pair's merge steps below 2^31.
+constexpr int64_t kMaxRows = (int64_t)1 << 30;
 // Number of hardware XCDs (each with its own L2) on MI355X.
 constexpr int kXcds = 8;
 

@@ -23,8 +23,9 @@
 //    time does not depend on the order, so the shares fit together.
 //  * Tiles and LDS. A workgroup takes a tile (row block x column block) from
 //    a persistent queue, copies both blocks' records into LDS and splits the
-//    tile's total step count evenly over its 1024 lanes, one contiguous run
-//    of steps per lane. A run may start inside a pair: its starting
+//    tile's total step count over its 1024 lanes, one contiguous run of
+//    steps per lane, longer runs for the waves the SIMDs issue first (see
+//    LaneSplit). A run may start inside a pair: its starting
 //    pointers come from a merge-path binary search on the pair's diagonal,
 //    and partial sums of one pair meet in LDS slots, added in lane order
 //    (deterministic). No lane waits for a longer pair, whatever the length
@@ -175,7 +176,7 @@ struct Chain {
     typename Src::ptr pP, pQ;
     T x;          // start of the current cell
     double acc;   // sum over the current pair (FP64 for both types)
-    int64_t left; // steps left in the current pair
+    int32_t left; // steps left in the current pair (rows < 2^30 per PCF)
     int32_t r, c;            // current pair (row, column) of the tile
     int32_t rb, rn, cb, cn;  // record base and rows of its two PCFs
 };
@@ -196,11 +197,11 @@ __device__ __forceinline__ void chain_step(Chain<T, Src> &ch, T &part, T p)
     ch.P = *ch.pP;
 }
 
-// Padded merge steps of a pair of PCFs with na and nb rows (as in the scan).
-__device__ __forceinline__ int64_t pair_steps(int32_t na, int32_t nb)
+// Padded merge steps of a pair of PCFs with na and nb rows (as in the scan;
+// below 2^31 since the planner admits fewer than 2^30 rows per PCF).
+__device__ __forceinline__ int32_t pair_steps(int32_t na, int32_t nb)
 {
-    const int64_t w = (int64_t)na + nb - 2;
-    return (w + kStepBlock - 1) / kStepBlock * kStepBlock;
+    return (na + nb - 2 + kStepBlock - 1) & ~(kStepBlock - 1);
 }
 
 // Starting state at step d of pair k (merge-path split).
@@ -225,7 +226,7 @@ __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
     ch.Q = *ch.pQ;
     ch.x = x;
     ch.acc = 0.0;
-    ch.left = pair_steps(ch.rn, ch.cn) - d;
+    ch.left = pair_steps(ch.rn, ch.cn) - (int32_t)d;
 }
 
 // Moves a chain that finished its pair to the next pair with steps, in the
@@ -281,12 +282,19 @@ __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
                                            int gram, T p)
 {
     Chain<T, Src> ch;
-    chain_begin(ch, sh, base, k, s - sh.pw[k], C);
-    for (int64_t blk = (e - s) / kStepBlock; blk > 0; --blk) {
+    const int64_t d0 = s - sh.pw[k];
+    chain_begin(ch, sh, base, k, d0, C);
+    // the lanes holding a pair's first and last step, for the finishing code
+    if (d0 == 0)
+        sh.plo[k] = (int16_t)vl;
+    for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
         if (ch.left == 0) {
             // next pair (a rare, divergent branch)
-            sh.part[ch.r * C + ch.c + vl] = ch.acc;
+            const int32_t kd = ch.r * C + ch.c;
+            sh.part[kd + vl] = ch.acc;
+            sh.phi[kd] = (int16_t)vl;
             chain_next_pair(ch, sh, base, C, diag, gram);
+            sh.plo[ch.r * C + ch.c] = (int16_t)vl;
         }
         T part = T(0);
 #pragma unroll
@@ -295,10 +303,13 @@ __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
         ch.acc += (double)part;
         ch.left -= kStepBlock;
     }
-    sh.part[ch.r * C + ch.c + vl] = ch.acc;
+    const int32_t kd = ch.r * C + ch.c;
+    sh.part[kd + vl] = ch.acc;
+    if (ch.left == 0)
+        sh.phi[kd] = (int16_t)vl;
 }
 
-template <typename T, int HK>
+template <typename T, int HK, int RT>
 __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -318,15 +329,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
         tile_scan<T>(sh, D, args.gram, gmode ? grec : lrec);
-        const int32_t R = D.R, C = D.C, npairs = sh.npairs;
+        const int32_t C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = sh.pw[npairs];
-        const int64_t per = sh.per;
 
         loop.take_next(ws);
-        // this lane's share: steps [tid * per, (tid + 1) * per)
-        const int64_t s0 = (int64_t)tid * per;
-        const int64_t e0 = (s0 + per < total) ? s0 + per : total;
+        // this lane's share of the tile's steps
+        int64_t s0, e0;
+        lane_steps(sh, tid, total, s0, e0);
         const int32_t k0 = s0 < e0 ? sh.pairof[tid] : 0;
         if (s0 < e0) {
             if (gmode)
@@ -338,6 +348,12 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         }
         sync_lds();
         loop.decode_next(sh, ws, offsets);
+        // the next tile's staging loads fly while this tile is finished
+        // (finishing reads neither records nor block metadata)
+        const bool has_next = loop.has_next(sh, ws);
+        StageRegs<T> next;
+        if (has_next)
+            stage_load<T>(next, sh.desc[loop.nxt()], grec, offsets);
 
         // finish: unbounded-tail rule, root; write (i, j) row-major
         for (int k = tid; k < npairs; k += kThreads) {
@@ -348,8 +364,8 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
             double val = 0.0;
             if (b1 > b0) {
                 // the pair's partial sums in lane order, loads batched
-                int64_t l = b0 / per;
-                const int64_t l1 = (b1 - 1) / per;
+                int32_t l = sh.plo[k];
+                const int32_t l1 = sh.phi[k];
                 for (; l + 3 <= l1; l += 4) {
                     const double q0 = sh.part[k + l], q1 = sh.part[k + l + 1];
                     const double q2 = sh.part[k + l + 2], q3 = sh.part[k + l + 3];
@@ -361,28 +377,17 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
             const T ht = hval<T, HK>((T)sh.rlast[r], (T)sh.clast[c], p);
             if (ht != T(0))
                 val = ht > T(0) ? INFINITY : -INFINITY;
-            if (args.root == kRootSqrt)
+            if constexpr (RT == kRootSqrt)
                 val = sqrt(val);
-            else if (args.root == kRootPow)
+            else if constexpr (RT == kRootPow)
                 val = pow(val, args.inv_p);
-            sh.part[k + b0 / per] = val;
             const int64_t i = D.r_lo + r, j = D.c_lo + c;
             out[D.obase + (i - D.row0) * D.ldo + (j - D.col0)] = (T)val;
-        }
-        if (D.mirror) {
-            sync_lds();
-            for (int q = tid; q < npairs; q += kThreads) {
-                const int c = q / R, r = q - (q / R) * R;
-                if (diag && r >= c)
-                    continue;
-                const int kk = r * C + c;
-                const double val = sh.part[kk + sh.pw[kk] / per];
-                const int64_t i = D.r_lo + r, j = D.c_lo + c;
+            if (D.mirror && !(diag && r == c))
                 out[D.obase + (j - D.row0) * D.ldo + (i - D.col0)] = (T)val;
-            }
         }
-        // (finishing reads neither records nor block metadata)
-        loop.stage_next<T>(sh, ws, grec, offsets, lrec, false);
+        if (has_next)
+            stage_store<T>(sh, next, sh.desc[loop.nxt()], lrec);
         loop.advance();
     }
 }
@@ -432,42 +437,47 @@ hipError_t launch_reset(unsigned char *ws, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int HK>
+template <typename T, int HK, int RT>
 static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
 {
     const size_t shm = tile_shared_bytes((int)sizeof(Rec<T>), false);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&pairwise_tiles<T, HK>),
+            reinterpret_cast<const void *>(&pairwise_tiles<T, HK, RT>),
             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess)
             return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((pairwise_tiles<T, HK>), dim3(grid), dim3(kThreads), shm,
-                       s, a);
+    hipLaunchKernelGGL((pairwise_tiles<T, HK, RT>), dim3(grid), dim3(kThreads),
+                       shm, s, a);
     return hipGetLastError();
+}
+
+// The (h, root) combinations the entry points use: |a-b| and ab without a
+// root, (a-b)^2 with or without sqrt, |a-b|^p with or without the p-th root.
+template <typename T>
+static hipError_t launch_fwd_dtype(int hk, const FwdArgs &a, int grid,
+                                   hipStream_t s)
+{
+    switch (hk) {
+    case kAbs: return launch_fwd_t<T, kAbs, kRootNone>(a, grid, s);
+    case kProd: return launch_fwd_t<T, kProd, kRootNone>(a, grid, s);
+    case kSqr:
+        return a.root == kRootSqrt ? launch_fwd_t<T, kSqr, kRootSqrt>(a, grid, s)
+                                   : launch_fwd_t<T, kSqr, kRootNone>(a, grid, s);
+    default:
+        return a.root == kRootPow ? launch_fwd_t<T, kPow, kRootPow>(a, grid, s)
+                                  : launch_fwd_t<T, kPow, kRootNone>(a, grid, s);
+    }
 }
 
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s)
 {
-    if (f64) {
-        switch (hk) {
-        case kAbs: return launch_fwd_t<double, kAbs>(a, grid, s);
-        case kSqr: return launch_fwd_t<double, kSqr>(a, grid, s);
-        case kProd: return launch_fwd_t<double, kProd>(a, grid, s);
-        default: return launch_fwd_t<double, kPow>(a, grid, s);
-        }
-    } else {
-        switch (hk) {
-        case kAbs: return launch_fwd_t<float, kAbs>(a, grid, s);
-        case kSqr: return launch_fwd_t<float, kSqr>(a, grid, s);
-        case kProd: return launch_fwd_t<float, kProd>(a, grid, s);
-        default: return launch_fwd_t<float, kPow>(a, grid, s);
-        }
-    }
+    return f64 ? launch_fwd_dtype<double>(hk, a, grid, s)
+               : launch_fwd_dtype<float>(hk, a, grid, s);
 }
 
 template hipError_t launch_pack<float>(const int64_t *, int64_t, const void *,

@@ -77,6 +77,10 @@ bool check_offsets(int64_t n, const int64_t *offsets, std::string &err)
                   " has no rows (every PCF needs at least one row)";
             return false;
         }
+        if (offsets[i + 1] - offsets[i] >= kMaxRows) {
+            err = "PCF " + std::to_string(i) + " has 2^30 rows or more";
+            return false;
+        }
     }
     return true;
 }

@@ -86,19 +86,22 @@ struct TileShared {
     // goes to slot k + pw[k] / per, also unique per pair, zero-step pairs
     // included.
     double part[kMaxPairs + kThreads];
-    int32_t pairof[kThreads];  // pair holding the first step of each lane
+    int16_t pairof[kThreads];  // pair holding the first step of each lane
+    int16_t plo[kMaxPairs], phi[kMaxPairs];  // lanes of a pair's first/last step
+                                             // (written by the merge chains)
     int32_t rn[kMaxBlock], rb[kMaxBlock];  // row PCF rows / record base
     int32_t cn[kMaxBlock], cb[kMaxBlock];  // column PCF rows / record base
     double rlast[kMaxBlock], clast[kMaxBlock];  // last values (tail rule)
     int64_t wsum[kThreads / 64];
     TileDesc desc[3];  // ring of tile descriptors (see TileLoop)
-    int64_t per;       // steps per lane of the current tile
+    int64_t gper[4];   // steps per lane of each wave group (see LaneSplit)
+    int64_t gbase[5];  // first step of each wave group
     int32_t npairs;
 };
 
 constexpr int kSharedHead = (int)((sizeof(TileShared) + 255) / 256 * 256);
-static_assert(kSharedHead + kLdsRecordBytes <= 160 * 1024,
-              "tile LDS must fit the 160 KiB a gfx950 workgroup can have");
+static_assert(kSharedHead + kLdsRecordBytes <= 160 * 1024 / kWgPerCu,
+              "the tile workgroups of a CU must fit its 160 KiB of LDS");
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS
 // operations, not for its global stores (no thread of the workgroup reads
@@ -364,21 +367,82 @@ __device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T> &
     }
 }
 
-// Even split of a tile's steps over the kThreads lanes: a multiple of
-// kStepBlock (pair step counts are too, so a block of steps never straddles
-// two pairs), at least one block.
-__device__ __forceinline__ int64_t steps_per_lane(int64_t total)
+// Split of a tile's steps over its lanes. The waves of a workgroup form four
+// age groups (waves 4g..4g+3, one per SIMD); each SIMD issues the older of
+// its waves first, so equal runs would leave the youngest group finishing
+// last while the others wait. Group g's lanes get runs in proportion to
+// kGroupWeight[g] (their measured issue share), so that all groups finish
+// together. Runs are multiples of kStepBlock (pair step counts are too, so a
+// block never straddles two pairs) and lie in [gbase[g], gbase[g + 1]) for
+// group g, lane by lane; the last runs of the tile may be short or empty.
+constexpr int kGroups = kThreads / 256;
+constexpr int kGroupLanes = 256;
+// Weights measured on MI355X (per-wave completion times of equal runs):
+// FP64 records, FP32 records.
+constexpr int64_t kGroupWeights[2][4] = {{64, 62, 58, 52}, {64, 60, 54, 46}};
+template <typename T>
+__device__ __forceinline__ int64_t group_weight(int g)
 {
-    int64_t per = ((total + kThreads - 1) / kThreads + kStepBlock - 1) /
-                  kStepBlock * kStepBlock;
-    return per < kStepBlock ? kStepBlock : per;
+    return kGroupWeights[sizeof(T) == 4][g];
 }
+template <typename T>
+constexpr int64_t weight_sum()
+{
+    int64_t w = 0;
+    for (int g = 0; g < kGroups; ++g)
+        w += kGroupWeights[sizeof(T) == 4][g];
+    return w;
+}
+
+template <typename T>
+struct LaneSplit {
+    int64_t per[kGroups], base[kGroups + 1];
+
+    __device__ __forceinline__ void make(int64_t total)
+    {
+        // groups before the last: their share rounded down to whole blocks;
+        // the last group takes the rest (rounded up)
+        constexpr int64_t kUnit = kGroupLanes * weight_sum<T>();
+        base[0] = 0;
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+            int64_t p;
+            if (g + 1 < kGroups) {
+                p = total * group_weight<T>(g) / kUnit / kStepBlock * kStepBlock;
+            } else {
+                const int64_t rest = total - base[g];
+                p = ((rest > 0 ? rest : 0) + kGroupLanes - 1) / kGroupLanes;
+                p = (p + kStepBlock - 1) / kStepBlock * kStepBlock;
+            }
+            per[g] = p < kStepBlock ? kStepBlock : p;
+            base[g + 1] = base[g] + kGroupLanes * per[g];
+        }
+    }
+    // a / b for 0 <= a, 0 < b, in 32 bits when both fit
+    __device__ __forceinline__ static int32_t quot(int64_t a, int64_t b)
+    {
+        if (a < ((int64_t)1 << 31) && b < ((int64_t)1 << 31))
+            return (int32_t)((uint32_t)a / (uint32_t)b);
+        return (int32_t)(a / b);
+    }
+};
+
+// Steps [s, e) of lane `lane` (e <= s when it has none).
+__device__ __forceinline__ void lane_steps(const TileShared &sh, int lane,
+                                           int64_t total, int64_t &s, int64_t &e)
+{
+    const int g = lane / kGroupLanes;
+    s = sh.gbase[g] + (int64_t)(lane - g * kGroupLanes) * sh.gper[g];
+    e = s + sh.gper[g];
+    e = e < total ? e : total;
+}
+
 
 // Padded step count of every pair of tile d, prefix-summed into sh.pw
 // (diagonal tiles give work to pairs r < c, and to r == c when `gram`);
-// the even split of the total over the kThreads lanes (sh.per, a multiple
-// of kStepBlock) and, for each lane, the pair holding its first step
-// (sh.pairof); the last value of every PCF of the tile (sh.rlast, clast),
+// the split of the total over the lanes (sh.gper, sh.gbase: LaneSplit) and,
+// for each lane, the pair holding its first step (sh.pairof); the last value
+// of every PCF of the tile (sh.rlast, clast),
 // read from `src` (the LDS records, or the packed records in global mode).
 // Needs the staged tile; ends with a barrier.
 template <typename T>
@@ -404,17 +468,31 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
     }
     int64_t total;
     const int64_t excl = block_scan(wp, sh.wsum, &total);
-    const int64_t per = steps_per_lane(total);
+    LaneSplit<T> sp;
+    sp.make(total);
     if (tid < npairs) {
         sh.pw[tid] = excl;
-        // lanes whose first step l * per lies in [excl, excl + wp)
-        for (int64_t l = (excl + per - 1) / per; l * per < excl + wp; ++l)
-            sh.pairof[l] = tid;
+        // lanes whose first step lies in [excl, excl + wp)
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+            const int64_t lo = excl > sp.base[g] ? excl : sp.base[g];
+            const int64_t hi = excl + wp < sp.base[g + 1] ? excl + wp : sp.base[g + 1];
+            if (lo < hi) {
+                for (int64_t j = LaneSplit<T>::quot(lo - sp.base[g] + sp.per[g] - 1, sp.per[g]);
+                     sp.base[g] + j * sp.per[g] < hi; ++j)
+                    sh.pairof[g * kGroupLanes + j] = (int16_t)tid;
+            }
+        }
     }
     if (tid == 0) {
         sh.pw[npairs] = total;
         sh.npairs = npairs;
-        sh.per = per;
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+            sh.gper[g] = sp.per[g];
+            sh.gbase[g] = sp.base[g];
+        }
+        sh.gbase[kGroups] = sp.base[kGroups];
     }
     sync_lds();
 }
@@ -469,6 +547,12 @@ struct TileLoop {
     {
         if (threadIdx.x == kQueueLane)
             tile_decode(sh.desc[aft()], ticket, ws, offsets);
+    }
+    // whether there is a next tile (its descriptor, decoded one tile ago)
+    __device__ __forceinline__ bool has_next(const TileShared &sh,
+                                             const unsigned char *ws) const
+    {
+        return sh.desc[nxt()].tile < hdr_of(ws).ntiles;
     }
     // staging of the next tile, after finishing the current one; `barrier`
     // when the finishing code reads records or block metadata (otherwise a

@@ -104,3 +104,14 @@ def test_planner_rejects_empty_pcf():
     with pytest.raises(_lib.PcfError) as e:
         _inspect(o)
     assert "no rows" in str(e.value)
+
+
+def test_planner_rejects_pcf_with_2_pow_30_rows():
+    # only the offsets are read: a PCF of 2^30 rows is refused (a pair's
+    # merge steps must stay below 2^31), one row fewer is accepted
+    o = np.array([0, 3, 3 + (1 << 30)], dtype=np.int64)
+    with pytest.raises(_lib.PcfError) as e:
+        _inspect(o)
+    assert "2^30" in str(e.value)
+    nb, ns, nt, blocks = _inspect(np.array([0, 3, 2 + (1 << 30)], dtype=np.int64))
+    assert nt >= 1
