@@ -111,16 +111,17 @@ __device__ __forceinline__ void sync_lds()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Exclusive block-wide scan of one int64 per thread; returns the exclusive
-// prefix and writes the total to *total (all threads).
-__device__ __forceinline__ int64_t block_scan(int64_t x, int64_t *wsum,
-                                              int64_t *total)
+// Exclusive block-wide scan of one integer per thread; returns the exclusive
+// prefix and the block total. Two barriers. `wsum` holds kThreads / 64
+// values of type I.
+template <typename I>
+__device__ __forceinline__ I block_scan(I x, I *wsum, I *total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t inc = x;
+    I inc = x;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        int64_t y = __shfl_up(inc, o, 64);
+        const I y = __shfl_up(inc, o, 64);
         if (lane >= o)
             inc += y;
     }
@@ -128,18 +129,18 @@ __device__ __forceinline__ int64_t block_scan(int64_t x, int64_t *wsum,
         wsum[wave] = inc;
     sync_lds();
     if (wave == 0) {
-        int64_t s = (lane < kThreads / 64) ? wsum[lane] : 0;
+        I v = (lane < kThreads / 64) ? wsum[lane] : I(0);
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            int64_t y = __shfl_up(s, o, 64);
+            const I y = __shfl_up(v, o, 64);
             if (lane >= o)
-                s += y;
+                v += y;
         }
         if (lane < kThreads / 64)
-            wsum[lane] = s;  // inclusive over waves
+            wsum[lane] = v;  // inclusive over waves
     }
     sync_lds();
-    const int64_t before = (wave > 0 ? wsum[wave - 1] : 0);
+    const I before = (wave > 0 ? wsum[wave - 1] : I(0));
     *total = wsum[kThreads / 64 - 1];
     return before + inc - x;
 }
@@ -183,13 +184,14 @@ __device__ __forceinline__ void locate_tile(const WsHeader &h,
 // indices of the two PCFs' first records in `src`; na, nb their row counts.
 template <typename T, typename Src>
 __device__ __forceinline__ int32_t merge_path(Src src, int32_t A, int32_t na,
-                                              int32_t B, int32_t nb, int64_t d)
+                                              int32_t B, int32_t nb, int32_t d)
 {
-    int64_t lo = d - (nb - 1);
+    // 32-bit: d is below a pair's step count, which stays below 2^31
+    int32_t lo = d - (nb - 1);
     lo = lo < 0 ? 0 : lo;
-    int64_t hi = d < (na - 1) ? d : (na - 1);
+    int32_t hi = d < (na - 1) ? d : (na - 1);
     while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
+        const int32_t mid = (lo + hi) >> 1;
         const T ta = src[A + mid].t;          // breakpoint mid+1 of the row PCF
         const T tb = src[B + (d - 1 - mid)].t;  // breakpoint d-mid of the column
         if (ta <= tb)
@@ -197,7 +199,7 @@ __device__ __forceinline__ int32_t merge_path(Src src, int32_t A, int32_t na,
         else
             hi = mid;
     }
-    return (int32_t)lo;
+    return lo;
 }
 
 typedef __attribute__((address_space(3))) unsigned char lds_byte;
@@ -217,8 +219,8 @@ __device__ __forceinline__ void pair_start(Src src, int32_t A, int32_t na,
     ib = B;
     x = T(0);
     if (d > 0) {
-        const int32_t i = merge_path<T>(src, A, na, B, nb, d);
-        const int32_t j = (int32_t)(d - i);
+        const int32_t i = merge_path<T>(src, A, na, B, nb, (int32_t)d);
+        const int32_t j = (int32_t)d - i;
         const T xa = (i > 0) ? src[A + i - 1].t : T(0);
         const T xb = (j > 0) ? src[B + j - 1].t : T(0);
         x = xa > xb ? xa : xb;
@@ -466,8 +468,17 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
             wp = (w + kStepBlock - 1) / kStepBlock * kStepBlock;
         }
     }
-    int64_t total;
-    const int64_t excl = block_scan(wp, sh.wsum, &total);
+    // 32-bit scan when the tile's step total certainly fits (LDS tiles)
+    int64_t total, excl;
+    const int64_t bound = (int64_t)C * d.rrecs + (int64_t)d.R * d.crecs +
+                          (int64_t)kStepBlock * npairs;
+    if (bound < ((int64_t)1 << 31)) {
+        int32_t t32;
+        excl = block_scan<int32_t>((int32_t)wp, reinterpret_cast<int32_t *>(sh.wsum), &t32);
+        total = t32;
+    } else {
+        excl = block_scan<int64_t>(wp, sh.wsum, &total);
+    }
     LaneSplit<T> sp;
     sp.make(total);
     if (tid < npairs) {
