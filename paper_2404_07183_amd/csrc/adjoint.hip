@@ -415,15 +415,20 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 const int64_t lq = in_rows ? q : q - D.rrecs;
                 const int64_t rec = base + lq;           // global record index
                 // PCF of this record: the block's PCF whose record range
-                // holds it (blocks are short: linear scan over <= 32)
+                // holds it
                 const int32_t nb = in_rows ? R : C;
                 const int32_t *bs = in_rows ? sh.rb : sh.cb;
                 const int32_t *ns = in_rows ? sh.rn : sh.cn;
                 const int64_t pcf0 = in_rows ? D.r_lo : D.c_lo;
-                int32_t which = 0;
-                for (int32_t u = 1; u < nb; ++u)
-                    if (bs[u] <= q)
-                        which = u;
+                // last PCF of the block whose records start at or before q
+                int32_t which = 0, hi = nb - 1;
+                while (which < hi) {
+                    const int32_t mid = (which + hi + 1) >> 1;
+                    if (bs[mid] <= q)
+                        which = mid;
+                    else
+                        hi = mid - 1;
+                }
                 const int64_t kk = q - bs[which];  // record within the PCF
                 if (kk >= ns[which])
                     continue;                      // padding

@@ -402,15 +402,16 @@ struct LaneSplit {
 
     __device__ __forceinline__ void make(int64_t total)
     {
-        // groups before the last: their share rounded down to whole blocks;
-        // the last group takes the rest (rounded up)
+        // groups before the last: their share rounded to whole blocks; the
+        // last group takes the rest (rounded up)
         constexpr int64_t kUnit = kGroupLanes * weight_sum<T>();
         base[0] = 0;
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
             int64_t p;
             if (g + 1 < kGroups) {
-                p = total * group_weight<T>(g) / kUnit / kStepBlock * kStepBlock;
+                p = (total * group_weight<T>(g) + kUnit * kStepBlock / 2) /
+                    (kUnit * kStepBlock) * kStepBlock;
             } else {
                 const int64_t rest = total - base[g];
                 p = ((rest > 0 ? rest : 0) + kGroupLanes - 1) / kGroupLanes;
