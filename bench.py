@@ -73,7 +73,8 @@ def merge_steps_full(o):
 def cpu_baseline(o, t, v, kind_name, seconds=12.0, seed=123):
     """The oracle, as it stands, on random pairs of the same workload, run on
     all host cores (one thread per core; each ctypes call releases the GIL).
-    Returns pairs/s, the number of pairs timed and the thread count."""
+    Returns pairs/s, the number of pairs timed, the thread count, the wall
+    time, and the pairs with their oracle values and sums of |h|·width."""
     import concurrent.futures as cf
 
     import oracle
@@ -94,9 +95,12 @@ def cpu_baseline(o, t, v, kind_name, seconds=12.0, seed=123):
     parts = [(I[k * chunk:(k + 1) * chunk], J[k * chunk:(k + 1) * chunk]) for k in range(cores)]
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(lambda ij: oracle.entries(kind, p, o, t, v, ij[0], ij[1]), parts))
+        got = list(ex.map(lambda ij: oracle.entries(kind, p, o, t, v, ij[0], ij[1],
+                                                    with_abs=True), parts))
     dt = time.perf_counter() - t0
-    return len(I) / dt, len(I), cores, dt
+    ref = np.concatenate([g[0] for g in got])
+    ab = np.concatenate([g[1] for g in got])
+    return len(I) / dt, len(I), cores, dt, (I, J, ref, ab)
 
 
 def run_plain(args):
@@ -177,11 +181,21 @@ def run_plain(args):
         },
     }
     if not args.no_cpu:
-        pps, npairs, cores, dt = cpu_baseline(o, t, v, args.kind)
+        pps, npairs, cores, dt, (I, J, ref, ab) = cpu_baseline(o, t, v, args.kind)
         res["cpu_baseline"] = {"value": pps, "unit": "pairs/s", "cores": cores,
                                "kind": "oracle",
                                "sample": "%d random pairs of the same workload, %.1f s on %d "
                                          "host threads" % (npairs, dt, cores)}
+        # the same pairs of the benchmarked matrix against the oracle: error
+        # over the scale sum |h|·width (its p-th root for d_p)
+        got = out[torch.as_tensor(I, device="cuda:0"),
+                  torch.as_tensor(J, device="cuda:0")].double().cpu().numpy()
+        root = {"l1": 1.0, "l2": 2.0, "l2sq": 1.0, "gram": 1.0}[args.kind]
+        scale = np.maximum(ab, 1e-300) ** (1.0 / root)
+        err = np.abs(got - ref) / scale
+        res["parity"] = {"pairs": int(len(I)), "max_error_over_scale": float(err.max()),
+                         "tolerance": 1e-12 if args.dtype == "f64" else 1e-5,
+                         "reference": "oracle on the cpu_baseline pairs"}
     return res
 
 
