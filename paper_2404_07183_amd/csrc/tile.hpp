@@ -145,6 +145,36 @@ __device__ __forceinline__ I block_scan(I x, I *wsum, I *total)
     return before + inc - x;
 }
 
+// The 32-bit scan: the wave's inclusive scan with DPP row shifts (1, 2, 4, 8
+// within rows of 16 lanes) and row broadcasts (lane 15 into the next row,
+// lane 31 into rows 2 and 3), lanes without a source adding 0; then one
+// barrier, after which every wave adds the totals of the waves before it.
+template <>
+__device__ __forceinline__ int32_t block_scan<int32_t>(int32_t x, int32_t *wsum,
+                                                       int32_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t v = x;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    if (lane == 63)
+        wsum[wave] = v;
+    sync_lds();
+    int32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        const int32_t t = wsum[w];
+        before += w < wave ? t : 0;
+        tot += t;
+    }
+    *total = tot;
+    return before + v - x;
+}
+
 // Decode a tile index into (segment, I, J); thread 0 only.
 __device__ __forceinline__ void locate_tile(const WsHeader &h,
                                             const unsigned char *ws,
