@@ -409,20 +409,20 @@ __device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T> &
 // group g, lane by lane; the last runs of the tile may be short or empty.
 constexpr int kGroups = kThreads / 256;
 constexpr int kGroupLanes = 256;
-// Weights measured on MI355X (per-wave completion times of equal runs; the
-// same table fits FP64 and FP32 records within the timing noise).
-constexpr int64_t kGroupWeights[4] = {64, 60, 54, 46};
+// Weights measured on MI355X (per-wave completion times of equal runs):
+// FP64 records, FP32 records.
+constexpr int64_t kGroupWeights[2][4] = {{64, 60, 54, 42}, {64, 60, 54, 46}};
 template <typename T>
 __device__ __forceinline__ int64_t group_weight(int g)
 {
-    return kGroupWeights[g];
+    return kGroupWeights[sizeof(T) == 4][g];
 }
 template <typename T>
 constexpr int64_t weight_sum()
 {
     int64_t w = 0;
     for (int g = 0; g < kGroups; ++g)
-        w += kGroupWeights[g];
+        w += kGroupWeights[sizeof(T) == 4][g];
     return w;
 }
 
