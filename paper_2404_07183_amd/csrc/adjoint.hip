@@ -229,7 +229,7 @@ __device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
                                           int64_t d, int32_t C)
 {
     const d2 *lv = reinterpret_cast<const d2 *>(lrec);
-    const int r = k / C, c = k - (k / C) * C;
+    const int r = div_by_c(k, sh.cmag), c = k - r * C;
     ch.r = r;
     ch.c = c;
     ch.rb = sh.rb[r];
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         // pair weights: W = (G_ij + G_ji) * chain for i != j, G_ii on the
         // diagonal; stored in the partial-sum slots (unused here)
         if (tid < npairs) {
-            const int r = tid / C, c = tid - (tid / C) * C;
+            const int r = div_by_c(tid, sh.cmag), c = tid - r * C;
             const int64_t i = D.r_lo + r, j = D.c_lo + c;
             double W = 0.0;
             if (sh.pw[tid + 1] > sh.pw[tid]) {
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             int32_t k = sh.pairof[tid];
             int64_t d = s - sh.pw[k];
             while (s < e) {
-                const int r = k / C, c = k - (k / C) * C;
+                const int r = div_by_c(k, sh.cmag), c = k - r * C;
                 const int64_t len = sh.pw[k + 1] - sh.pw[k];
                 const int64_t m = (len - d < e - s) ? len - d : e - s;
                 const int32_t A = sh.rb[r], B = sh.cb[c];

@@ -210,7 +210,7 @@ __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
                                             const Rec<T> *base, int32_t k,
                                             int64_t d, int32_t C)
 {
-    const int r = k / C, c = k - (k / C) * C;
+    const int r = div_by_c(k, sh.cmag), c = k - r * C;
     ch.r = r;
     ch.c = c;
     ch.rb = sh.rb[r];
@@ -357,24 +357,25 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
 
         // finish: unbounded-tail rule, root; write (i, j) row-major
         for (int k = tid; k < npairs; k += kThreads) {
-            const int r = k / C, c = k - (k / C) * C;
+            const int r = div_by_c(k, D.cmag), c = k - r * C;
             if (diag && r > c)
                 continue;
+            // every LDS value this pair needs, read at once (plo / phi are
+            // stale for a pair without steps: then no partial sum is read)
             const int64_t b0 = sh.pw[k], b1 = sh.pw[k + 1];
+            int32_t l = sh.plo[k];
+            const int32_t l1 = b1 > b0 ? (int32_t)sh.phi[k] : l - 1;
+            const T lr = (T)sh.rlast[r], lc = (T)sh.clast[c];
+            // the pair's partial sums in lane order, loads batched
             double val = 0.0;
-            if (b1 > b0) {
-                // the pair's partial sums in lane order, loads batched
-                int32_t l = sh.plo[k];
-                const int32_t l1 = sh.phi[k];
-                for (; l + 3 <= l1; l += 4) {
-                    const double q0 = sh.part[k + l], q1 = sh.part[k + l + 1];
-                    const double q2 = sh.part[k + l + 2], q3 = sh.part[k + l + 3];
-                    val = (((val + q0) + q1) + q2) + q3;
-                }
-                for (; l <= l1; ++l)
-                    val += sh.part[k + l];
+            for (; l + 3 <= l1; l += 4) {
+                const double q0 = sh.part[k + l], q1 = sh.part[k + l + 1];
+                const double q2 = sh.part[k + l + 2], q3 = sh.part[k + l + 3];
+                val = (((val + q0) + q1) + q2) + q3;
             }
-            const T ht = hval<T, HK>((T)sh.rlast[r], (T)sh.clast[c], p);
+            for (; l <= l1; ++l)
+                val += sh.part[k + l];
+            const T ht = hval<T, HK>(lr, lc, p);
             if (ht != T(0))
                 val = ht > T(0) ? INFINITY : -INFINITY;
             if constexpr (RT == kRootSqrt)

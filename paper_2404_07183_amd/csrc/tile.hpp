@@ -74,7 +74,8 @@ struct TileDesc {
     int64_t rrec0, crec0;  // first global record of the row / column block
     int64_t rrecs, crecs;  // records of the row / column block
     int64_t obase, ldo, row0, col0;  // output mapping of the segment
-    int32_t R, C, diag, mirror, global_mode, pad_;
+    int32_t R, C, diag, mirror, global_mode;
+    int32_t cmag;          // floor(2^16 / C) + 1 (see div_by_c)
 };
 
 struct TileShared {
@@ -97,11 +98,22 @@ struct TileShared {
     int64_t gper[4];   // steps per lane of each wave group (see LaneSplit)
     int64_t gbase[5];  // first step of each wave group
     int32_t npairs;
+    int32_t cmag;      // the current tile's cmag (see div_by_c)
 };
 
 constexpr int kSharedHead = (int)((sizeof(TileShared) + 255) / 256 * 256);
 static_assert(kSharedHead + kLdsRecordBytes <= 160 * 1024 / kWgPerCu,
               "the tile workgroups of a CU must fit its 160 KiB of LDS");
+
+// k / C for 0 <= k < 2048 and 1 <= C <= 32, by a multiply: with
+// m = floor(2^16 / C) + 1, k m / 2^16 exceeds k / C by less than
+// k / 2^16 < 1/32 <= 1/C, which cannot carry it past the next integer (the
+// fractional part of k / C is at most 1 - 1/C).
+static_assert(kMaxBlock <= 32 && kMaxPairs <= 2048, "div_by_c range");
+__device__ __forceinline__ int32_t div_by_c(int32_t k, int32_t cmag)
+{
+    return (int32_t)(((uint32_t)k * (uint32_t)cmag) >> 16);
+}
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS
 // operations, not for its global stores (no thread of the workgroup reads
@@ -164,15 +176,17 @@ __device__ __forceinline__ int32_t block_scan<int32_t>(int32_t x, int32_t *wsum,
     if (lane == 63)
         wsum[wave] = v;
     sync_lds();
-    int32_t before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-        const int32_t t = wsum[w];
-        before += w < wave ? t : 0;
-        tot += t;
-    }
-    *total = tot;
-    return before + v - x;
+    // the sixteen wave totals, scanned again inside each row of 16 lanes
+    static_assert(kThreads == 1024, "one wave total per lane of a DPP row");
+    int32_t w = wsum[lane & 15];
+    w += __builtin_amdgcn_update_dpp(0, w, 0x111, 0xf, 0xf, false);
+    w += __builtin_amdgcn_update_dpp(0, w, 0x112, 0xf, 0xf, false);
+    w += __builtin_amdgcn_update_dpp(0, w, 0x114, 0xf, 0xf, false);
+    w += __builtin_amdgcn_update_dpp(0, w, 0x118, 0xf, 0xf, false);
+    *total = __builtin_amdgcn_readlane(w, 15);
+    const int sw = __builtin_amdgcn_readfirstlane(wave);
+    const int32_t before = __builtin_amdgcn_readlane(w, sw > 0 ? sw - 1 : 0);
+    return (sw > 0 ? before : 0) + v - x;
 }
 
 // Decode a tile index into (segment, I, J); thread 0 only.
@@ -291,6 +305,7 @@ __device__ __forceinline__ void tile_decode(TileDesc &d, int64_t tile,
     d.c_lo = c_lo;
     d.R = (int32_t)(r_hi - r_lo);
     d.C = (int32_t)(c_hi - c_lo);
+    d.cmag = (1 << 16) / d.C + 1;
     d.diag = (seg->type == kSegTriangle && I == J) ? 1 : 0;
     d.mirror = seg->mirror;
     d.obase = seg->obase;
@@ -451,6 +466,39 @@ struct LaneSplit {
             base[g + 1] = base[g] + kGroupLanes * per[g];
         }
     }
+    // make() for totals below 2^30, with the divisions by constants done
+    // in FP64 (the same instructions on every lane, so the same split)
+    __device__ __forceinline__ void make_small(int32_t total)
+    {
+        constexpr double kInv = 1.0 / (double)(kGroupLanes * weight_sum<T>() * kStepBlock);
+        int32_t b = 0;
+        base[0] = 0;
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+            int32_t p;
+            if (g + 1 < kGroups) {
+                p = (int32_t)rint((double)total * (double)group_weight<T>(g) * kInv) *
+                    kStepBlock;
+            } else {
+                const int32_t rest = total - b > 0 ? total - b : 0;
+                p = (rest + kGroupLanes - 1) / kGroupLanes;
+                p = (p + kStepBlock - 1) & ~(kStepBlock - 1);
+            }
+            p = p < kStepBlock ? kStepBlock : p;
+            per[g] = p;
+            b += kGroupLanes * p;
+            base[g + 1] = b;
+        }
+    }
+    // a / b for 0 <= a < 2^30, 8 <= b < 2^30 and a / b < 2^10: a float
+    // reciprocal estimate (off by at most one at these ratios), corrected
+    __device__ __forceinline__ static int32_t quot_small(int32_t a, int32_t b)
+    {
+        int32_t j = (int32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+        const int32_t r = a - j * b;
+        j += (r >= b ? 1 : 0) - (r < 0 ? 1 : 0);
+        return j;
+    }
     // a / b for 0 <= a, 0 < b, in 32 bits when both fit
     __device__ __forceinline__ static int32_t quot(int64_t a, int64_t b)
     {
@@ -490,7 +538,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
     const int32_t C = d.C, npairs = d.R * d.C;
     int64_t wp = 0;
     if (tid < npairs) {
-        const int r = tid / C, c = tid - (tid / C) * C;
+        const int r = div_by_c(tid, d.cmag), c = tid - r * C;
         bool live = true;
         if (d.diag)
             live = gram ? (r <= c) : (r < c);
@@ -499,36 +547,57 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
             wp = (w + kStepBlock - 1) / kStepBlock * kStepBlock;
         }
     }
-    // 32-bit scan when the tile's step total certainly fits (LDS tiles)
-    int64_t total, excl;
+    // 32-bit work when the tile's step total certainly stays below 2^30
+    // (LDS tiles)
+    int64_t total;
+    LaneSplit<T> sp;
     const int64_t bound = (int64_t)C * d.rrecs + (int64_t)d.R * d.crecs +
                           (int64_t)kStepBlock * npairs;
-    if (bound < ((int64_t)1 << 31)) {
+    if (bound < ((int64_t)1 << 30)) {
         int32_t t32;
-        excl = block_scan<int32_t>((int32_t)wp, reinterpret_cast<int32_t *>(sh.wsum), &t32);
+        const int32_t excl =
+            block_scan<int32_t>((int32_t)wp, reinterpret_cast<int32_t *>(sh.wsum), &t32);
         total = t32;
-    } else {
-        excl = block_scan<int64_t>(wp, sh.wsum, &total);
-    }
-    LaneSplit<T> sp;
-    sp.make(total);
-    if (tid < npairs) {
-        sh.pw[tid] = excl;
-        // lanes whose first step lies in [excl, excl + wp)
+        sp.make_small(t32);
+        if (tid < npairs) {
+            sh.pw[tid] = excl;
+            // lanes whose first step lies in [excl, excl + wp)
+            const int32_t end = excl + (int32_t)wp;
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
-            const int64_t lo = excl > sp.base[g] ? excl : sp.base[g];
-            const int64_t hi = excl + wp < sp.base[g + 1] ? excl + wp : sp.base[g + 1];
-            if (lo < hi) {
-                for (int64_t j = LaneSplit<T>::quot(lo - sp.base[g] + sp.per[g] - 1, sp.per[g]);
-                     sp.base[g] + j * sp.per[g] < hi; ++j)
-                    sh.pairof[g * kGroupLanes + j] = (int16_t)tid;
+            for (int g = 0; g < kGroups; ++g) {
+                const int32_t b0 = (int32_t)sp.base[g], b1 = (int32_t)sp.base[g + 1];
+                const int32_t per = (int32_t)sp.per[g];
+                const int32_t lo = excl > b0 ? excl : b0;
+                const int32_t hi = end < b1 ? end : b1;
+                if (lo < hi) {
+                    for (int32_t j = LaneSplit<T>::quot_small(lo - b0 + per - 1, per);
+                         b0 + j * per < hi; ++j)
+                        sh.pairof[g * kGroupLanes + j] = (int16_t)tid;
+                }
+            }
+        }
+    } else {
+        const int64_t excl = block_scan<int64_t>(wp, sh.wsum, &total);
+        sp.make(total);
+        if (tid < npairs) {
+            sh.pw[tid] = excl;
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) {
+                const int64_t lo = excl > sp.base[g] ? excl : sp.base[g];
+                const int64_t hi = excl + wp < sp.base[g + 1] ? excl + wp : sp.base[g + 1];
+                if (lo < hi) {
+                    for (int64_t j = LaneSplit<T>::quot(lo - sp.base[g] + sp.per[g] - 1,
+                                                        sp.per[g]);
+                         sp.base[g] + j * sp.per[g] < hi; ++j)
+                        sh.pairof[g * kGroupLanes + j] = (int16_t)tid;
+                }
             }
         }
     }
     if (tid == 0) {
         sh.pw[npairs] = total;
         sh.npairs = npairs;
+        sh.cmag = d.cmag;
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
             sh.gper[g] = sp.per[g];
