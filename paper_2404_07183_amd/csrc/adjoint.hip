@@ -318,10 +318,13 @@ __device__ __forceinline__ void adj_lane_chain(const TileShared &sh,
 template <int HK>
 __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
 {
+    // tile state in static LDS, records (and the adjoint's accumulators)
+    // in the dynamic part: distinct objects, so the compiler knows that the
+    // direct record loads into the latter never touch the former
+    __shared__ TileShared sh;
     extern __shared__ __align__(16) unsigned char smem[];
-    TileShared &sh = *reinterpret_cast<TileShared *>(smem);
     const WsHeader &h = hdr_of(args.ws);
-    Rec<double> *lrec = reinterpret_cast<Rec<double> *>(smem + kSharedHead);
+    Rec<double> *lrec = reinterpret_cast<Rec<double> *>(smem);
     // gradient slots (gt, gv) follow the record slots
     double *lg = reinterpret_cast<double *>(lrec + h.lds_records);
     const Rec<double> *grec = reinterpret_cast<const Rec<double> *>(args.ws + h.off_rec);
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     const double p = args.p;
 
     TileLoop loop;
-    loop.start<double>(sh, args.ws, offsets, lrec, grec);
+    loop.start<double, true>(sh, args.ws, offsets, lrec, grec);
     while (loop.live(sh, args.ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             }
         }
         // (the accumulator flush reads the block metadata)
-        loop.stage_next<double>(sh, args.ws, grec, offsets, lrec, true);
+        loop.stage_next<double, true>(sh, args.ws, grec, offsets, lrec, true);
         loop.advance();
     }
 }

@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     T *out = reinterpret_cast<T *>(args.out);
 
     TileLoop loop;
-    loop.start<T>(sh, ws, offsets, lrec, grec);
+    loop.start<T, false>(sh, ws, offsets, lrec, grec);
     while (loop.live(sh, ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
@@ -351,9 +351,9 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         // the next tile's staging loads fly while this tile is finished
         // (finishing reads neither records nor block metadata)
         const bool has_next = loop.has_next(sh, ws);
-        StageRegs<T> next;
+        StageRegs<T, false> next;
         if (has_next)
-            stage_load<T>(next, sh.desc[loop.nxt()], grec, offsets);
+            stage_load<T, false>(next, sh.desc[loop.nxt()], grec, offsets, lrec);
 
         // finish: unbounded-tail rule, root; write (i, j) row-major
         for (int k = tid; k < npairs; k += kThreads) {
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
                 out[D.obase + (j - D.row0) * D.ldo + (i - D.col0)] = (T)val;
         }
         if (has_next)
-            stage_store<T>(sh, next, sh.desc[loop.nxt()], lrec);
+            stage_store<T, false>(sh, next, sh.desc[loop.nxt()], lrec);
         loop.advance();
     }
 }
@@ -399,7 +399,9 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
 size_t tile_shared_bytes(int rec_bytes, bool backward)
 {
     const int per = rec_bytes + (backward ? 16 : 0);
-    return (size_t)kSharedHead + (size_t)(kLdsRecordBytes / per) * per;
+    // the forward kernel keeps its tile state at the start of the dynamic
+    // LDS, the adjoint in static LDS
+    return (size_t)(backward ? 0 : kSharedHead) + (size_t)(kLdsRecordBytes / per) * per;
 }
 
 template <typename T>

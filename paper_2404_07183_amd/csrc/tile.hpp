@@ -335,18 +335,27 @@ template <typename T> struct RecVec;
 template <> struct RecVec<double> { typedef d2v type; };
 template <> struct RecVec<float> { typedef f2v type; };
 
-template <typename T>
+// Direct staging (`Direct`, FP64 records only) moves records straight from
+// global memory to LDS (global_load_lds_dwordx4: each lane's record lands at
+// the wave's LDS base plus 16 bytes per lane), with no register round trip
+// or LDS store instructions. The compiler then makes every later LDS read
+// wait for those loads unless it can tell the tile state apart (a separate
+// LDS object), so it pays where staging is not overlapped with other LDS
+// work (the adjoint); the forward kernel stages through registers, with the
+// loads in flight while it finishes the current tile.
+template <typename T, bool Direct>
 struct StageRegs {
-    typename RecVec<T>::type r[stage_unroll<T>()];
+    static_assert(!Direct || sizeof(Rec<T>) == 16, "direct staging moves 16-byte records");
+    typename RecVec<T>::type r[Direct ? 1 : stage_unroll<T>()];
     int64_t m0, m1;
 };
 
 // Loads of tile d's staging: its records (row block, then column block
 // unless diagonal; none in global mode) and the block metadata.
-template <typename T>
-__device__ __forceinline__ void stage_load(StageRegs<T> &g, const TileDesc &d,
+template <typename T, bool Direct>
+__device__ __forceinline__ void stage_load(StageRegs<T, Direct> &g, const TileDesc &d,
                                            const Rec<T> *grec,
-                                           const int64_t *offsets)
+                                           const int64_t *offsets, Rec<T> *lrec)
 {
     typedef typename RecVec<T>::type V;
     constexpr int U = stage_unroll<T>();
@@ -354,17 +363,38 @@ __device__ __forceinline__ void stage_load(StageRegs<T> &g, const TileDesc &d,
     const int64_t rrecs = d.rrecs, rrec0 = d.rrec0, crec0 = d.crec0;
     const int64_t total = d.global_mode ? 0 : (d.diag ? rrecs : rrecs + d.crecs);
     if (total > 0) {
-        // unconditional loads (indices past the end read record 0 of the
-        // tile again), so that the values stay in registers; a tile's LDS
-        // records number less than 2^31, so 32-bit indices
+        // a tile's LDS records number less than 2^31, so 32-bit indices
         const V *rbase = reinterpret_cast<const V *>(grec) + rrec0;
         const V *cbase = reinterpret_cast<const V *>(grec) + (crec0 - rrecs);
         const int32_t tot = (int32_t)total, nr = (int32_t)rrecs;
+        if constexpr (Direct) {
+            // whole waves past the end issue nothing; in the last wave the
+            // lanes past the end reload record 0 into slots below the next
+            // multiple of 64 records, inside the record area
+            const int32_t wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+            // not unrolled: one load instruction, which the compiler's
+            // tracking of direct-to-LDS loads can tell apart from the tile
+            // state (so reads of the latter do not wait for these loads)
+#pragma unroll 1
+            for (int u = 0; u < U; ++u) {
+                const int32_t q0 = wbase + u * kThreads;
+                if (q0 < tot) {
+                    int32_t q = tid + u * kThreads;
+                    q = q < tot ? q : 0;
+                    __builtin_amdgcn_global_load_lds(
+                        (const void *)((q < nr ? rbase : cbase) + q),
+                        (void *)(reinterpret_cast<V *>(lrec) + q0), 16, 0, 0);
+                }
+            }
+        } else {
+            // unconditional loads (indices past the end read record 0 of
+            // the tile again), so that the values stay in registers
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            int32_t q = tid + u * kThreads;
-            q = q < tot ? q : 0;
-            g.r[u] = (q < nr ? rbase : cbase)[q];
+            for (int u = 0; u < U; ++u) {
+                int32_t q = tid + u * kThreads;
+                q = q < tot ? q : 0;
+                g.r[u] = (q < nr ? rbase : cbase)[q];
+            }
         }
     }
     const bool mrow = tid < d.R;
@@ -377,8 +407,8 @@ __device__ __forceinline__ void stage_load(StageRegs<T> &g, const TileDesc &d,
 }
 
 // LDS stores of tile d's staging (after stage_load on the same thread).
-template <typename T>
-__device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T> &g,
+template <typename T, bool Direct>
+__device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T, Direct> &g,
                                             const TileDesc &d, Rec<T> *lrec)
 {
     constexpr int U = stage_unroll<T>();
@@ -388,11 +418,19 @@ __device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T> &
     typedef typename RecVec<T>::type V;
     V *lv = reinterpret_cast<V *>(lrec);
     const int32_t tot = (int32_t)total;
+    if constexpr (Direct) {
+        // the direct loads have landed (the barrier that follows publishes
+        // them to the workgroup)
+        (void)lv;
+        (void)tot;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    } else {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int32_t q = tid + u * kThreads;
-        if (q < tot)
-            lv[q] = g.r[u];
+        for (int u = 0; u < U; ++u) {
+            const int32_t q = tid + u * kThreads;
+            if (q < tot)
+                lv[q] = g.r[u];
+        }
     }
     const bool mrow = tid < d.R;
     const bool mcol = tid >= 64 && tid < 64 + d.C;
@@ -623,7 +661,7 @@ struct TileLoop {
     __device__ __forceinline__ int aft() const { return cur == 0 ? 2 : cur - 1; }
 
     // decode the first two tiles, stage the first one
-    template <typename T>
+    template <typename T, bool Direct>
     __device__ __forceinline__ void start(TileShared &sh, const unsigned char *ws,
                                           const int64_t *offsets, Rec<T> *lrec,
                                           const Rec<T> *grec)
@@ -634,9 +672,9 @@ struct TileLoop {
         }
         sync_lds();
         if (sh.desc[0].tile < hdr_of(ws).ntiles) {
-            StageRegs<T> g;
-            stage_load<T>(g, sh.desc[0], grec, offsets);
-            stage_store<T>(sh, g, sh.desc[0], lrec);
+            StageRegs<T, Direct> g;
+            stage_load<T, Direct>(g, sh.desc[0], grec, offsets, lrec);
+            stage_store<T, Direct>(sh, g, sh.desc[0], lrec);
         }
         sync_lds();
     }
@@ -668,7 +706,7 @@ struct TileLoop {
     // staging of the next tile, after finishing the current one; `barrier`
     // when the finishing code reads records or block metadata (otherwise a
     // wave stages as soon as its own finishing work is done)
-    template <typename T>
+    template <typename T, bool Direct>
     __device__ __forceinline__ void stage_next(TileShared &sh, const unsigned char *ws,
                                                const Rec<T> *grec,
                                                const int64_t *offsets,
@@ -679,9 +717,9 @@ struct TileLoop {
             return;
         if (barrier)
             sync_lds();
-        StageRegs<T> g;
-        stage_load<T>(g, n, grec, offsets);
-        stage_store<T>(sh, g, n, lrec);
+        StageRegs<T, Direct> g;
+        stage_load<T, Direct>(g, n, grec, offsets, lrec);
+        stage_store<T, Direct>(sh, g, n, lrec);
     }
     __device__ __forceinline__ void advance()
     {
