@@ -32,6 +32,10 @@ def compile_flags():
         "-fPIC",
         # no packed FP32 instructions anywhere in device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # the tile queue's single-lane ticket atomic stays a plain atomic:
+        # the wave-aggregating rewrite would wait for its return right away,
+        # in front of the merge work, instead of at the decode after it
+        "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
         "-I", os.path.join(ROOT, "include"),
         "-I", CSRC,
         "-Wall",

@@ -278,12 +278,14 @@ __device__ __forceinline__ void pair_start(Src src, int32_t A, int32_t na,
 // at most kThreads - 64 pairs.
 constexpr int kQueueLane = kThreads - 64;
 
-// Takes the next ticket from the tile queue.
-__device__ __forceinline__ int64_t tile_ticket(const unsigned char *ws)
+// Takes the next ticket from the tile queue. The ticket stays 32-bit until
+// it is decoded, so that no instruction reads the returned value (and waits
+// for it) before the decode, after the merge work.
+__device__ __forceinline__ uint32_t tile_ticket(const unsigned char *ws)
 {
     uint32_t *counter =
         const_cast<uint32_t *>(reinterpret_cast<const WsHeader *>(ws)->counter);
-    return (int64_t)atomicAdd(&counter[0], 1u);
+    return atomicAdd(&counter[0], 1u);
 }
 
 // Decodes ticket `tile` into d (one lane).
@@ -655,7 +657,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
 //   scan -> take_next -> merge -> decode_next, finish -> stage_next -> advance
 struct TileLoop {
     int cur = 0;
-    int64_t ticket = 0;
+    uint32_t ticket = 0;
 
     __device__ __forceinline__ int nxt() const { return cur == 2 ? 0 : cur + 1; }
     __device__ __forceinline__ int aft() const { return cur == 0 ? 2 : cur - 1; }
