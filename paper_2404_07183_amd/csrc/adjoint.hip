@@ -298,6 +298,7 @@ __device__ __forceinline__ void adj_lane_chain(const TileShared &sh,
 {
     const d2 *lv = reinterpret_cast<const d2 *>(lrec);
     AdjChain ch;
+    // (an LDS tile: its step prefix is the 32-bit one)
     adj_begin(ch, sh, lrec, k, s - sh.pw[k], C);
     for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
         if (ch.left == 0) {
@@ -325,6 +326,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     extern __shared__ __align__(16) unsigned char smem[];
     const WsHeader &h = hdr_of(args.ws);
     Rec<double> *lrec = reinterpret_cast<Rec<double> *>(smem);
+    int64_t *pw64 = reinterpret_cast<int64_t *>(lrec);  // wide step prefix
     // gradient slots (gt, gv) follow the record slots
     double *lg = reinterpret_cast<double *>(lrec + h.lds_records);
     const Rec<double> *grec = reinterpret_cast<const Rec<double> *>(args.ws + h.off_rec);
@@ -337,10 +339,10 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     while (loop.live(sh, args.ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
-        tile_scan<double>(sh, D, args.gram, gmode ? grec : lrec);
+        tile_scan<double>(sh, D, args.gram, gmode ? grec : lrec, pw64);
         const int32_t R = D.R, C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
-        const int64_t total = sh.pw[npairs];
+        const int64_t total = pw_at(sh, pw64, npairs);
         const int64_t nslots = diag ? D.rrecs : D.rrecs + D.crecs;
         if (!gmode)
             for (int64_t q = tid; q < 2 * nslots; q += kThreads)
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             const int r = div_by_c(tid, sh.cmag), c = tid - r * C;
             const int64_t i = D.r_lo + r, j = D.c_lo + c;
             double W = 0.0;
-            if (sh.pw[tid + 1] > sh.pw[tid]) {
+            if (pw_at(sh, pw64, tid + 1) > pw_at(sh, pw64, tid)) {
                 W = args.grad_out[i * args.ldg + j];
                 if (i != j)
                     W += args.grad_out[j * args.ldg + i];
@@ -373,10 +375,10 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                                diag, args.gram, p);
         } else if (s < e) {
             int32_t k = sh.pairof[tid];
-            int64_t d = s - sh.pw[k];
+            int64_t d = s - pw_at(sh, pw64, k);
             while (s < e) {
                 const int r = div_by_c(k, sh.cmag), c = k - r * C;
-                const int64_t len = sh.pw[k + 1] - sh.pw[k];
+                const int64_t len = pw_at(sh, pw64, k + 1) - pw_at(sh, pw64, k);
                 const int64_t m = (len - d < e - s) ? len - d : e - s;
                 const int32_t A = sh.rb[r], B = sh.cb[c];
                 GradSink sa, sb;
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 s += m;
                 d = 0;
                 ++k;
-                while (k < npairs && sh.pw[k + 1] == sh.pw[k])
+                while (k < npairs && pw_at(sh, pw64, k + 1) == pw_at(sh, pw64, k))
                     ++k;
             }
         }

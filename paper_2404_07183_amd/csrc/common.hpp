@@ -23,7 +23,10 @@ constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
 // LDS bytes a tile may use for breakpoint records (of 160 KiB per CU on
 // gfx950; the rest holds per-pair prefix sums, accumulators and block
 // metadata).
-constexpr int kLdsRecordBytes = 128 * 1024;
+#ifndef PCF_LDSREC
+#define PCF_LDSREC (136 * 1024)
+#endif
+constexpr int kLdsRecordBytes = PCF_LDSREC;
 
 // Rows a PCF may have (exclusive): keeps a pair's merge steps below 2^31.
 constexpr int64_t kMaxRows = (int64_t)1 << 30;

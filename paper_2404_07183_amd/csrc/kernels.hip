@@ -272,29 +272,22 @@ __device__ __forceinline__ void chain_next_pair(Chain<T, Src> &ch, const Shared 
     ch.left = pair_steps(rn, cn);
 }
 
-// This lane's share of the tile: steps [s, e) (e - s a multiple of
-// kStepBlock, pair boundaries too), starting in pair k; its partial sum of
-// pair k' goes to sh.part[k' + vl].
+// This lane's share of the tile: nblk blocks of kStepBlock steps (pair
+// boundaries fall between blocks), starting at step d0 of pair k; its
+// partial sum of pair k' goes to sh.part[k' + vl].
 template <typename T, int HK, typename Src, typename Shared>
 __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
-                                           int64_t s, int64_t e, int32_t k,
+                                           int64_t d0, int32_t nblk, int32_t k,
                                            int32_t vl, int32_t C, bool diag,
                                            int gram, T p)
 {
     Chain<T, Src> ch;
-    const int64_t d0 = s - sh.pw[k];
     chain_begin(ch, sh, base, k, d0, C);
-    // the lanes holding a pair's first and last step, for the finishing code
-    if (d0 == 0)
-        sh.plo[k] = (int16_t)vl;
-    for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
+    for (int32_t blk = nblk; blk > 0; --blk) {
         if (ch.left == 0) {
             // next pair (a rare, divergent branch)
-            const int32_t kd = ch.r * C + ch.c;
-            sh.part[kd + vl] = ch.acc;
-            sh.phi[kd] = (int16_t)vl;
+            sh.part[ch.r * C + ch.c + vl] = ch.acc;
             chain_next_pair(ch, sh, base, C, diag, gram);
-            sh.plo[ch.r * C + ch.c] = (int16_t)vl;
         }
         T part = T(0);
 #pragma unroll
@@ -303,10 +296,7 @@ __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
         ch.acc += (double)part;
         ch.left -= kStepBlock;
     }
-    const int32_t kd = ch.r * C + ch.c;
-    sh.part[kd + vl] = ch.acc;
-    if (ch.left == 0)
-        sh.phi[kd] = (int16_t)vl;
+    sh.part[ch.r * C + ch.c + vl] = ch.acc;
 }
 
 template <typename T, int HK, int RT>
@@ -315,6 +305,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     extern __shared__ __align__(16) unsigned char smem[];
     TileShared &sh = *reinterpret_cast<TileShared *>(smem);
     Rec<T> *lrec = reinterpret_cast<Rec<T> *>(smem + kSharedHead);
+    int64_t *pw64 = reinterpret_cast<int64_t *>(lrec);  // wide step prefix
     const int tid = threadIdx.x;
     const unsigned char *ws = args.ws;
     const WsHeader &h = hdr_of(ws);
@@ -328,10 +319,10 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     while (loop.live(sh, ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
-        tile_scan<T>(sh, D, args.gram, gmode ? grec : lrec);
+        tile_scan<T>(sh, D, args.gram, gmode ? grec : lrec, pw64);
         const int32_t C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
-        const int64_t total = sh.pw[npairs];
+        const int64_t total = pw_at(sh, pw64, npairs);
 
         loop.take_next(ws);
         // this lane's share of the tile's steps
@@ -339,11 +330,13 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         lane_steps(sh, tid, total, s0, e0);
         const int32_t k0 = s0 < e0 ? sh.pairof[tid] : 0;
         if (s0 < e0) {
+            const int64_t d0 = s0 - pw_at(sh, pw64, k0);
+            const int32_t nblk = (int32_t)((e0 - s0) / kStepBlock);
             if (gmode)
-                lane_chain<T, HK, GlobalSrc<T>>(sh, grec, s0, e0, k0, tid, C,
+                lane_chain<T, HK, GlobalSrc<T>>(sh, grec, d0, nblk, k0, tid, C,
                                                 diag, args.gram, p);
             else
-                lane_chain<T, HK, LdsSrc<T>>(sh, lrec, s0, e0, k0, tid, C,
+                lane_chain<T, HK, LdsSrc<T>>(sh, lrec, d0, nblk, k0, tid, C,
                                              diag, args.gram, p);
         }
         sync_lds();
@@ -360,11 +353,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
             const int r = div_by_c(k, D.cmag), c = k - r * C;
             if (diag && r > c)
                 continue;
-            // every LDS value this pair needs, read at once (plo / phi are
-            // stale for a pair without steps: then no partial sum is read)
-            const int64_t b0 = sh.pw[k], b1 = sh.pw[k + 1];
-            int32_t l = sh.plo[k];
-            const int32_t l1 = b1 > b0 ? (int32_t)sh.phi[k] : l - 1;
+            // the lanes holding the pair's first and last steps (none for a
+            // pair without steps)
+            const int64_t b0 = pw_at(sh, pw64, k), b1 = pw_at(sh, pw64, k + 1);
+            int32_t l = 0, l1 = -1;
+            if (b1 > b0) {
+                l = lane_of(sh, b0);
+                l1 = lane_of(sh, b1 - 1);
+            }
             const T lr = (T)sh.rlast[r], lc = (T)sh.clast[c];
             // the pair's partial sums in lane order, loads batched
             double val = 0.0;

@@ -79,17 +79,17 @@ struct TileDesc {
 };
 
 struct TileShared {
-    int64_t pw[kMaxPairs + 1];  // exclusive prefix of padded pair steps
-    // partial sums: virtual lane l's share of pair k lands in slot k + l
-    // (distinct for all (k, l) because both the pairs and the lanes' step
-    // ranges are ordered); each pair then adds its slots in lane order, so
-    // the result does not depend on timing. The finished result of pair k
-    // goes to slot k + pw[k] / per, also unique per pair, zero-step pairs
-    // included.
+    // exclusive prefix of padded pair steps, 32-bit; a tile whose step
+    // total may reach 2^30 (only global-mode tiles) keeps it in 64 bits at
+    // the start of the LDS record area instead (pw_wide; see pw_at)
+    int32_t pw[kMaxPairs + 1];
+    // partial sums: lane l's share of pair k lands in slot k + l (distinct
+    // for all (k, l) because both the pairs and the lanes' step ranges are
+    // ordered); each pair then adds its slots in lane order, from the lane
+    // of its first step to the lane of its last (lane_of), so the result
+    // does not depend on timing
     double part[kMaxPairs + kThreads];
     int16_t pairof[kThreads];  // pair holding the first step of each lane
-    int16_t plo[kMaxPairs], phi[kMaxPairs];  // lanes of a pair's first/last step
-                                             // (written by the merge chains)
     int32_t rn[kMaxBlock], rb[kMaxBlock];  // row PCF rows / record base
     int32_t cn[kMaxBlock], cb[kMaxBlock];  // column PCF rows / record base
     double rlast[kMaxBlock], clast[kMaxBlock];  // last values (tail rule)
@@ -99,6 +99,7 @@ struct TileShared {
     int64_t gbase[5];  // first step of each wave group
     int32_t npairs;
     int32_t cmag;      // the current tile's cmag (see div_by_c)
+    int32_t pw_wide;   // the step prefix is the 64-bit one in the record area
 };
 
 constexpr int kSharedHead = (int)((sizeof(TileShared) + 255) / 256 * 256);
@@ -322,11 +323,13 @@ __device__ __forceinline__ void tile_decode(TileDesc &d, int64_t tile,
     d.global_mode = need > h.lds_records ? 1 : 0;
 }
 
-// Records each thread stages: 128 bytes, so that one pass moves a full LDS
-// record area (kLdsRecordBytes <= kThreads * 128).
+// Records each thread stages, so that one pass moves a full LDS record area.
 template <typename T>
-constexpr int stage_unroll() { return 128 / (int)sizeof(Rec<T>); }
-static_assert(kLdsRecordBytes <= kThreads * 128, "one staging pass per tile");
+constexpr int stage_unroll()
+{
+    return (int)((kLdsRecordBytes + kThreads * (int)sizeof(Rec<T>) - 1) /
+                 (kThreads * (int)sizeof(Rec<T>)));
+}
 
 // One thread's part of a tile's staging, held in registers between the
 // loads (issued early) and the LDS stores: up to stage_unroll() records and,
@@ -548,6 +551,27 @@ struct LaneSplit {
     }
 };
 
+// Entry k of the tile's step prefix (pw64: the LDS record area).
+__device__ __forceinline__ int64_t pw_at(const TileShared &sh, const int64_t *pw64, int k)
+{
+    return sh.pw_wide ? pw64[k] : (int64_t)sh.pw[k];
+}
+
+// The lane whose run holds step `step` of the tile (the inverse of
+// lane_steps).
+__device__ __forceinline__ int32_t lane_of(const TileShared &sh, int64_t step)
+{
+    const int g = (step >= sh.gbase[1] ? 1 : 0) + (step >= sh.gbase[2] ? 1 : 0) +
+                  (step >= sh.gbase[3] ? 1 : 0);
+    const int64_t a = step - sh.gbase[g], b = sh.gper[g];
+    int32_t j;
+    if (!sh.pw_wide)
+        j = LaneSplit<float>::quot_small((int32_t)a, (int32_t)b);
+    else
+        j = (int32_t)(a / b);
+    return g * kGroupLanes + j;
+}
+
 // Steps [s, e) of lane `lane` (e <= s when it has none).
 __device__ __forceinline__ void lane_steps(const TileShared &sh, int lane,
                                            int64_t total, int64_t &s, int64_t &e)
@@ -559,7 +583,15 @@ __device__ __forceinline__ void lane_steps(const TileShared &sh, int lane,
 }
 
 
-// Padded step count of every pair of tile d, prefix-summed into sh.pw
+// an LDS tile's step total stays below 2^30, so only global-mode tiles (which
+// leave the record area unused) take the 64-bit prefix
+static_assert((int64_t)kMaxBlock * (kLdsRecordBytes / 8) + 8 * (int64_t)kMaxPairs <
+                  ((int64_t)1 << 30),
+              "LDS tiles scan in 32 bits");
+
+// Padded step count of every pair of tile d, prefix-summed into sh.pw, or
+// into pw64 (the LDS record area, unused by global-mode tiles, the only ones
+// whose total may reach 2^30)
 // (diagonal tiles give work to pairs r < c, and to r == c when `gram`);
 // the split of the total over the lanes (sh.gper, sh.gbase: LaneSplit) and,
 // for each lane, the pair holding its first step (sh.pairof); the last value
@@ -568,7 +600,7 @@ __device__ __forceinline__ void lane_steps(const TileShared &sh, int lane,
 // Needs the staged tile; ends with a barrier.
 template <typename T>
 __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
-                                          int gram, const Rec<T> *src)
+                                          int gram, const Rec<T> *src, int64_t *pw64)
 {
     const int tid = threadIdx.x;
     if (tid < d.R)
@@ -620,7 +652,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
         const int64_t excl = block_scan<int64_t>(wp, sh.wsum, &total);
         sp.make(total);
         if (tid < npairs) {
-            sh.pw[tid] = excl;
+            pw64[tid] = excl;
 #pragma unroll
             for (int g = 0; g < kGroups; ++g) {
                 const int64_t lo = excl > sp.base[g] ? excl : sp.base[g];
@@ -635,7 +667,12 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
         }
     }
     if (tid == 0) {
-        sh.pw[npairs] = total;
+        const bool wide = !(bound < ((int64_t)1 << 30));
+        if (wide)
+            pw64[npairs] = total;
+        else
+            sh.pw[npairs] = (int32_t)total;
+        sh.pw_wide = wide ? 1 : 0;
         sh.npairs = npairs;
         sh.cmag = d.cmag;
 #pragma unroll

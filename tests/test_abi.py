@@ -74,7 +74,7 @@ def test_planner_full_matrix_blocks():
                             (_lib.PCF_F64, 16, True)]:
         nb, ns, nt, blocks = _inspect(o, dtype, backward=bwd)
         per = rec + (16 if bwd else 0)
-        budget = (128 * 1024 // per) // 2  # LDS record area of a tile
+        budget = (136 * 1024 // per) // 2  # LDS record area of a tile
         assert blocks[0] == 0 and blocks[-1] == 500
         assert np.all(np.diff(blocks) >= 1) and np.all(np.diff(blocks) <= 32)
         for a, b in zip(blocks[:-1], blocks[1:]):
