@@ -484,6 +484,16 @@ constexpr int64_t weight_sum()
     return w;
 }
 
+// a / b for 0 <= a < 2^30, 8 <= b < 2^30 and a / b < 2^10: a float
+// reciprocal estimate (off by at most one at these ratios), corrected
+__device__ __forceinline__ int32_t quot_small(int32_t a, int32_t b)
+{
+    int32_t j = (int32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
+    const int32_t r = a - j * b;
+    j += (r >= b ? 1 : 0) - (r < 0 ? 1 : 0);
+    return j;
+}
+
 template <typename T>
 struct LaneSplit {
     int64_t per[kGroups], base[kGroups + 1];
@@ -533,15 +543,6 @@ struct LaneSplit {
             base[g + 1] = b;
         }
     }
-    // a / b for 0 <= a < 2^30, 8 <= b < 2^30 and a / b < 2^10: a float
-    // reciprocal estimate (off by at most one at these ratios), corrected
-    __device__ __forceinline__ static int32_t quot_small(int32_t a, int32_t b)
-    {
-        int32_t j = (int32_t)((float)a * __builtin_amdgcn_rcpf((float)b));
-        const int32_t r = a - j * b;
-        j += (r >= b ? 1 : 0) - (r < 0 ? 1 : 0);
-        return j;
-    }
     // a / b for 0 <= a, 0 < b, in 32 bits when both fit
     __device__ __forceinline__ static int32_t quot(int64_t a, int64_t b)
     {
@@ -566,7 +567,7 @@ __device__ __forceinline__ int32_t lane_of(const TileShared &sh, int64_t step)
     const int64_t a = step - sh.gbase[g], b = sh.gper[g];
     int32_t j;
     if (!sh.pw_wide)
-        j = LaneSplit<float>::quot_small((int32_t)a, (int32_t)b);
+        j = quot_small((int32_t)a, (int32_t)b);
     else
         j = (int32_t)(a / b);
     return g * kGroupLanes + j;
@@ -642,7 +643,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
                 const int32_t lo = excl > b0 ? excl : b0;
                 const int32_t hi = end < b1 ? end : b1;
                 if (lo < hi) {
-                    for (int32_t j = LaneSplit<T>::quot_small(lo - b0 + per - 1, per);
+                    for (int32_t j = quot_small(lo - b0 + per - 1, per);
                          b0 + j * per < hi; ++j)
                         sh.pairof[g * kGroupLanes + j] = (int16_t)tid;
                 }
