@@ -469,7 +469,7 @@ constexpr int kGroups = kThreads / 256;
 constexpr int kGroupLanes = 256;
 // Weights measured on MI355X (per-wave completion times of equal runs):
 // FP64 records, FP32 records.
-constexpr int64_t kGroupWeights[2][4] = {{64, 60, 54, 42}, {64, 60, 54, 46}};
+constexpr int64_t kGroupWeights[2][4] = {{64, 60, 54, 40}, {64, 60, 54, 46}};
 template <typename T>
 __device__ __forceinline__ int64_t group_weight(int g)
 {
