@@ -241,3 +241,33 @@ def test_tiny_tiles_few_active_lanes(n):
         v[o[1:] - 1] = 0.0
         for name in ("l1", "l2sq", "gram"):
             _check_full(name, o, t, v, 1e-12)
+
+
+def test_huge_pcf_wide_step_prefix():
+    # one PCF of 2^25 rows against a block of 32 two-row PCFs: that tile's
+    # step total passes 2^30 (global mode, 64-bit step prefix and lane split)
+    rng = np.random.default_rng(11)
+    n0 = 1 << 25
+    counts = np.array([n0] + [2] * 32)
+    o = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    P = int(o[-1])
+    t = np.empty(P)
+    v = np.empty(P)
+    t[:n0] = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0, n0 - 1))])
+    v[:n0] = rng.standard_normal(n0)
+    v[n0 - 1] = 0.0
+    tmax = t[n0 - 1]
+    for j in range(32):
+        a = n0 + 2 * j
+        t[a], t[a + 1] = 0.0, rng.uniform(0.01, 1.0) * tmax
+        v[a], v[a + 1] = rng.standard_normal(), 0.0
+    X = api.PcfSet(o, t, v, device=DEV)
+    pick_i = np.array([0, 0, 0, 5, 9])
+    pick_j = np.array([3, 17, 32, 0, 21])
+    for name in ("l1", "gram"):
+        fn, okind, p = KINDS[name]
+        M = fn(X).cpu().numpy()
+        assert np.array_equal(M, M.T), name
+        ref, ab = oracle.entries(okind, p, o, t, v, pick_i, pick_j, with_abs=True)
+        err = np.abs(M[pick_i, pick_j] - ref)
+        assert np.all(err <= 1e-12 * np.maximum(ab, 1e-300)), (name, err, ref)
