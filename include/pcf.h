@@ -160,6 +160,25 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
                                  size_t ws_bytes, uint32_t flags,
                                  void *stream);
 
+/* Cross-set matrix of two collections X (rows) and Y (columns): entry
+ * (i, j) is F(X_i, Y_j) for the combination integral F of Section 2.2 (the
+ * pairwise matrix of Section 3.1 taken over two collections instead of one,
+ * e.g. test against training PCFs), written at out[i*ldo + j] (ldo >= Y->n).
+ * kind and p as in pcf_pairwise_lp, or PCF_GRAM (p ignored). X and Y share
+ * their dtype. The library copies both offset arrays to the host unless
+ * offsets_host is given, plans the X x Y rectangle over one CSR of X then Y,
+ * and packs both sets' records into one array of the workspace (size from
+ * pcf_cross_workspace_bytes). Flags: PCF_VALIDATE and the tile shape;
+ * PCF_UPPER_ONLY, PCF_REUSE_PLAN and PCF_RECORDS_PACKED give PCF_EINVAL.
+ * Errors as pcf_pairwise_lp (PCF_EDATA names the set and PCF). */
+pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p,
+                     void *out, int64_t ldo, void *ws, size_t ws_bytes,
+                     uint32_t flags, void *stream);
+
+/* Workspace size for pcf_cross on X and Y, enough for every tile shape. */
+pcf_status pcf_cross_workspace_bytes(const pcf_set *X, const pcf_set *Y,
+                                     size_t *bytes);
+
 /* Many independent full matrices in one persistent launch. `all` is one CSR
  * set holding every problem's PCFs; problem b owns PCFs
  * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)

@@ -72,6 +72,13 @@ _SIGS = {
     "pcf_batched_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p,
                                                    ctypes.POINTER(pcf_set),
                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "pcf_cross": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.POINTER(pcf_set),
+                                 ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
+                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.c_uint32, ctypes.c_void_p]),
+    "pcf_cross_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pcf_set),
+                                                 ctypes.POINTER(pcf_set),
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "pcf_validate": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.POINTER(ctypes.c_int64),
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "pcf_plan_inspect": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
@@ -155,6 +162,18 @@ def pcf_batched_workspace_bytes(B, set_offsets_host_ptr, X):
     out = ctypes.c_size_t(0)
     check(load().pcf_batched_workspace_bytes(B, set_offsets_host_ptr, ctypes.byref(X),
                                              ctypes.byref(out)))
+    return out.value
+
+
+def pcf_cross(X, Y, kind, p, out_ptr, ldo, ws_ptr, ws_bytes, flags, stream):
+    return load().pcf_cross(ctypes.byref(X), ctypes.byref(Y), kind, p, out_ptr, ldo,
+                            ws_ptr, ws_bytes, flags, stream)
+
+
+def pcf_cross_workspace_bytes(X, Y):
+    out = ctypes.c_size_t(0)
+    check(load().pcf_cross_workspace_bytes(ctypes.byref(X), ctypes.byref(Y),
+                                           ctypes.byref(out)))
     return out.value
 
 

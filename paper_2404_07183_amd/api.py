@@ -158,6 +158,39 @@ def gram(X, *, window=None, out=None, upper_only=False, validate=False,
                     stream, packed, shape)
 
 
+def _cross(X, Y, kind, p, out, validate, workspace, stream, shape=None):
+    if X.dtype != Y.dtype:
+        raise ValueError("X and Y must share their dtype")
+    Xc, Yc = X.c_struct(), Y.c_struct()
+    if out is None:
+        out = torch.zeros((X.n, Y.n), dtype=X.dtype, device=X.t.device)
+    if out.dtype != X.dtype or out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a row-major 2-D tensor of the input dtype")
+    ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    ws.ensure(_lib.pcf_cross_workspace_bytes(Xc, Yc))
+    flags = _flags(False, validate, False, shape)
+    check(_lib.pcf_cross(Xc, Yc, kind, float(p), out.data_ptr(), ldo, ws.ptr, ws.nbytes,
+                         flags, _stream_handle(stream)))
+    ws.planned = None  # the cross plan is never reused
+    ws.packed_data = None
+    return out
+
+
+def cdist(X, Y, p=1.0, *, power=False, out=None, validate=False, workspace=None,
+          stream=None, shape=None):
+    """L_p distances (``power=True``: d_p^p) between the PCFs of ``X`` (rows)
+    and those of ``Y`` (columns)."""
+    return _cross(X, Y, PCF_LP_POW if power else PCF_LP, p, out, validate, workspace,
+                  stream, shape)
+
+
+def cross_gram(X, Y, *, out=None, validate=False, workspace=None, stream=None,
+               shape=None):
+    """L2 inner products between the PCFs of ``X`` (rows) and ``Y`` (columns)."""
+    return _cross(X, Y, PCF_GRAM, 0.0, out, validate, workspace, stream, shape)
+
+
 def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None):
     """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, FP64)."""
     Xc = X.c_struct()

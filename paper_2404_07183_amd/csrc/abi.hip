@@ -271,6 +271,51 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
     return PCF_OK;
 }
 
+// The combined CSR of X then Y (host), and the plan of the window
+// [0, nx) x [nx, nx + ny) over it.
+pcf_status cross_plan(const pcf_set *X, const pcf_set *Y, int64_t ldo, uint32_t flags,
+                      hipStream_t s, std::vector<int64_t> &comb, Plan &plan)
+{
+    std::vector<int64_t> xb, yb;
+    const int64_t *xo = X->offsets_host, *yo = Y->offsets_host;
+    pcf_status st = host_offsets(X, xb, xo, s);
+    if (st == PCF_OK)
+        st = host_offsets(Y, yb, yo, s);
+    if (st != PCF_OK)
+        return st;
+    const int64_t nx = X->n, ny = Y->n;
+    comb.resize((size_t)(nx + ny + 1));
+    for (int64_t i = 0; i <= nx; ++i)
+        comb[i] = xo[i];
+    for (int64_t i = 1; i <= ny; ++i)
+        comb[nx + i] = xo[nx] + yo[i];
+    std::string err;
+    if (!plan_matrix(nx + ny, comb.data(), rec_bytes_of(X->dtype), false, true, 0, nx,
+                     nx, nx + ny, false, ldo, shape_of(flags), plan, err))
+        return fail(PCF_EINVAL, err);
+    return PCF_OK;
+}
+
+// Bytes of the cross-set workspace: the plan's, then the combined device
+// offsets.
+int64_t cross_offsets_at(const Plan &plan, int rec_bytes, bool bound)
+{
+    return bound ? plan_workspace_bound(plan, rec_bytes)
+                 : plan_workspace_bytes(plan, rec_bytes);
+}
+
+pcf_status check_pair(const pcf_set *X, const pcf_set *Y)
+{
+    pcf_status st = check_set(X);
+    if (st == PCF_OK)
+        st = check_set(Y);
+    if (st != PCF_OK)
+        return st;
+    if (X->dtype != Y->dtype)
+        return fail(PCF_EINVAL, "X and Y have different dtypes");
+    return PCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -543,6 +588,120 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
     e = launch_backward(hk, a, tile_grid(reuse ? nullptr : &plan, reuse), s);
     if (e != hipSuccess)
         return hip_fail(e, "adjoint kernel launch");
+    return PCF_OK;
+}
+
+pcf_status pcf_cross_workspace_bytes(const pcf_set *X, const pcf_set *Y,
+                                     size_t *bytes)
+{
+    pcf_status st = check_pair(X, Y);
+    if (st != PCF_OK)
+        return st;
+    if (!bytes)
+        return fail(PCF_EINVAL, "bytes is NULL");
+    if (X->n == 0 || Y->n == 0) {
+        *bytes = (size_t)kHeaderBytes;
+        return PCF_OK;
+    }
+    std::vector<int64_t> comb;
+    Plan plan;
+    st = cross_plan(X, Y, Y->n, 0, nullptr, comb, plan);
+    if (st != PCF_OK)
+        return st;
+    *bytes = (size_t)(cross_offsets_at(plan, rec_bytes_of(X->dtype), true) +
+                      align_up((X->n + Y->n + 1) * 8, 256));
+    return PCF_OK;
+}
+
+pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p,
+                     void *out, int64_t ldo, void *ws, size_t ws_bytes,
+                     uint32_t flags, void *stream)
+{
+    pcf_status st = check_pair(X, Y);
+    if (st != PCF_OK)
+        return st;
+    if (kind != PCF_LP && kind != PCF_LP_POW && kind != PCF_GRAM)
+        return fail(PCF_EINVAL, "unknown kind");
+    if (kind != PCF_GRAM && (!(p >= 1.0) || !isfinite(p)))
+        return fail(PCF_EINVAL, "p must be finite and >= 1");
+    if (flags & (PCF_UPPER_ONLY | PCF_REUSE_PLAN | PCF_RECORDS_PACKED))
+        return fail(PCF_EINVAL, "pcf_cross takes neither PCF_UPPER_ONLY nor "
+                                "PCF_REUSE_PLAN nor PCF_RECORDS_PACKED");
+    if (X->n == 0 || Y->n == 0)
+        return PCF_OK;
+    if (!out || !ws)
+        return fail(PCF_EINVAL, "out or ws is NULL");
+    if (ldo < Y->n)
+        return fail(PCF_EINVAL, "ldo smaller than Y->n");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> comb;
+    Plan plan;
+    st = cross_plan(X, Y, ldo, flags, s, comb, plan);
+    if (st != PCF_OK)
+        return st;
+    const int rb = rec_bytes_of(X->dtype);
+    const int64_t at = cross_offsets_at(plan, rb, false);
+    const int64_t need = at + align_up((X->n + Y->n + 1) * 8, 256);
+    if ((int64_t)ws_bytes < need)
+        return fail(PCF_ENOMEM, "workspace too small: need " + std::to_string(need) +
+                                    " bytes, got " + std::to_string(ws_bytes));
+    st = upload_plan(plan, rb, ws, ws_bytes, s);
+    if (st != PCF_OK)
+        return st;
+    unsigned char *w = (unsigned char *)ws;
+    if (flags & PCF_VALIDATE) {
+        const pcf_set *sets[2] = {X, Y};
+        for (int q = 0; q < 2; ++q) {
+            int64_t bad = -1;
+            const int64_t P = comb[q == 0 ? X->n : X->n + Y->n] - (q == 0 ? 0 : comb[X->n]);
+            st = run_validation(sets[q], w, P, s, &bad);
+            if (st != PCF_OK)
+                return st;
+            if (bad >= 0)
+                return fail(PCF_EDATA, std::string(q == 0 ? "X" : "Y") + " PCF " +
+                                           std::to_string(bad) +
+                                           " breaks the data contract (first time "
+                                           "0, strictly increasing finite times, "
+                                           "finite values, last value 0)");
+        }
+    }
+    // one record array: X's records, then Y's (starting past X's records and
+    // padding), indexed through the combined offsets
+    int64_t *coff = reinterpret_cast<int64_t *>(w + at);
+    const int64_t px = comb[X->n], py = comb[X->n + Y->n] - px;
+    const int64_t ybase = px + X->n * kPad;
+    hipError_t e = launch_reset(w, s);
+    if (e == hipSuccess)
+        e = launch_concat_offsets(X->offsets, X->n, Y->offsets, Y->n, coff, s);
+    if (e == hipSuccess)
+        e = X->dtype == PCF_F64
+                ? launch_pack<double>(X->offsets, X->n, X->t, X->v, w, px, s, 0)
+                : launch_pack<float>(X->offsets, X->n, X->t, X->v, w, px, s, 0);
+    if (e == hipSuccess)
+        e = X->dtype == PCF_F64
+                ? launch_pack<double>(Y->offsets, Y->n, Y->t, Y->v, w, py, s, ybase)
+                : launch_pack<float>(Y->offsets, Y->n, Y->t, Y->v, w, py, s, ybase);
+    if (e != hipSuccess)
+        return hip_fail(e, "packing breakpoint records");
+
+    FwdArgs a;
+    a.offsets = coff;
+    a.ws = w;
+    a.out = out;
+    a.p = p;
+    a.inv_p = 1.0 / p;
+    a.gram = kind == PCF_GRAM ? 1 : 0;
+    int hk;
+    if (kind == PCF_GRAM) {
+        hk = HK_PROD;
+        a.root = 0;
+    } else {
+        hk = (p == 1.0) ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW);
+        a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
+    }
+    e = launch_forward(X->dtype == PCF_F64, hk, a, tile_grid(&plan, false), s);
+    if (e != hipSuccess)
+        return hip_fail(e, "tile kernel launch");
     return PCF_OK;
 }
 

@@ -57,14 +57,16 @@ __global__ void reset_counters(unsigned char *ws)
 
 // ---------------------------------------------------------------------------
 // Pack CSR (t, v) rows into breakpoint records (see the file comment).
-// Grid-stride over rows; P comes from offsets[n] on the device.
+// Grid-stride over rows; P comes from offsets[n] on the device. The set's
+// records start at record rec_base (0, or past a first set's records when
+// two sets share one record array).
 template <typename T>
 __global__ void pack_records(const int64_t *__restrict__ offsets, int64_t n,
                              const T *__restrict__ t, const T *__restrict__ v,
-                             unsigned char *ws)
+                             unsigned char *ws, int64_t rec_base)
 {
     const WsHeader &h = hdr_of(ws);
-    Rec<T> *rec = reinterpret_cast<Rec<T> *>(ws + h.off_rec);
+    Rec<T> *rec = reinterpret_cast<Rec<T> *>(ws + h.off_rec) + rec_base;
     const int64_t P = offsets[n];
     const T S = sentinel<T>();
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < P;
@@ -403,7 +405,7 @@ size_t tile_shared_bytes(int rec_bytes, bool backward)
 template <typename T>
 hipError_t launch_pack(const int64_t *offsets, int64_t n, const void *t,
                        const void *v, unsigned char *ws, int64_t P,
-                       hipStream_t s)
+                       hipStream_t s, int64_t rec_base)
 {
     if (P <= 0)
         return hipSuccess;
@@ -411,7 +413,30 @@ hipError_t launch_pack(const int64_t *offsets, int64_t n, const void *t,
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(pack_records<T>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       offsets, n, (const T *)t, (const T *)v, ws);
+                       offsets, n, (const T *)t, (const T *)v, ws, rec_base);
+    return hipGetLastError();
+}
+
+// The offsets of set X followed by those of set Y shifted by X's row count:
+// one CSR over both sets (device; Y's rows come after X's).
+__global__ void concat_offsets(const int64_t *__restrict__ xo, int64_t nx,
+                               const int64_t *__restrict__ yo, int64_t ny,
+                               int64_t *__restrict__ out)
+{
+    const int64_t px = xo[nx];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= nx + ny;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = i <= nx ? xo[i] : px + yo[i - nx];
+}
+
+hipError_t launch_concat_offsets(const int64_t *xo, int64_t nx, const int64_t *yo,
+                                 int64_t ny, int64_t *out, hipStream_t s)
+{
+    int64_t blocks = (nx + ny + 1 + 255) / 256;
+    if (blocks > 1024)
+        blocks = 1024;
+    hipLaunchKernelGGL(concat_offsets, dim3((unsigned)blocks), dim3(256), 0, s, xo,
+                       nx, yo, ny, out);
     return hipGetLastError();
 }
 
@@ -481,10 +506,10 @@ hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
 
 template hipError_t launch_pack<float>(const int64_t *, int64_t, const void *,
                                        const void *, unsigned char *, int64_t,
-                                       hipStream_t);
+                                       hipStream_t, int64_t);
 template hipError_t launch_pack<double>(const int64_t *, int64_t, const void *,
                                         const void *, unsigned char *, int64_t,
-                                        hipStream_t);
+                                        hipStream_t, int64_t);
 template hipError_t launch_validate<float>(const int64_t *, int64_t,
                                            const void *, const void *,
                                            unsigned char *, int64_t,

@@ -41,7 +41,9 @@ struct BwdArgs {
 template <typename T>
 hipError_t launch_pack(const int64_t *offsets, int64_t n, const void *t,
                        const void *v, unsigned char *ws, int64_t P,
-                       hipStream_t s);
+                       hipStream_t s, int64_t rec_base = 0);
+hipError_t launch_concat_offsets(const int64_t *xo, int64_t nx, const int64_t *yo,
+                                 int64_t ny, int64_t *out, hipStream_t s);
 template <typename T>
 hipError_t launch_validate(const int64_t *offsets, int64_t n, const void *t,
                            const void *v, unsigned char *ws, int64_t P,
