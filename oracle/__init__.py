@@ -28,6 +28,7 @@ import subprocess
 import numpy as np
 
 LP, LP_POW, GRAM = 0, 1, 2
+S_INTEGRAL, S_NORM, S_NORM_POW = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcf_oracle.c")
@@ -72,6 +73,10 @@ def _load():
         lib.orc_backward.argtypes = [ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int64, _I64P, _F64P, _F64P,
                                      _F64P, _F64P, _F64P]
+        lib.orc_single.restype = ctypes.c_int
+        lib.orc_single.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int64, _I64P, _F64P,
+                                   _F64P, _F64P, _F64P]
         _lib = lib
     return _lib
 
@@ -146,3 +151,19 @@ def backward(kind, p, offsets, t, v, G):
     if rc:
         raise MemoryError("oracle: allocation failed")
     return gt, gv
+
+
+def single(kind, p, a, b, offsets, t, v, with_abs=False):
+    """F(f_i) = r(int_a^b h(f_i)) for every PCF of a CSR set (Section 3.2,
+    segment iteration); ``b`` may be ``inf``."""
+    lib = _load()
+    offsets, t, v = _i64(offsets), _f64(t), _f64(v)
+    n = len(offsets) - 1
+    out = np.empty(n, dtype=np.float64)
+    ab = np.empty(n, dtype=np.float64)
+    rc = lib.orc_single(int(kind), float(p), float(a), float(b), n, _p(offsets, _I64P),
+                        _p(t, _F64P), _p(v, _F64P), _p(out, _F64P), _p(ab, _F64P))
+    if rc:
+        raise ValueError("oracle: need 0 <= a < b")
+    return (out, ab) if with_abs else out
+

@@ -33,6 +33,9 @@
  * definition of a PCF, and sums the cells left to right with one rounding
  * per multiply and per add (build with -ffp-contract=off, no fast-math).
  *
+ * Single-PCF functionals F(f) = r(int_a^b h(f)) (Section 3.2) follow
+ * Algorithm IterateSegments: see orc_single below.
+ *
  * The adjoint (derivatives of F with respect to the values v_k and the
  * breakpoint times t_k, k >= 1) is not in the paper. Its reading:
  *   dI/dv_f[k] = sum over cells r where f takes its k-th value of
@@ -355,6 +358,97 @@ int orc_backward(int kind, double p, int64_t n_pcf, const int64_t *offsets,
         }
     }
     free(s);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Single-PCF functionals (Section 3.2, "PCF integrals"):                   */
+/*     F(f) = r( int_a^b h(f(t)) dt ),  0 <= a < b <= inf,                   */
+/* by segment iteration (Algorithm IterateSegments): start at t = a in the   */
+/* piece that contains a; each later breakpoint t_i closes the segment       */
+/* [t, min(t_i, b)) of the current value, the walk stops once t_i >= b; the  */
+/* last segment runs from the current left end to b. Each segment (l, r, v)  */
+/* adds (r - l) h(v), left to right. With b = inf the last segment adds 0    */
+/* when h(v) = 0 and an infinity of the sign of h(v) otherwise.              */
+/*   ORC_S_INTEGRAL  h(v) = v                                               */
+/*   ORC_S_NORM      h(v) = |v|^p, r(x) = x^(1/p)                           */
+/*   ORC_S_NORM_POW  h(v) = |v|^p, r(x) = x                                 */
+enum { ORC_S_INTEGRAL = 0, ORC_S_NORM = 1, ORC_S_NORM_POW = 2 };
+
+static double h_single(int kind, double p, double v)
+{
+    if (kind == ORC_S_INTEGRAL)
+        return v;
+    double a = fabs(v);
+    if (p == 1.0)
+        return a;
+    if (p == 2.0)
+        return a * a;
+    return pow(a, p);
+}
+
+static double segment_sum(int kind, double p, double a, double b, const double *t,
+                          const double *v, int64_t n, double *abs_out)
+{
+    double acc = 0.0, acc_abs = 0.0;
+    double l = a;
+    int64_t k = piece_at(t, n, a);
+    double val = v[k];
+    int done = 0;
+    for (int64_t i = k + 1; i < n; ++i) {
+        double r = t[i] < b ? t[i] : b;
+        double c = (r - l) * h_single(kind, p, val);
+        acc = acc + c;
+        acc_abs = acc_abs + fabs(c);
+        if (t[i] >= b) {
+            done = 1;
+            break;
+        }
+        l = t[i];
+        val = v[i];
+    }
+    if (!done) {
+        double hv = h_single(kind, p, val);
+        if (isinf(b)) {
+            if (hv != 0.0) {
+                acc = acc + (hv > 0.0 ? INFINITY : -INFINITY);
+                acc_abs = INFINITY;
+            }
+        } else {
+            double c = (b - l) * hv;
+            acc = acc + c;
+            acc_abs = acc_abs + fabs(c);
+        }
+    }
+    if (abs_out)
+        *abs_out = acc_abs;
+    return acc;
+}
+
+/* F(f_i) for every PCF of a CSR set; abs_out[i] (optional) = sum over
+ * segments of |h| * width. Returns 0, or -1 on bad arguments. */
+int orc_single(int kind, double p, double a, double b, int64_t n_pcf,
+               const int64_t *offsets, const double *t, const double *v,
+               double *out, double *abs_out)
+{
+    if (!(a >= 0.0) || !(b > a))
+        return -1;
+    for (int64_t i = 0; i < n_pcf; ++i) {
+        const int64_t o = offsets[i], n = offsets[i + 1] - offsets[i];
+        double ab = 0.0;
+        double I;
+        if (n < 1 || !pcf_ok(t + o, v + o, n)) {
+            I = NAN;
+            ab = NAN;
+        } else {
+            I = segment_sum(kind, p, a, b, t + o, v + o, n, &ab);
+        }
+        if (kind == ORC_S_NORM && p != 1.0)
+            I = p == 2.0 ? sqrt(I) : pow(I, 1.0 / p);
+        out[i] = I;
+        if (abs_out)
+            abs_out[i] = ab;
+    }
     return 0;
 }
 
