@@ -179,6 +179,25 @@ pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p
 pcf_status pcf_cross_workspace_bytes(const pcf_set *X, const pcf_set *Y,
                                      size_t *bytes);
 
+/* Functionals of one PCF at a time (paper, Section 3.2 "PCF integrals"):
+ *   F(f) = r( int_a^b h(f(t)) dt ),   0 <= a < b <= inf (b may be INFINITY),
+ * by segment iteration (Algorithm IterateSegments):
+ *   PCF_INTEGRAL  h(v) = v                         (p ignored)
+ *   PCF_NORM      h(v) = |v|^p, r(x) = x^(1/p)     (the L_p norm, p >= 1)
+ *   PCF_NORM_POW  h(v) = |v|^p, r(x) = x
+ * out[i] (n entries of X's dtype, device) = F(f_i). With b = inf a nonzero
+ * last value gives an infinity of the sign of h. Asynchronous on `stream`;
+ * no workspace, no host copy. PCF_EINVAL on bad arguments (bounds, p,
+ * kind, NULL pointers). */
+typedef enum {
+    PCF_INTEGRAL = 0,
+    PCF_NORM = 1,
+    PCF_NORM_POW = 2
+} pcf_single_kind;
+
+pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a,
+                      double b, void *out, void *stream);
+
 /* Many independent full matrices in one persistent launch. `all` is one CSR
  * set holding every problem's PCFs; problem b owns PCFs
  * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)

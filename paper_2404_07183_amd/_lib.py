@@ -17,6 +17,7 @@ PCF_F32, PCF_F64 = 0, 1
 PCF_LP, PCF_LP_POW, PCF_GRAM = 0, 1, 2
 PCF_UPPER_ONLY, PCF_VALIDATE, PCF_DETERMINISTIC, PCF_REUSE_PLAN = 1, 2, 4, 8
 PCF_RECORDS_PACKED = 16
+PCF_INTEGRAL, PCF_NORM, PCF_NORM_POW = 0, 1, 2
 
 STATUS_NAMES = {0: "PCF_OK", 1: "PCF_EINVAL", 2: "PCF_EDATA", 3: "PCF_EDEVICE",
                 4: "PCF_ENOMEM", 5: "PCF_EUNSUPPORTED"}
@@ -72,6 +73,9 @@ _SIGS = {
     "pcf_batched_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p,
                                                    ctypes.POINTER(pcf_set),
                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "pcf_single": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
     "pcf_cross": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.POINTER(pcf_set),
                                  ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t,
@@ -163,6 +167,10 @@ def pcf_batched_workspace_bytes(B, set_offsets_host_ptr, X):
     check(load().pcf_batched_workspace_bytes(B, set_offsets_host_ptr, ctypes.byref(X),
                                              ctypes.byref(out)))
     return out.value
+
+
+def pcf_single(X, kind, p, a, b, out_ptr, stream):
+    return load().pcf_single(ctypes.byref(X), kind, p, a, b, out_ptr, stream)
 
 
 def pcf_cross(X, Y, kind, p, out_ptr, ldo, ws_ptr, ws_bytes, flags, stream):

@@ -9,6 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
+import math
+
 import numpy as np
 import torch
 
@@ -189,6 +191,26 @@ def cross_gram(X, Y, *, out=None, validate=False, workspace=None, stream=None,
                shape=None):
     """L2 inner products between the PCFs of ``X`` (rows) and ``Y`` (columns)."""
     return _cross(X, Y, PCF_GRAM, 0.0, out, validate, workspace, stream, shape)
+
+
+def _single(X, kind, p, a, b, out, stream):
+    if out is None:
+        out = torch.empty(X.n, dtype=X.dtype, device=X.t.device)
+    if out.dtype != X.dtype or out.numel() != X.n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous vector of n entries of the input dtype")
+    check(_lib.pcf_single(X.c_struct(), kind, float(p), float(a), float(b),
+                          out.data_ptr(), _stream_handle(stream)))
+    return out
+
+
+def integrals(X, a=0.0, b=math.inf, *, out=None, stream=None):
+    """int_a^b f_i for every PCF of ``X`` (Section 3.2)."""
+    return _single(X, _lib.PCF_INTEGRAL, 1.0, a, b, out, stream)
+
+
+def norms(X, p=2.0, a=0.0, b=math.inf, *, power=False, out=None, stream=None):
+    """L_p norms (``power=True``: int |f_i|^p) of the PCFs of ``X`` over [a, b)."""
+    return _single(X, _lib.PCF_NORM_POW if power else _lib.PCF_NORM, p, a, b, out, stream)
 
 
 def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None):

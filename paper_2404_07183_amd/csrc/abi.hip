@@ -705,4 +705,43 @@ pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p
     return PCF_OK;
 }
 
+pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a,
+                      double b, void *out, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (kind != PCF_INTEGRAL && kind != PCF_NORM && kind != PCF_NORM_POW)
+        return fail(PCF_EINVAL, "unknown single-PCF kind");
+    if (kind != PCF_INTEGRAL && (!(p >= 1.0) || !isfinite(p)))
+        return fail(PCF_EINVAL, "p must be finite and >= 1");
+    if (!(a >= 0.0) || !isfinite(a) || !(b > a))
+        return fail(PCF_EINVAL, "the bounds must satisfy 0 <= a < b (b may be inf)");
+    if (X->n == 0)
+        return PCF_OK;
+    if (!out)
+        return fail(PCF_EINVAL, "out is NULL");
+    SingleArgs g;
+    g.offsets = X->offsets;
+    g.n = X->n;
+    g.t = X->t;
+    g.v = X->v;
+    g.out = out;
+    g.a = a;
+    g.b = b;
+    g.p = p;
+    int sk;
+    if (kind == PCF_INTEGRAL) {
+        sk = 0;
+        g.root = 0;
+    } else {
+        sk = p == 1.0 ? 1 : (p == 2.0 ? 2 : 3);
+        g.root = (kind == PCF_NORM_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
+    }
+    hipError_t e = launch_single(X->dtype == PCF_F64, sk, g, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "single-PCF kernel launch");
+    return PCF_OK;
+}
+
 }  // extern "C"

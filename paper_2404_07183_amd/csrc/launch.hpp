@@ -48,6 +48,17 @@ template <typename T>
 hipError_t launch_validate(const int64_t *offsets, int64_t n, const void *t,
                            const void *v, unsigned char *ws, int64_t P,
                            hipStream_t s);
+// Single-PCF functionals (single.hip).
+struct SingleArgs {
+    const int64_t *offsets;
+    int64_t n;
+    const void *t, *v;
+    void *out;
+    double a, b;  // integration bounds, 0 <= a < b <= inf
+    double p;
+    int root;     // 0: none, 1: sqrt, 2: x^(1/p)
+};
+hipError_t launch_single(bool f64, int sk, const SingleArgs &a, hipStream_t s);
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);
