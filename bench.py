@@ -311,6 +311,52 @@ def run_cross(steps, warmup, plain_steps_per_s=None):
     return res
 
 
+def run_single(steps, warmup):
+    """L2 norms of the plain 20,000-PCF set (FP64) by segment iteration: one
+    pass over the rows, so HBM-bound; bytes = t and v of every row plus the
+    offsets read, one value per PCF written."""
+    import torch
+
+    import oracle
+    from paper_2404_07183_amd import api, workloads
+
+    o, t, v = workloads.config_plain()
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    out = torch.empty(X.n, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    call = lambda: api.norms(X, 2.0, out=out)
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    # a call takes microseconds: 50 calls captured in a graph and replayed,
+    # so that launch gaps do not count
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(50):
+                call()
+    stream.wait_stream(s)
+    torch.cuda.synchronize()
+    ms = _events_ms(g.replay, steps, stream) / 50
+    P = int(o[-1])
+    nbytes = P * 16 + (X.n + 1) * 8 + X.n * 8
+    ref, ab = oracle.single(oracle.S_NORM, 2.0, 0.0, np.inf, o, t, v, with_abs=True)
+    got = out.cpu().numpy()
+    return {"workload": "L2 norms of N=20000 PCFs (counts U{50..500}), FP64, one call",
+            "pcfs": int(X.n), "rows": P, "ms_per_call": ms,
+            "pcfs_per_s": X.n / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
+                         "peak": 8000.0, "unit": "GB/s",
+                         "frac": nbytes / (ms * 1e-3) / 1e9 / 8000.0,
+                         "bytes_per_call": nbytes},
+            "parity": {"pcfs": int(X.n),
+                       "max_error_over_scale": float(np.max(np.abs(got - ref) /
+                                                            np.maximum(np.sqrt(ab), 1e-300))),
+                       "tolerance": 1e-12}}
+
+
 def run_grad(steps, warmup, plain_steps_per_s=None):
     """Forward + adjoint of L = sum W_ij d_2(f_i,f_j)^2 + sum U_ij <f_i,f_j>,
     N = 4,096 PCFs, FP64 (two forward matrices, two adjoint passes)."""
@@ -458,6 +504,7 @@ def main():
         res["batched"] = run_batched(max(2, args.steps // 2), 1, plain)
         res["fwd_bwd"] = run_grad(max(2, args.steps // 2), 1, plain)
         res["cross"] = run_cross(max(2, args.steps // 2), 1, plain)
+        res["single"] = run_single(max(2, args.steps // 2), 1)
     print(json.dumps(res), flush=True)
 
 
