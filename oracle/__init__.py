@@ -73,6 +73,11 @@ def _load():
         lib.orc_backward.argtypes = [ctypes.c_int, ctypes.c_double,
                                      ctypes.c_int64, _I64P, _F64P, _F64P,
                                      _F64P, _F64P, _F64P]
+        lib.orc_entries_ab.restype = ctypes.c_int
+        lib.orc_entries_ab.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int64, _I64P, _F64P,
+                                       _F64P, ctypes.c_int64, _I64P, _I64P, _F64P,
+                                       _F64P]
         lib.orc_single.restype = ctypes.c_int
         lib.orc_single.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_int64, _I64P, _F64P,
@@ -121,6 +126,21 @@ def entries(kind, p, offsets, t, v, I, J, with_abs=False):
                          _p(ab, _F64P))
     if rc:
         raise ValueError("oracle: bad pair index")
+    return (out, ab) if with_abs else out
+
+
+def entries_ab(kind, p, a, b, offsets, t, v, I, J, with_abs=False):
+    """As ``entries`` over the integration range [a, b) (Section 2.2)."""
+    lib = _load()
+    offsets, t, v = _i64(offsets), _f64(t), _f64(v)
+    I, J = _i64(I), _i64(J)
+    out = np.empty(len(I), dtype=np.float64)
+    ab = np.empty(len(I), dtype=np.float64)
+    rc = lib.orc_entries_ab(int(kind), float(p), float(a), float(b), len(offsets) - 1,
+                            _p(offsets, _I64P), _p(t, _F64P), _p(v, _F64P), len(I),
+                            _p(I, _I64P), _p(J, _I64P), _p(out, _F64P), _p(ab, _F64P))
+    if rc:
+        raise ValueError("oracle: bad pair index or bounds")
     return (out, ab) if with_abs else out
 
 

@@ -149,13 +149,16 @@ static int64_t piece_before(const double *t, int64_t n, double x)
     return lo;
 }
 
-/* I_h(f, g) by Eq. simpleint over the union grid. scratch holds nf + ng
- * doubles. *abs_out (optional) receives sum |h| * width, the scale used
- * for cancellation-aware tolerances. Returns NaN when either PCF breaks
- * the contract. */
-static double integral(int kind, double p, const double *tf, const double *vf,
-                       int64_t nf, const double *tg, const double *vg,
-                       int64_t ng, double *scratch, double *abs_out)
+/* I_h(f, g) by Eq. simpleint over the union grid, restricted to the
+ * integration range [a, b) of Section 2.2 (0 <= a < b <= inf): each cell
+ * [s_r, s_{r+1}) counts with its part inside [a, b). scratch holds nf + ng
+ * doubles. *abs_out (optional) receives sum |h| * width, the scale used for
+ * cancellation-aware tolerances. Returns NaN when either PCF breaks the
+ * contract. */
+static double integral_ab(int kind, double p, double a, double b, const double *tf,
+                          const double *vf, int64_t nf, const double *tg,
+                          const double *vg, int64_t ng, double *scratch,
+                          double *abs_out)
 {
     if (!pcf_ok(tf, vf, nf) || !pcf_ok(tg, vg, ng)) {
         if (abs_out)
@@ -174,20 +177,38 @@ static double integral(int kind, double p, const double *tf, const double *vf,
         while (kg + 1 < ng && tg[kg + 1] <= x)
             ++kg;
         double hv = h_val(kind, p, vf[kf], vg[kg]);
+        /* the cell's part inside [a, b) */
+        double l = x < a ? a : x;
         if (r + 1 < m) {
-            double w = scratch[r + 1] - x;
+            double rr = scratch[r + 1] > b ? b : scratch[r + 1];
+            double w = rr > l ? rr - l : 0.0;
             double c = hv * w;
             acc = acc + c;
             acc_abs = acc_abs + fabs(c);
-        } else if (hv != 0.0) {
+        } else if (isinf(b)) {
             /* unbounded last cell */
-            acc = acc + (hv > 0.0 ? INFINITY : -INFINITY);
-            acc_abs = INFINITY;
+            if (hv != 0.0) {
+                acc = acc + (hv > 0.0 ? INFINITY : -INFINITY);
+                acc_abs = INFINITY;
+            }
+        } else {
+            double w = b > l ? b - l : 0.0;
+            double c = hv * w;
+            acc = acc + c;
+            acc_abs = acc_abs + fabs(c);
         }
     }
     if (abs_out)
         *abs_out = acc_abs;
     return acc;
+}
+
+static double integral(int kind, double p, const double *tf, const double *vf,
+                       int64_t nf, const double *tg, const double *vg,
+                       int64_t ng, double *scratch, double *abs_out)
+{
+    return integral_ab(kind, p, 0.0, INFINITY, tf, vf, nf, tg, vg, ng, scratch,
+                       abs_out);
 }
 
 static double finish(int kind, double p, double I)
@@ -245,6 +266,41 @@ int orc_entries(int kind, double p, int64_t n_pcf, const int64_t *offsets,
         double ab = 0.0;
         double Iv = integral(kind, p, t + oa, v + oa, offsets[a + 1] - oa,
                              t + ob, v + ob, offsets[b + 1] - ob, s, &ab);
+        out[k] = finish(kind, p, Iv);
+        if (abs_out)
+            abs_out[k] = ab;
+    }
+    free(s);
+    return 0;
+}
+
+/* As orc_entries over the integration range [a, b) (0 <= a < b <= inf). */
+int orc_entries_ab(int kind, double p, double a, double b, int64_t n_pcf,
+                   const int64_t *offsets, const double *t, const double *v,
+                   int64_t npairs, const int64_t *I, const int64_t *J, double *out,
+                   double *abs_out)
+{
+    if (!(a >= 0.0) || !(b > a))
+        return -1;
+    int64_t nmax = 0;
+    for (int64_t i = 0; i < n_pcf; ++i) {
+        int64_t n = offsets[i + 1] - offsets[i];
+        if (n > nmax)
+            nmax = n;
+    }
+    double *s = (double *)malloc(sizeof(double) * (size_t)(2 * nmax + 1));
+    if (!s)
+        return -1;
+    for (int64_t k = 0; k < npairs; ++k) {
+        int64_t i = I[k], j = J[k];
+        if (i < 0 || j < 0 || i >= n_pcf || j >= n_pcf) {
+            free(s);
+            return -1;
+        }
+        const int64_t oi = offsets[i], oj = offsets[j];
+        double ab = 0.0;
+        double Iv = integral_ab(kind, p, a, b, t + oi, v + oi, offsets[i + 1] - oi,
+                                t + oj, v + oj, offsets[j + 1] - oj, s, &ab);
         out[k] = finish(kind, p, Iv);
         if (abs_out)
             abs_out[k] = ab;
