@@ -198,6 +198,23 @@ typedef enum {
 pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a,
                       double b, void *out, void *stream);
 
+/* Restriction to an integration range (Section 2.2: combination integrals
+ * over [a, b), 0 <= a < b <= inf). f 1_[a,b) is a PCF again, and h(0,0) = 0
+ * for every kind, so any entry point run on the restricted set computes its
+ * integrals over [a, b) (e.g. pcf_pairwise_lp gives (int_a^b |f-g|^p)^(1/p)).
+ * Rows of the restriction of f: (0, 0) and (a, f(a)) when a > 0, else
+ * (0, f(0)); the rows of f with a < t_k < b; (b, 0) when b is finite. a and
+ * b are rounded to the set's dtype and must stay ordered (PCF_EINVAL).
+ * Two calls: pcf_restrict_rows writes the restricted set's offsets to
+ * offsets_out (device, n+1) and to offsets_out_host (host, n+1), and
+ * synchronises; the caller then allocates t_out and v_out with
+ * offsets_out_host[n] entries of X's dtype and calls pcf_restrict
+ * (asynchronous), which fills them. */
+pcf_status pcf_restrict_rows(const pcf_set *X, double a, double b, int64_t *offsets_out,
+                             int64_t *offsets_out_host, void *stream);
+pcf_status pcf_restrict(const pcf_set *X, double a, double b, const int64_t *offsets_out,
+                        void *t_out, void *v_out, void *stream);
+
 /* Many independent full matrices in one persistent launch. `all` is one CSR
  * set holding every problem's PCFs; problem b owns PCFs
  * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)

@@ -73,6 +73,12 @@ _SIGS = {
     "pcf_batched_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p,
                                                    ctypes.POINTER(pcf_set),
                                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "pcf_restrict_rows": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "pcf_restrict": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p]),
     "pcf_single": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                   ctypes.c_void_p]),
@@ -167,6 +173,16 @@ def pcf_batched_workspace_bytes(B, set_offsets_host_ptr, X):
     check(load().pcf_batched_workspace_bytes(B, set_offsets_host_ptr, ctypes.byref(X),
                                              ctypes.byref(out)))
     return out.value
+
+
+def pcf_restrict_rows(X, a, b, offsets_out_ptr, offsets_out_host_ptr, stream):
+    return load().pcf_restrict_rows(ctypes.byref(X), a, b, offsets_out_ptr,
+                                    offsets_out_host_ptr, stream)
+
+
+def pcf_restrict(X, a, b, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
+    return load().pcf_restrict(ctypes.byref(X), a, b, offsets_out_ptr, t_out_ptr,
+                               v_out_ptr, stream)
 
 
 def pcf_single(X, kind, p, a, b, out_ptr, stream):

@@ -144,18 +144,24 @@ def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
 
 
 def pdist(X, p=1.0, *, power=False, window=None, out=None, upper_only=False,
-          validate=False, workspace=None, stream=None, packed=False, shape=None):
-    """L_p distance matrix (``power=True``: d_p^p) of the PCFs in ``X``.
+          validate=False, workspace=None, stream=None, packed=False, shape=None,
+          bounds=None):
+    """L_p distance matrix (``power=True``: d_p^p) of the PCFs in ``X``;
+    ``bounds=(a, b)``: of the integrals over [a, b) (Section 2.2).
 
     ``packed=True`` skips re-packing the breakpoint records: only valid when
     ``workspace`` served the previous call on this very set and data."""
+    if bounds is not None:
+        X = restrict(X, *bounds, stream=stream)
     return _forward(X, PCF_LP_POW if power else PCF_LP, p, window, out, upper_only,
                     validate, workspace, stream, packed, shape)
 
 
 def gram(X, *, window=None, out=None, upper_only=False, validate=False,
-         workspace=None, stream=None, packed=False, shape=None):
-    """L2 Gram matrix of the PCFs in ``X``."""
+         workspace=None, stream=None, packed=False, shape=None, bounds=None):
+    """L2 Gram matrix of the PCFs in ``X`` (``bounds=(a, b)``: over [a, b))."""
+    if bounds is not None:
+        X = restrict(X, *bounds, stream=stream)
     return _forward(X, PCF_GRAM, 0.0, window, out, upper_only, validate, workspace,
                     stream, packed, shape)
 
@@ -180,17 +186,42 @@ def _cross(X, Y, kind, p, out, validate, workspace, stream, shape=None):
 
 
 def cdist(X, Y, p=1.0, *, power=False, out=None, validate=False, workspace=None,
-          stream=None, shape=None):
+          stream=None, shape=None, bounds=None):
     """L_p distances (``power=True``: d_p^p) between the PCFs of ``X`` (rows)
-    and those of ``Y`` (columns)."""
+    and those of ``Y`` (columns); ``bounds=(a, b)``: over [a, b)."""
+    if bounds is not None:
+        X, Y = restrict(X, *bounds, stream=stream), restrict(Y, *bounds, stream=stream)
     return _cross(X, Y, PCF_LP_POW if power else PCF_LP, p, out, validate, workspace,
                   stream, shape)
 
 
 def cross_gram(X, Y, *, out=None, validate=False, workspace=None, stream=None,
-               shape=None):
-    """L2 inner products between the PCFs of ``X`` (rows) and ``Y`` (columns)."""
+               shape=None, bounds=None):
+    """L2 inner products between the PCFs of ``X`` (rows) and ``Y`` (columns);
+    ``bounds=(a, b)``: over [a, b)."""
+    if bounds is not None:
+        X, Y = restrict(X, *bounds, stream=stream), restrict(Y, *bounds, stream=stream)
     return _cross(X, Y, PCF_GRAM, 0.0, out, validate, workspace, stream, shape)
+
+
+def restrict(X, a, b, stream=None):
+    """The PCFs of ``X`` times the indicator of [a, b) (a new set on the same
+    device): any matrix of the result is the matrix of integrals over
+    [a, b) (Section 2.2). ``b`` may be ``inf``."""
+    Xc = X.c_struct()
+    off_h = np.empty(X.n + 1, dtype=np.int64)
+    off_d = torch.empty(X.n + 1, dtype=torch.int64, device=X.t.device)
+    check(_lib.pcf_restrict_rows(Xc, float(a), float(b), off_d.data_ptr(),
+                                 off_h.ctypes.data, _stream_handle(stream)))
+    rows = int(off_h[-1])
+    t = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    v = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    check(_lib.pcf_restrict(Xc, float(a), float(b), off_d.data_ptr(), t.data_ptr(),
+                            v.data_ptr(), _stream_handle(stream)))
+    new = object.__new__(PcfSet)
+    new.offsets_host, new.offsets, new.n = off_h, off_d, X.n
+    new.t, new.v = t, v
+    return new
 
 
 def _single(X, kind, p, a, b, out, stream):

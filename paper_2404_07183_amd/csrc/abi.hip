@@ -316,6 +316,20 @@ pcf_status check_pair(const pcf_set *X, const pcf_set *Y)
     return PCF_OK;
 }
 
+// The bounds of a restriction in the set's precision: 0 <= a < b <= inf,
+// both still ordered (and b still finite when given finite) once rounded.
+pcf_status check_range(const pcf_set *X, double a, double b)
+{
+    if (!(a >= 0.0) || !isfinite(a) || !(b > a))
+        return fail(PCF_EINVAL, "the bounds must satisfy 0 <= a < b (b may be inf)");
+    if (X->dtype == PCF_F32) {
+        const float fa = (float)a, fb = (float)b;
+        if (!(fb > fa) || (isfinite(b) && !isfinite(fb)))
+            return fail(PCF_EINVAL, "the bounds are not ordered once rounded to FP32");
+    }
+    return PCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -741,6 +755,69 @@ pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a
     hipError_t e = launch_single(X->dtype == PCF_F64, sk, g, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "single-PCF kernel launch");
+    return PCF_OK;
+}
+
+pcf_status pcf_restrict_rows(const pcf_set *X, double a, double b, int64_t *offsets_out,
+                             int64_t *offsets_out_host, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    st = check_range(X, a, b);
+    if (st != PCF_OK)
+        return st;
+    if (!offsets_out || !offsets_out_host)
+        return fail(PCF_EINVAL, "offsets_out or offsets_out_host is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = X->n;
+    if (n == 0) {
+        offsets_out_host[0] = 0;
+        hipError_t e = hipMemcpyAsync(offsets_out, offsets_out_host, sizeof(int64_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        return e == hipSuccess ? PCF_OK : hip_fail(e, "writing the offsets");
+    }
+    // rows per restricted PCF into offsets_out[1..n], then the prefix sum
+    hipError_t e = launch_restrict_count(X->dtype == PCF_F64, X->offsets, n, X->t, a, b,
+                                         offsets_out, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(offsets_out_host, offsets_out, sizeof(int64_t) * (size_t)(n + 1),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "counting the restricted rows");
+    for (int64_t i = 0; i < n; ++i)
+        offsets_out_host[i + 1] += offsets_out_host[i];
+    e = hipMemcpyAsync(offsets_out, offsets_out_host, sizeof(int64_t) * (size_t)(n + 1),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // offsets_out_host may be a local
+    if (e != hipSuccess)
+        return hip_fail(e, "writing the restricted offsets");
+    return PCF_OK;
+}
+
+pcf_status pcf_restrict(const pcf_set *X, double a, double b, const int64_t *offsets_out,
+                        void *t_out, void *v_out, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    st = check_range(X, a, b);
+    if (st != PCF_OK)
+        return st;
+    if (X->n == 0)
+        return PCF_OK;
+    if (!offsets_out || !t_out || !v_out)
+        return fail(PCF_EINVAL, "an output pointer is NULL");
+    hipError_t e = launch_restrict_fill(X->dtype == PCF_F64, X->offsets, X->n, X->t, X->v,
+                                        a, b, offsets_out, t_out, v_out,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "restriction kernel launch");
     return PCF_OK;
 }
 

@@ -59,6 +59,13 @@ struct SingleArgs {
     int root;     // 0: none, 1: sqrt, 2: x^(1/p)
 };
 hipError_t launch_single(bool f64, int sk, const SingleArgs &a, hipStream_t s);
+hipError_t launch_restrict_count(bool f64, const int64_t *offsets, int64_t n,
+                                 const void *t, double a, double b, int64_t *counts,
+                                 hipStream_t s);
+hipError_t launch_restrict_fill(bool f64, const int64_t *offsets, int64_t n,
+                                const void *t, const void *v, double a, double b,
+                                const int64_t *out_off, void *t_out, void *v_out,
+                                hipStream_t s);
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);

@@ -1,5 +1,6 @@
-// single.hip -- functionals of one PCF at a time (paper, Section 3.2 "PCF
-// integrals"): F(f) = r(int_a^b h(f(t)) dt) for every PCF of a set.
+// single.hip -- per-PCF operations: functionals of one PCF at a time (paper,
+// Section 3.2 "PCF integrals": F(f) = r(int_a^b h(f(t)) dt) for every PCF of
+// a set), and the restriction of a set to an integration range [a, b).
 //
 // Segment iteration (Algorithm IterateSegments) walks a PCF's pieces and
 // adds (r - l) h(v) per segment [l, r) of [a, b). Piece k of a PCF is
@@ -114,6 +115,141 @@ hipError_t launch_single(bool f64, int sk, const SingleArgs &a, hipStream_t s)
     case SK_SQR: return launch_single_t<float, SK_SQR>(a, s);
     default: return launch_single_t<float, SK_POW>(a, s);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Restriction to an integration range (paper, Section 2.2: combination
+// integrals over [a, b)): f 1_[a,b) is again a PCF, and since h(0, 0) = 0
+// for every kind, int_a^b h(f, g) = int_0^inf h(f 1_[a,b), g 1_[a,b)). Its
+// rows: (0, 0) and (a, f(a)) when a > 0, else (0, f(0)); the rows of f with
+// a < t_k < b; (b, 0) when b is finite. a and b are taken in the set's
+// precision.
+
+// Rows of f before and at x: the number of times t_k <= x (strict: t_k < x).
+template <typename T>
+__device__ __forceinline__ int64_t count_le(const T *t, int64_t n, T x, bool strict)
+{
+    int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const bool in = strict ? (t[mid] < x) : (t[mid] <= x);
+        if (in)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Row range [k_a + 1, k_b) of the rows kept from f, and k_a (the piece
+// holding a).
+template <typename T>
+__device__ __forceinline__ void kept_rows(const T *t, int64_t n, T a, T b, bool b_finite,
+                                          int64_t &ka, int64_t &kb)
+{
+    ka = count_le(t, n, a, false) - 1;  // t_0 = 0 <= a
+    kb = b_finite ? count_le(t, n, b, true) : n;
+}
+
+template <typename T>
+__global__ void restrict_count(const int64_t *__restrict__ offsets, int64_t n,
+                               const T *__restrict__ t, double a, double b,
+                               int64_t *__restrict__ counts)
+{
+    const T ta = (T)a, tb = (T)b;
+    const bool bf = !(b == INFINITY);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = offsets[i], ni = offsets[i + 1] - o;
+        int64_t ka, kb;
+        kept_rows(t + o, ni, ta, tb, bf, ka, kb);
+        const int64_t mid = kb - (ka + 1) > 0 ? kb - (ka + 1) : 0;
+        counts[i + 1] = (ta > T(0) ? 2 : 1) + mid + (bf ? 1 : 0);
+        if (i == 0)
+            counts[0] = 0;
+    }
+}
+
+// One wave per PCF: lane 0 writes the head and tail rows, the lanes copy the
+// kept rows.
+template <typename T>
+__global__ void restrict_fill(const int64_t *__restrict__ offsets, int64_t n,
+                              const T *__restrict__ t, const T *__restrict__ v,
+                              double a, double b, const int64_t *__restrict__ out_off,
+                              T *__restrict__ t_out, T *__restrict__ v_out)
+{
+    const T ta = (T)a, tb = (T)b;
+    const bool bf = !(b == INFINITY);
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves) {
+        const int64_t o = offsets[i], ni = offsets[i + 1] - o;
+        int64_t ka, kb;
+        kept_rows(t + o, ni, ta, tb, bf, ka, kb);
+        int64_t w = out_off[i];
+        const int head = ta > T(0) ? 2 : 1;
+        if (lane == 0) {
+            if (head == 2) {
+                t_out[w] = T(0);
+                v_out[w] = T(0);
+                t_out[w + 1] = ta;
+                v_out[w + 1] = v[o + ka];
+            } else {
+                t_out[w] = T(0);
+                v_out[w] = v[o];
+            }
+        }
+        w += head;
+        for (int64_t k = ka + 1 + lane; k < kb; k += 64) {
+            t_out[w + (k - ka - 1)] = t[o + k];
+            v_out[w + (k - ka - 1)] = v[o + k];
+        }
+        if (lane == 0 && bf) {
+            const int64_t last = out_off[i + 1] - 1;
+            t_out[last] = tb;
+            v_out[last] = T(0);
+        }
+    }
+}
+
+hipError_t launch_restrict_count(bool f64, const int64_t *offsets, int64_t n,
+                                 const void *t, double a, double b, int64_t *counts,
+                                 hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    if (f64)
+        hipLaunchKernelGGL(restrict_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const double *)t, a, b, counts);
+    else
+        hipLaunchKernelGGL(restrict_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const float *)t, a, b, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_fill(bool f64, const int64_t *offsets, int64_t n,
+                                const void *t, const void *v, double a, double b,
+                                const int64_t *out_off, void *t_out, void *v_out,
+                                hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (f64)
+        hipLaunchKernelGGL(restrict_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const double *)t, (const double *)v, a, b,
+                           out_off, (double *)t_out, (double *)v_out);
+    else
+        hipLaunchKernelGGL(restrict_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const float *)t, (const float *)v, a, b,
+                           out_off, (float *)t_out, (float *)v_out);
+    return hipGetLastError();
 }
 
 }  // namespace pcf
