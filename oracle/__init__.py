@@ -29,6 +29,7 @@ import numpy as np
 
 LP, LP_POW, GRAM = 0, 1, 2
 S_INTEGRAL, S_NORM, S_NORM_POW = 0, 1, 2
+W_EXP, W_POW = 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcf_oracle.c")
@@ -78,6 +79,11 @@ def _load():
                                        ctypes.c_double, ctypes.c_int64, _I64P, _F64P,
                                        _F64P, ctypes.c_int64, _I64P, _I64P, _F64P,
                                        _F64P]
+        lib.orc_entries_w.restype = ctypes.c_int
+        lib.orc_entries_w.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int64, _I64P, _F64P, _F64P, ctypes.c_int64,
+                                      _I64P, _I64P, _F64P, _F64P]
         lib.orc_single.restype = ctypes.c_int
         lib.orc_single.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_int64, _I64P, _F64P,
@@ -141,6 +147,24 @@ def entries_ab(kind, p, a, b, offsets, t, v, I, J, with_abs=False):
                             _p(I, _I64P), _p(J, _I64P), _p(out, _F64P), _p(ab, _F64P))
     if rc:
         raise ValueError("oracle: bad pair index or bounds")
+    return (out, ab) if with_abs else out
+
+
+def entries_w(kind, p, weight, c, offsets, t, v, I, J, a=0.0, b=np.inf, with_abs=False):
+    """As ``entries_ab`` with the time weight ``weight`` (``W_EXP``:
+    w(t) = exp(-c t); ``W_POW``: w(t) = t^c): the time-dependent h of
+    Section 3 summed through its antiderivative H = h0 * W. ``with_abs``
+    also returns sum |h0| (|W(r)| + |W(l)|)."""
+    lib = _load()
+    offsets, t, v = _i64(offsets), _f64(t), _f64(v)
+    I, J = _i64(I), _i64(J)
+    out = np.empty(len(I), dtype=np.float64)
+    ab = np.empty(len(I), dtype=np.float64)
+    rc = lib.orc_entries_w(int(kind), float(p), int(weight), float(c), float(a), float(b),
+                           len(offsets) - 1, _p(offsets, _I64P), _p(t, _F64P), _p(v, _F64P),
+                           len(I), _p(I, _I64P), _p(J, _I64P), _p(out, _F64P), _p(ab, _F64P))
+    if rc:
+        raise ValueError("oracle: bad pair index, bounds or weight")
     return (out, ab) if with_abs else out
 
 

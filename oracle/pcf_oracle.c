@@ -309,6 +309,101 @@ int orc_entries_ab(int kind, double p, double a, double b, int64_t n_pcf,
     return 0;
 }
 
+/* Time-dependent combinations (Section 2.2, weighted L_p and weighted
+ * inner product; Section 3, the time-dependent h with a known antiderivative
+ * H in t). The weight w >= 0 multiplies a time-independent h:
+ * h(a, b, t) = h0(a, b) w(t), so H(a, b, t) = h0(a, b) W(t) with
+ * W(t) = int_0^t w. Two weight families with closed-form W:
+ *   ORC_W_EXP  w(t) = exp(-c t), c > 0:   W(t) = (1 - exp(-c t)) / c
+ *   ORC_W_POW  w(t) = t^c, c > -1:        W(t) = t^(c+1) / (c+1)      */
+#define ORC_W_EXP 1
+#define ORC_W_POW 2
+
+static double w_anti(int wk, double c, double t)
+{
+    if (wk == ORC_W_EXP)
+        return isinf(t) ? 1.0 / c : -expm1(-c * t) / c;
+    return isinf(t) ? INFINITY : pow(t, c + 1.0) / (c + 1.0);
+}
+
+/* I = sum over the cells [l, r) of the common refinement, clipped to
+ * [a, b), of H(f(l), g(l), r) - H(f(l), g(l), l) (Section 3). *abs_out
+ * (optional) receives sum |h0| (|W(r)| + |W(l)|): the magnitudes of the
+ * terms the sum adds, the scale of its rounding error. */
+static double integral_w(int kind, double p, int wk, double c, double a, double b,
+                         const double *tf, const double *vf, int64_t nf,
+                         const double *tg, const double *vg, int64_t ng,
+                         double *scratch, double *abs_out)
+{
+    if (!pcf_ok(tf, vf, nf) || !pcf_ok(tg, vg, ng)) {
+        if (abs_out)
+            *abs_out = NAN;
+        return NAN;
+    }
+    int64_t m = union_grid(tf, nf, tg, ng, scratch);
+    double acc = 0.0, acc_abs = 0.0;
+    int64_t kf = 0, kg = 0;
+    for (int64_t r = 0; r < m; ++r) {
+        double x = scratch[r];
+        while (kf + 1 < nf && tf[kf + 1] <= x)
+            ++kf;
+        while (kg + 1 < ng && tg[kg + 1] <= x)
+            ++kg;
+        double h0 = h_val(kind, p, vf[kf], vg[kg]);
+        double l = x < a ? a : x;
+        double rr = r + 1 < m ? scratch[r + 1] : INFINITY;
+        if (rr > b)
+            rr = b;
+        if (!(rr > l) || h0 == 0.0)
+            continue; /* empty cell, or a zero integrand (the unbounded tail) */
+        double Hr = h0 * w_anti(wk, c, rr), Hl = h0 * w_anti(wk, c, l);
+        acc = acc + (Hr - Hl);
+        acc_abs = acc_abs + fabs(Hr) + fabs(Hl);
+    }
+    if (abs_out)
+        *abs_out = acc_abs;
+    return acc;
+}
+
+/* As orc_entries_ab with the weight (wk, c): F = r(I) of integral_w.
+ * Returns -1 on bad indices, bounds or weight parameters. */
+int orc_entries_w(int kind, double p, int wk, double c, double a, double b,
+                  int64_t n_pcf, const int64_t *offsets, const double *t,
+                  const double *v, int64_t npairs, const int64_t *I,
+                  const int64_t *J, double *out, double *abs_out)
+{
+    if (!(a >= 0.0) || !(b > a))
+        return -1;
+    if (!((wk == ORC_W_EXP && c > 0.0 && isfinite(c)) ||
+          (wk == ORC_W_POW && c > -1.0 && isfinite(c))))
+        return -1;
+    int64_t nmax = 0;
+    for (int64_t i = 0; i < n_pcf; ++i) {
+        int64_t n = offsets[i + 1] - offsets[i];
+        if (n > nmax)
+            nmax = n;
+    }
+    double *s = (double *)malloc(sizeof(double) * (size_t)(2 * nmax + 1));
+    if (!s)
+        return -1;
+    for (int64_t k = 0; k < npairs; ++k) {
+        int64_t i = I[k], j = J[k];
+        if (i < 0 || j < 0 || i >= n_pcf || j >= n_pcf) {
+            free(s);
+            return -1;
+        }
+        const int64_t oi = offsets[i], oj = offsets[j];
+        double ab = 0.0;
+        double Iv = integral_w(kind, p, wk, c, a, b, t + oi, v + oi, offsets[i + 1] - oi,
+                               t + oj, v + oj, offsets[j + 1] - oj, s, &ab);
+        out[k] = finish(kind, p, Iv);
+        if (abs_out)
+            abs_out[k] = ab;
+    }
+    free(s);
+    return 0;
+}
+
 /* Full M x M matrix F(C) (Section 3.1): every entry computed on its own,
  * symmetry not assumed. out is row-major with leading dimension M. */
 int orc_matrix(int kind, double p, int64_t n_pcf, const int64_t *offsets,
