@@ -215,6 +215,33 @@ pcf_status pcf_restrict_rows(const pcf_set *X, double a, double b, int64_t *offs
 pcf_status pcf_restrict(const pcf_set *X, double a, double b, const int64_t *offsets_out,
                         void *t_out, void *v_out, void *stream);
 
+/* Time-dependent combinations (Section 3: h(a, b, t) with an antiderivative
+ * H in t; Section 2.2: weighted L_p distance and weighted inner product).
+ * For h = h0(a, b) w(t) every cell [l, r) of the merge adds
+ * h0 (W(r) - W(l)), W(t) = int_0^t w. pcf_warp carries each breakpoint t_k
+ * to tau_k = W(t_k), so every entry point run on the warped set computes the
+ * weighted integrals (pcf_pairwise_lp gives (int |f-g|^p w)^(1/p)); with a
+ * range, restrict first, then warp. Weights (c is the parameter):
+ *   PCF_WEIGHT_EXP  w(t) = exp(-c t), c > 0    W(t) = (1 - exp(-c t)) / c
+ *   PCF_WEIGHT_POW  w(t) = t^c, c > -1         W(t) = t^(c+1) / (c+1)
+ * W is computed in FP64 and rounded to the set's dtype; rows whose rounded
+ * tau ties with the next row's are dropped (the later row's value holds on
+ * the next piece), so the warped set is again strictly increasing. A tau
+ * that overflows gives PCF_EINVAL naming the PCF. Two calls, as for the
+ * restriction: pcf_warp_rows writes the warped offsets to offsets_out
+ * (device, n+1) and offsets_out_host (host, n+1) and synchronises;
+ * pcf_warp (asynchronous) fills t_out and v_out, offsets_out_host[n]
+ * entries of X's dtype each, allocated by the caller. */
+typedef enum {
+    PCF_WEIGHT_EXP = 1,
+    PCF_WEIGHT_POW = 2
+} pcf_weight_kind;
+
+pcf_status pcf_warp_rows(const pcf_set *X, pcf_weight_kind weight, double c,
+                         int64_t *offsets_out, int64_t *offsets_out_host, void *stream);
+pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
+                    const int64_t *offsets_out, void *t_out, void *v_out, void *stream);
+
 /* Many independent full matrices in one persistent launch. `all` is one CSR
  * set holding every problem's PCFs; problem b owns PCFs
  * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)

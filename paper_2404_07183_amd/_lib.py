@@ -18,6 +18,7 @@ PCF_LP, PCF_LP_POW, PCF_GRAM = 0, 1, 2
 PCF_UPPER_ONLY, PCF_VALIDATE, PCF_DETERMINISTIC, PCF_REUSE_PLAN = 1, 2, 4, 8
 PCF_RECORDS_PACKED = 16
 PCF_INTEGRAL, PCF_NORM, PCF_NORM_POW = 0, 1, 2
+PCF_WEIGHT_EXP, PCF_WEIGHT_POW = 1, 2
 
 STATUS_NAMES = {0: "PCF_OK", 1: "PCF_EINVAL", 2: "PCF_EDATA", 3: "PCF_EDEVICE",
                 4: "PCF_ENOMEM", 5: "PCF_EUNSUPPORTED"}
@@ -79,6 +80,12 @@ _SIGS = {
     "pcf_restrict": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_double,
                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "pcf_warp_rows": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "pcf_warp": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p]),
     "pcf_single": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                   ctypes.c_void_p]),
@@ -183,6 +190,16 @@ def pcf_restrict_rows(X, a, b, offsets_out_ptr, offsets_out_host_ptr, stream):
 def pcf_restrict(X, a, b, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
     return load().pcf_restrict(ctypes.byref(X), a, b, offsets_out_ptr, t_out_ptr,
                                v_out_ptr, stream)
+
+
+def pcf_warp_rows(X, weight, c, offsets_out_ptr, offsets_out_host_ptr, stream):
+    return load().pcf_warp_rows(ctypes.byref(X), weight, c, offsets_out_ptr,
+                                offsets_out_host_ptr, stream)
+
+
+def pcf_warp(X, weight, c, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
+    return load().pcf_warp(ctypes.byref(X), weight, c, offsets_out_ptr, t_out_ptr,
+                           v_out_ptr, stream)
 
 
 def pcf_single(X, kind, p, a, b, out_ptr, stream):

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
                    PCF_RECORDS_PACKED, PCF_REUSE_PLAN, PCF_UPPER_ONLY,
-                   PCF_VALIDATE, check)
+                   PCF_VALIDATE, PCF_WEIGHT_EXP, PCF_WEIGHT_POW, check)
 
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
@@ -145,23 +145,25 @@ def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
 
 def pdist(X, p=1.0, *, power=False, window=None, out=None, upper_only=False,
           validate=False, workspace=None, stream=None, packed=False, shape=None,
-          bounds=None):
+          bounds=None, weight=None):
     """L_p distance matrix (``power=True``: d_p^p) of the PCFs in ``X``;
-    ``bounds=(a, b)``: of the integrals over [a, b) (Section 2.2).
+    ``bounds=(a, b)``: of the integrals over [a, b) (Section 2.2);
+    ``weight=("exp", c)`` or ``("pow", c)``: with the time weight
+    w(t) = exp(-c t) or t^c (the weighted L_p distance of Section 2.2).
 
     ``packed=True`` skips re-packing the breakpoint records: only valid when
     ``workspace`` served the previous call on this very set and data."""
-    if bounds is not None:
-        X = restrict(X, *bounds, stream=stream)
+    X = _transform(X, bounds, weight, stream)
     return _forward(X, PCF_LP_POW if power else PCF_LP, p, window, out, upper_only,
                     validate, workspace, stream, packed, shape)
 
 
 def gram(X, *, window=None, out=None, upper_only=False, validate=False,
-         workspace=None, stream=None, packed=False, shape=None, bounds=None):
-    """L2 Gram matrix of the PCFs in ``X`` (``bounds=(a, b)``: over [a, b))."""
-    if bounds is not None:
-        X = restrict(X, *bounds, stream=stream)
+         workspace=None, stream=None, packed=False, shape=None, bounds=None,
+         weight=None):
+    """L2 Gram matrix of the PCFs in ``X`` (``bounds=(a, b)``: over [a, b);
+    ``weight``: the weighted inner product, as in ``pdist``)."""
+    X = _transform(X, bounds, weight, stream)
     return _forward(X, PCF_GRAM, 0.0, window, out, upper_only, validate, workspace,
                     stream, packed, shape)
 
@@ -186,21 +188,19 @@ def _cross(X, Y, kind, p, out, validate, workspace, stream, shape=None):
 
 
 def cdist(X, Y, p=1.0, *, power=False, out=None, validate=False, workspace=None,
-          stream=None, shape=None, bounds=None):
+          stream=None, shape=None, bounds=None, weight=None):
     """L_p distances (``power=True``: d_p^p) between the PCFs of ``X`` (rows)
-    and those of ``Y`` (columns); ``bounds=(a, b)``: over [a, b)."""
-    if bounds is not None:
-        X, Y = restrict(X, *bounds, stream=stream), restrict(Y, *bounds, stream=stream)
+    and those of ``Y`` (columns); ``bounds`` and ``weight`` as in ``pdist``."""
+    X, Y = _transform(X, bounds, weight, stream), _transform(Y, bounds, weight, stream)
     return _cross(X, Y, PCF_LP_POW if power else PCF_LP, p, out, validate, workspace,
                   stream, shape)
 
 
 def cross_gram(X, Y, *, out=None, validate=False, workspace=None, stream=None,
-               shape=None, bounds=None):
+               shape=None, bounds=None, weight=None):
     """L2 inner products between the PCFs of ``X`` (rows) and ``Y`` (columns);
-    ``bounds=(a, b)``: over [a, b)."""
-    if bounds is not None:
-        X, Y = restrict(X, *bounds, stream=stream), restrict(Y, *bounds, stream=stream)
+    ``bounds`` and ``weight`` as in ``pdist``."""
+    X, Y = _transform(X, bounds, weight, stream), _transform(Y, bounds, weight, stream)
     return _cross(X, Y, PCF_GRAM, 0.0, out, validate, workspace, stream, shape)
 
 
@@ -222,6 +222,40 @@ def restrict(X, a, b, stream=None):
     new.offsets_host, new.offsets, new.n = off_h, off_d, X.n
     new.t, new.v = t, v
     return new
+
+
+_WEIGHTS = {"exp": PCF_WEIGHT_EXP, "pow": PCF_WEIGHT_POW}
+
+
+def warp(X, weight, c, stream=None):
+    """The PCFs of ``X`` with every breakpoint t carried to W(t), the
+    antiderivative of the weight (``"exp"``: w(t) = exp(-c t); ``"pow"``:
+    w(t) = t^c). Any matrix of the result is the matrix of the time-weighted
+    integrals (Section 3, time-dependent h with antiderivative H)."""
+    wk = _WEIGHTS.get(weight, weight)
+    Xc = X.c_struct()
+    off_h = np.empty(X.n + 1, dtype=np.int64)
+    off_d = torch.empty(X.n + 1, dtype=torch.int64, device=X.t.device)
+    check(_lib.pcf_warp_rows(Xc, int(wk), float(c), off_d.data_ptr(), off_h.ctypes.data,
+                             _stream_handle(stream)))
+    rows = int(off_h[-1])
+    t = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    v = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    check(_lib.pcf_warp(Xc, int(wk), float(c), off_d.data_ptr(), t.data_ptr(), v.data_ptr(),
+                        _stream_handle(stream)))
+    new = object.__new__(PcfSet)
+    new.offsets_host, new.offsets, new.n = off_h, off_d, X.n
+    new.t, new.v = t, v
+    return new
+
+
+def _transform(X, bounds, weight, stream):
+    """Restriction to ``bounds``, then the time warp of ``weight``."""
+    if bounds is not None:
+        X = restrict(X, *bounds, stream=stream)
+    if weight is not None:
+        X = warp(X, *weight, stream=stream)
+    return X
 
 
 def _single(X, kind, p, a, b, out, stream):

@@ -316,6 +316,46 @@ pcf_status check_pair(const pcf_set *X, const pcf_set *Y)
     return PCF_OK;
 }
 
+// offsets_out[1..n] hold per-PCF row counts written by a count kernel on
+// s (-1: a PCF the transform cannot carry): copy them to the host, turn
+// them into offsets there and copy those back. Synchronous, as the caller
+// needs the total to allocate the rows.
+pcf_status counts_to_offsets(int64_t n, int64_t *offsets_out, int64_t *offsets_out_host,
+                             hipStream_t s, const char *what)
+{
+    hipError_t e = hipSuccess;
+    if (n == 0)
+        offsets_out_host[0] = 0;
+    else
+        e = hipMemcpyAsync(offsets_out_host, offsets_out, sizeof(int64_t) * (size_t)(n + 1),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "reading the row counts");
+    for (int64_t i = 0; i < n; ++i) {
+        if (offsets_out_host[i + 1] < 0)
+            return fail(PCF_EINVAL, std::string("PCF ") + std::to_string(i) +
+                                        ": its " + what + " times are not finite and increasing");
+        offsets_out_host[i + 1] += offsets_out_host[i];
+    }
+    e = hipMemcpyAsync(offsets_out, offsets_out_host, sizeof(int64_t) * (size_t)(n + 1),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // offsets_out_host may be a local
+    return e == hipSuccess ? PCF_OK : hip_fail(e, "writing the offsets");
+}
+
+// A time weight: exponential needs 0 < c < inf, power -1 < c < inf.
+pcf_status check_weight(int weight, double c)
+{
+    if (weight == PCF_WEIGHT_EXP && c > 0.0 && isfinite(c))
+        return PCF_OK;
+    if (weight == PCF_WEIGHT_POW && c > -1.0 && isfinite(c))
+        return PCF_OK;
+    return fail(PCF_EINVAL, "weight: PCF_WEIGHT_EXP needs c > 0, PCF_WEIGHT_POW c > -1");
+}
+
 // The bounds of a restriction in the set's precision: 0 <= a < b <= inf,
 // both still ordered (and b still finite when given finite) once rounded.
 pcf_status check_range(const pcf_set *X, double a, double b)
@@ -770,34 +810,11 @@ pcf_status pcf_restrict_rows(const pcf_set *X, double a, double b, int64_t *offs
     if (!offsets_out || !offsets_out_host)
         return fail(PCF_EINVAL, "offsets_out or offsets_out_host is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t n = X->n;
-    if (n == 0) {
-        offsets_out_host[0] = 0;
-        hipError_t e = hipMemcpyAsync(offsets_out, offsets_out_host, sizeof(int64_t),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
-        return e == hipSuccess ? PCF_OK : hip_fail(e, "writing the offsets");
-    }
-    // rows per restricted PCF into offsets_out[1..n], then the prefix sum
-    hipError_t e = launch_restrict_count(X->dtype == PCF_F64, X->offsets, n, X->t, a, b,
+    hipError_t e = launch_restrict_count(X->dtype == PCF_F64, X->offsets, X->n, X->t, a, b,
                                          offsets_out, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(offsets_out_host, offsets_out, sizeof(int64_t) * (size_t)(n + 1),
-                           hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
     if (e != hipSuccess)
-        return hip_fail(e, "counting the restricted rows");
-    for (int64_t i = 0; i < n; ++i)
-        offsets_out_host[i + 1] += offsets_out_host[i];
-    e = hipMemcpyAsync(offsets_out, offsets_out_host, sizeof(int64_t) * (size_t)(n + 1),
-                       hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(s);  // offsets_out_host may be a local
-    if (e != hipSuccess)
-        return hip_fail(e, "writing the restricted offsets");
-    return PCF_OK;
+        return hip_fail(e, "restriction count launch");
+    return counts_to_offsets(X->n, offsets_out, offsets_out_host, s, "restricted");
 }
 
 pcf_status pcf_restrict(const pcf_set *X, double a, double b, const int64_t *offsets_out,
@@ -818,6 +835,44 @@ pcf_status pcf_restrict(const pcf_set *X, double a, double b, const int64_t *off
                                         (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "restriction kernel launch");
+    return PCF_OK;
+}
+
+pcf_status pcf_warp_rows(const pcf_set *X, pcf_weight_kind weight, double c,
+                         int64_t *offsets_out, int64_t *offsets_out_host, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st == PCF_OK)
+        st = check_weight(weight, c);
+    if (st != PCF_OK)
+        return st;
+    if (!offsets_out || !offsets_out_host)
+        return fail(PCF_EINVAL, "offsets_out or offsets_out_host is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_warp_count(X->dtype == PCF_F64, X->offsets, X->n, X->t,
+                                     (int)weight, c, offsets_out, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "warp count launch");
+    return counts_to_offsets(X->n, offsets_out, offsets_out_host, s, "warped");
+}
+
+pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
+                    const int64_t *offsets_out, void *t_out, void *v_out, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st == PCF_OK)
+        st = check_weight(weight, c);
+    if (st != PCF_OK)
+        return st;
+    if (X->n == 0)
+        return PCF_OK;
+    if (!offsets_out || !t_out || !v_out)
+        return fail(PCF_EINVAL, "an output pointer is NULL");
+    hipError_t e = launch_warp_fill(X->dtype == PCF_F64, X->offsets, X->n, X->t, X->v,
+                                    (int)weight, c, offsets_out, t_out, v_out,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "warp kernel launch");
     return PCF_OK;
 }
 

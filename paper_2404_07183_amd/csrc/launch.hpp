@@ -66,6 +66,11 @@ hipError_t launch_restrict_fill(bool f64, const int64_t *offsets, int64_t n,
                                 const void *t, const void *v, double a, double b,
                                 const int64_t *out_off, void *t_out, void *v_out,
                                 hipStream_t s);
+hipError_t launch_warp_count(bool f64, const int64_t *offsets, int64_t n, const void *t,
+                             int wk, double c, int64_t *counts, hipStream_t s);
+hipError_t launch_warp_fill(bool f64, const int64_t *offsets, int64_t n, const void *t,
+                            const void *v, int wk, double c, const int64_t *out_off,
+                            void *t_out, void *v_out, hipStream_t s);
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);

@@ -1,6 +1,7 @@
 // single.hip -- per-PCF operations: functionals of one PCF at a time (paper,
 // Section 3.2 "PCF integrals": F(f) = r(int_a^b h(f(t)) dt) for every PCF of
-// a set), and the restriction of a set to an integration range [a, b).
+// a set), the restriction of a set to an integration range [a, b), and the
+// time warp of a set for a time-dependent h = h0(a, b) w(t).
 //
 // Segment iteration (Algorithm IterateSegments) walks a PCF's pieces and
 // adds (r - l) h(v) per segment [l, r) of [a, b). Piece k of a PCF is
@@ -248,6 +249,141 @@ hipError_t launch_restrict_fill(bool f64, const int64_t *offsets, int64_t n,
     else
         hipLaunchKernelGGL(restrict_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                            offsets, n, (const float *)t, (const float *)v, a, b,
+                           out_off, (float *)t_out, (float *)v_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Time warp (Section 3, time-dependent h with an antiderivative H in t;
+// Section 2.2, weighted L_p and inner products). For h = h0(a, b) w(t),
+// H = h0 W with W(t) = int_0^t w, and a cell [l, r) of the merge adds
+// h0 (W(r) - W(l)). Carrying every breakpoint t_k to tau_k = W(t_k) turns
+// that into h0 (tau_r - tau_l), the contribution of the plain merge on the
+// warped set: W is evaluated once per breakpoint instead of twice per cell
+// and pair, and the pairwise kernels run unchanged. Weights:
+//   WK_EXP  w(t) = exp(-c t), c > 0:  W(t) = -expm1(-c t) / c
+//   WK_POW  w(t) = t^c, c > -1:       W(t) = t^(c+1) / (c+1)
+// W is increasing, but rounded values can tie: a run of rows with one tau
+// keeps only its last row (its value holds on the next piece of positive
+// width), so the warped set is strictly increasing again. A tau that is not
+// finite, or decreases, marks the PCF bad (count -1).
+enum { WK_EXP = 1, WK_POW = 2 };
+
+template <typename T>
+__device__ __forceinline__ T warped(const T *t, int64_t k, int wk, double c)
+{
+    if (k == 0)
+        return T(0);
+    const double x = (double)t[k];
+    const double w = wk == WK_EXP ? -expm1(-c * x) / c : pow(x, c + 1.0) / (c + 1.0);
+    return (T)w;
+}
+
+// One 64-row chunk of a PCF's warped rows: tau of row base + lane, whether
+// that row is kept, and whether it breaks monotonicity or finiteness.
+template <typename T>
+__device__ __forceinline__ void warp_chunk(const T *t, int64_t ni, int64_t base, int lane,
+                                           int wk, double c, T &tau, bool &keep, bool &bad)
+{
+    const int64_t k = base + lane;
+    tau = k < ni ? warped(t, k, wk, c) : T(0);
+    T nxt = __shfl_down(tau, 1, 64);
+    if (lane == 63 && k + 1 < ni)
+        nxt = warped(t, k + 1, wk, c);
+    const bool in = k < ni, last = k + 1 == ni;
+    keep = in && (last || nxt > tau);
+    bad = in && (!isfinite(tau) || (!last && nxt < tau));
+}
+
+template <typename T>
+__global__ void warp_count(const int64_t *__restrict__ offsets, int64_t n,
+                           const T *__restrict__ t, int wk, double c,
+                           int64_t *__restrict__ counts)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves) {
+        const int64_t o = offsets[i], ni = offsets[i + 1] - o;
+        int64_t kept = 0;
+        bool anybad = false;
+        for (int64_t base = 0; base < ni; base += 64) {
+            T tau;
+            bool keep, bad;
+            warp_chunk(t + o, ni, base, lane, wk, c, tau, keep, bad);
+            kept += __popcll(__ballot(keep));
+            anybad = anybad || __ballot(bad) != 0;
+        }
+        if (lane == 0) {
+            counts[i + 1] = anybad ? -1 : kept;
+            if (i == 0)
+                counts[0] = 0;
+        }
+    }
+}
+
+template <typename T>
+__global__ void warp_fill(const int64_t *__restrict__ offsets, int64_t n,
+                          const T *__restrict__ t, const T *__restrict__ v, int wk,
+                          double c, const int64_t *__restrict__ out_off,
+                          T *__restrict__ t_out, T *__restrict__ v_out)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves) {
+        const int64_t o = offsets[i], ni = offsets[i + 1] - o;
+        int64_t w = out_off[i];
+        const int64_t end = out_off[i + 1];  // the count pass made the same decisions
+        for (int64_t base = 0; base < ni; base += 64) {
+            T tau;
+            bool keep, bad;
+            warp_chunk(t + o, ni, base, lane, wk, c, tau, keep, bad);
+            const uint64_t m = __ballot(keep);
+            const int64_t pos = w + __popcll(m & below);
+            if (keep && pos < end) {
+                t_out[pos] = tau;
+                v_out[pos] = v[o + base + lane];
+            }
+            w += __popcll(m);
+        }
+    }
+}
+
+hipError_t launch_warp_count(bool f64, const int64_t *offsets, int64_t n, const void *t,
+                             int wk, double c, int64_t *counts, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (f64)
+        hipLaunchKernelGGL(warp_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const double *)t, wk, c, counts);
+    else
+        hipLaunchKernelGGL(warp_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const float *)t, wk, c, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_warp_fill(bool f64, const int64_t *offsets, int64_t n, const void *t,
+                            const void *v, int wk, double c, const int64_t *out_off,
+                            void *t_out, void *v_out, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (f64)
+        hipLaunchKernelGGL(warp_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const double *)t, (const double *)v, wk, c,
+                           out_off, (double *)t_out, (double *)v_out);
+    else
+        hipLaunchKernelGGL(warp_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const float *)t, (const float *)v, wk, c,
                            out_off, (float *)t_out, (float *)v_out);
     return hipGetLastError();
 }

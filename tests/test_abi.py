@@ -54,6 +54,16 @@ def test_argument_errors_need_no_device():
     # n < 0
     Xn = _lib.pcf_set(-1, None, None, None, _lib.PCF_F64, None)
     assert lib.pcf_gram(ctypes.byref(Xn), None, 1, None, None, 0, 0, None) == _lib.PCF_EINVAL
+    # integration ranges and time weights are checked before any device work
+    for a, b in ((2.0, 2.0), (-1.0, 3.0), (3.0, 1.0), (float("nan"), 1.0)):
+        assert lib.pcf_restrict_rows(ctypes.byref(X), a, b, None, None, None) == _lib.PCF_EINVAL
+    bad_weights = ((0, 1.0), (_lib.PCF_WEIGHT_EXP, 0.0), (_lib.PCF_WEIGHT_EXP, float("inf")),
+                   (_lib.PCF_WEIGHT_POW, -1.0), (_lib.PCF_WEIGHT_POW, float("nan")))
+    for wk, c in bad_weights:
+        assert lib.pcf_warp_rows(ctypes.byref(X), wk, c, None, None, None) == _lib.PCF_EINVAL
+        assert lib.pcf_warp(ctypes.byref(X), wk, c, None, None, None, None) == _lib.PCF_EINVAL
+    assert lib.pcf_warp(ctypes.byref(X), _lib.PCF_WEIGHT_EXP, 1.0, None, None, None,
+                        None) == _lib.PCF_OK
 
 
 def _inspect(offsets, dtype=_lib.PCF_F64, window=None, backward=False):
