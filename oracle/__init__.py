@@ -7,7 +7,8 @@ matrices"). Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg
 of ``bench.py`` may import it. The GPU library shares no code with it and never
 calls it.
 
-The arithmetic lives in ``pcf_oracle.c`` (built with ``gcc -O2
+Reductions (mean, std, max, min of PCF collections) live in ``reduce.py``
+(plain Python). The pair integrals live in ``pcf_oracle.c`` (built with ``gcc -O2
 -ffp-contract=off``); this module only builds that file and marshals NumPy
 arrays to it through ctypes. Kinds: ``LP`` (L_p distance), ``LP_POW`` (d_p^p)
 and ``GRAM`` (L2 inner product).

@@ -1,0 +1,108 @@
+"""Pins of the reductions oracle (Section 2.1 reductions, Section 4
+Algorithm ReducePair and reduction trees): pointwise NumPy evaluation of the
+mean, extremes and sample standard deviation at every breakpoint and between
+them, exactness on dyadic data, the minimal-representation invariants, a
+worked two-PCF example and the single-PCF group."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import reduce as red
+from paper_2404_07183_amd import workloads
+
+
+def _probe_points(offsets, t):
+    b = np.unique(t)
+    mids = (b[:-1] + b[1:]) / 2 if len(b) > 1 else b
+    return np.concatenate([b, mids, [b[-1] + 1.0]])
+
+
+def _values(offsets, t, v, lo, hi, x):
+    return np.stack([red.evaluate((t[offsets[i]:offsets[i + 1]], v[offsets[i]:offsets[i + 1]]), x)
+                     for i in range(lo, hi)])
+
+
+def _check_minimal(pcf):
+    t, v = pcf
+    assert t[0] == 0.0 and np.all(np.diff(t) > 0)
+    assert np.all(v[1:] != v[:-1])
+
+
+def test_worked_example():
+    # f = 2 on [0,1), -3 on [1,4); g = 1 on [0,2), 2 on [2,3); zero afterwards
+    f = (np.array([0.0, 1.0, 4.0]), np.array([2.0, -3.0, 0.0]))
+    g = (np.array([0.0, 2.0, 3.0]), np.array([1.0, 2.0, 0.0]))
+    s = red.reduce_pair(f, g, red.OPS["sum"])
+    assert s[0].tolist() == [0.0, 1.0, 2.0, 3.0, 4.0]
+    assert s[1].tolist() == [3.0, -2.0, -1.0, -3.0, 0.0]
+    m = red.reduce_pair(f, g, red.OPS["max"])  # the run of 0 from t = 3 is one row
+    assert m[0].tolist() == [0.0, 1.0, 2.0, 3.0] and m[1].tolist() == [2.0, 1.0, 2.0, 0.0]
+    n = red.reduce_pair(f, g, red.OPS["min"])
+    assert n[0].tolist() == [0.0, 1.0, 4.0] and n[1].tolist() == [1.0, -3.0, 0.0]
+    # std of {f, g}: |f - g| / sqrt(2) pointwise
+    o = np.array([0, 3, 6])
+    t = np.concatenate([f[0], g[0]])
+    v = np.concatenate([f[1], g[1]])
+    (st, sv), = red.reduce_groups("std", [0, 2], o, t, v)
+    x = _probe_points(o, t)
+    want = np.abs(red.evaluate(f, x) - red.evaluate(g, x)) / math.sqrt(2)
+    assert np.allclose(red.evaluate((st, sv), x), want, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("op", ["sum", "mean", "max", "min", "std"])
+def test_pointwise(op):
+    o, t, v = workloads.uniform_counts(37, 1, 40, seed=91)
+    groups = [0, 1, 2, 9, 20, 37]
+    if op == "std":
+        groups = [0, 2, 9, 20, 37]
+    res = red.reduce_groups(op, groups, o, t, v)
+    x = _probe_points(o, t)
+    for b, pcf in enumerate(res):
+        vals = _values(o, t, v, groups[b], groups[b + 1], x)
+        want = {"sum": lambda a: a.sum(0), "mean": lambda a: a.mean(0),
+                "max": lambda a: a.max(0), "min": lambda a: a.min(0),
+                "std": lambda a: a.std(0, ddof=1)}[op](vals)
+        got = red.evaluate(pcf, x)
+        scale = np.abs(vals).sum(0) + 1e-300
+        if op in ("max", "min"):
+            assert np.array_equal(got, want)
+        elif op == "std":
+            # the square root halves relative error; compare the variances
+            assert np.all(np.abs(got ** 2 - want ** 2) <= 1e-13 * (scale ** 2 + want ** 2))
+        else:
+            assert np.all(np.abs(got - want) <= 1e-14 * scale)
+        if groups[b + 1] - groups[b] > 1:
+            _check_minimal(pcf)
+        assert pcf[1][-1] == 0.0  # every f_i ends at 0
+
+
+def test_dyadic_sums_are_exact():
+    rng = np.random.default_rng(92)
+    pcfs = []
+    for _ in range(23):
+        n = int(rng.integers(1, 12))
+        ts = np.concatenate([[0.0], np.sort(rng.choice(np.arange(1, 200), n - 1, replace=False))]) / 8
+        vs = np.concatenate([rng.integers(-64, 64, n - 1) / 16.0, [0.0]])
+        pcfs.append((ts, vs))
+    o = np.concatenate([[0], np.cumsum([len(p[0]) for p in pcfs])])
+    t = np.concatenate([p[0] for p in pcfs])
+    v = np.concatenate([p[1] for p in pcfs])
+    (st, sv), = red.reduce_groups("sum", [0, 23], o, t, v)
+    x = _probe_points(o, t)
+    assert np.array_equal(red.evaluate((st, sv), x), _values(o, t, v, 0, 23, x).sum(0))
+    _check_minimal((st, sv))
+
+
+def test_single_pcf_group_and_pairs():
+    # a one-PCF reduction is the PCF itself, rows included; a pair goes
+    # through ReducePair, which merges equal neighbours
+    f = (np.array([0.0, 1.0, 2.0, 3.0]), np.array([5.0, 5.0, -1.0, 0.0]))
+    o = np.array([0, 4, 8])
+    t, v = np.concatenate([f[0], f[0]]), np.concatenate([f[1], f[1]])
+    (t1, v1), = red.reduce_groups("mean", [0, 1], o, t, v)
+    assert t1.tolist() == f[0].tolist() and v1.tolist() == f[1].tolist()
+    (t2, v2), = red.reduce_groups("mean", [0, 2], o, t, v)
+    assert t2.tolist() == [0.0, 2.0, 3.0] and v2.tolist() == [5.0, -1.0, 0.0]
+    with pytest.raises(ValueError):
+        red.reduce_groups("std", [0, 1], o, t, v)
