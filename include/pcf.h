@@ -242,6 +242,42 @@ pcf_status pcf_warp_rows(const pcf_set *X, pcf_weight_kind weight, double c,
 pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
                     const int64_t *offsets_out, void *t_out, void *v_out, void *stream);
 
+/* Reductions of groups of PCFs (Section 2.1, combinations and reductions;
+ * Section 4, Algorithm ReducePair and reduction trees). Group b is PCFs
+ * group_offsets_host[b] .. group_offsets_host[b+1]-1 (HOST array, B+1
+ * entries, 0 .. n, every group non-empty) and yields one PCF:
+ *   PCF_REDUCE_SUM   f_1 + ... + f_m      PCF_REDUCE_MAX / _MIN  pointwise
+ *   PCF_REDUCE_MEAN  (f_1 + ... + f_m) / m
+ *   PCF_REDUCE_STD   sqrt(sum_i (f_i - mean)^2 / (m - 1)), m >= 2
+ * Each group is reduced by a binary tree (neighbours paired level by
+ * level, an unpaired last item moving up), and the result keeps a row at
+ * t = 0 and wherever the reduced value changes (ReducePair's rule), before
+ * the mean or std transformation of the values; a one-PCF group returns its
+ * PCF's rows unchanged. Arithmetic in the set's dtype.
+ * Calls: pcf_reduce_workspace_bytes sizes the workspace (device, caller
+ * owned); pcf_reduce_rows runs the tree into it, writes the output offsets
+ * to offsets_out (device, B+1) and offsets_out_host (host, B+1) and
+ * synchronises; pcf_reduce (asynchronous) then writes t_out and v_out
+ * (offsets_out_host[B] entries of X's dtype each) from the same workspace,
+ * which must be passed unchanged with the same X, groups and op. */
+typedef enum {
+    PCF_REDUCE_SUM = 0,
+    PCF_REDUCE_MEAN = 1,
+    PCF_REDUCE_MAX = 2,
+    PCF_REDUCE_MIN = 3,
+    PCF_REDUCE_STD = 4
+} pcf_reduce_op;
+
+pcf_status pcf_reduce_workspace_bytes(const pcf_set *X, int32_t B,
+                                      const int64_t *group_offsets_host, pcf_reduce_op op,
+                                      size_t *bytes);
+pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
+                           pcf_reduce_op op, void *ws, size_t ws_bytes, int64_t *offsets_out,
+                           int64_t *offsets_out_host, void *stream);
+pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
+                      pcf_reduce_op op, const void *ws, size_t ws_bytes,
+                      const int64_t *offsets_out, void *t_out, void *v_out, void *stream);
+
 /* Many independent full matrices in one persistent launch. `all` is one CSR
  * set holding every problem's PCFs; problem b owns PCFs
  * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)

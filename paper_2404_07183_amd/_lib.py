@@ -19,6 +19,7 @@ PCF_UPPER_ONLY, PCF_VALIDATE, PCF_DETERMINISTIC, PCF_REUSE_PLAN = 1, 2, 4, 8
 PCF_RECORDS_PACKED = 16
 PCF_INTEGRAL, PCF_NORM, PCF_NORM_POW = 0, 1, 2
 PCF_WEIGHT_EXP, PCF_WEIGHT_POW = 1, 2
+PCF_REDUCE_SUM, PCF_REDUCE_MEAN, PCF_REDUCE_MAX, PCF_REDUCE_MIN, PCF_REDUCE_STD = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "PCF_OK", 1: "PCF_EINVAL", 2: "PCF_EDATA", 3: "PCF_EDEVICE",
                 4: "PCF_ENOMEM", 5: "PCF_EUNSUPPORTED"}
@@ -80,6 +81,17 @@ _SIGS = {
     "pcf_restrict": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_double,
                                     ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "pcf_reduce_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int32,
+                                                  ctypes.c_void_p, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "pcf_reduce_rows": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "pcf_reduce": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p]),
     "pcf_warp_rows": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int,
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
@@ -190,6 +202,25 @@ def pcf_restrict_rows(X, a, b, offsets_out_ptr, offsets_out_host_ptr, stream):
 def pcf_restrict(X, a, b, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
     return load().pcf_restrict(ctypes.byref(X), a, b, offsets_out_ptr, t_out_ptr,
                                v_out_ptr, stream)
+
+
+def pcf_reduce_workspace_bytes(X, B, groups_ptr, op):
+    out = ctypes.c_size_t(0)
+    check(load().pcf_reduce_workspace_bytes(ctypes.byref(X), B, groups_ptr, op,
+                                            ctypes.byref(out)))
+    return out.value
+
+
+def pcf_reduce_rows(X, B, groups_ptr, op, ws_ptr, ws_bytes, offsets_out_ptr,
+                    offsets_out_host_ptr, stream):
+    return load().pcf_reduce_rows(ctypes.byref(X), B, groups_ptr, op, ws_ptr, ws_bytes,
+                                  offsets_out_ptr, offsets_out_host_ptr, stream)
+
+
+def pcf_reduce(X, B, groups_ptr, op, ws_ptr, ws_bytes, offsets_out_ptr, t_out_ptr, v_out_ptr,
+               stream):
+    return load().pcf_reduce(ctypes.byref(X), B, groups_ptr, op, ws_ptr, ws_bytes,
+                             offsets_out_ptr, t_out_ptr, v_out_ptr, stream)
 
 
 def pcf_warp_rows(X, weight, c, offsets_out_ptr, offsets_out_host_ptr, stream):

@@ -17,7 +17,8 @@ import torch
 from . import _lib
 from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
                    PCF_RECORDS_PACKED, PCF_REUSE_PLAN, PCF_UPPER_ONLY,
-                   PCF_VALIDATE, PCF_WEIGHT_EXP, PCF_WEIGHT_POW, check)
+                   PCF_VALIDATE, PCF_WEIGHT_EXP, PCF_WEIGHT_POW, PCF_REDUCE_SUM,
+                   PCF_REDUCE_MEAN, PCF_REDUCE_MAX, PCF_REDUCE_MIN, PCF_REDUCE_STD, check)
 
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
@@ -245,6 +246,38 @@ def warp(X, weight, c, stream=None):
                         _stream_handle(stream)))
     new = object.__new__(PcfSet)
     new.offsets_host, new.offsets, new.n = off_h, off_d, X.n
+    new.t, new.v = t, v
+    return new
+
+
+_REDUCE_OPS = {"sum": PCF_REDUCE_SUM, "mean": PCF_REDUCE_MEAN, "max": PCF_REDUCE_MAX,
+               "min": PCF_REDUCE_MIN, "std": PCF_REDUCE_STD}
+
+
+def reduce(X, op="mean", groups=None, workspace=None, stream=None):
+    """Reduce groups of the PCFs in ``X`` (Section 2.1 reductions, Section 4
+    reduction trees): ``op`` in sum, mean, max, min, std (sample, 1/(m-1)).
+    ``groups``: B+1 offsets into the set's PCFs (default: one group of all).
+    Returns a set of B PCFs."""
+    opc = _REDUCE_OPS.get(op, op)
+    g = np.ascontiguousarray([0, X.n] if groups is None else groups, dtype=np.int64)
+    B = len(g) - 1
+    Xc = X.c_struct()
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    ws.ensure(_lib.pcf_reduce_workspace_bytes(Xc, B, g.ctypes.data, int(opc)))
+    off_h = np.empty(B + 1, dtype=np.int64)
+    off_d = torch.empty(B + 1, dtype=torch.int64, device=X.t.device)
+    check(_lib.pcf_reduce_rows(Xc, B, g.ctypes.data, int(opc), ws.ptr, ws.nbytes,
+                               off_d.data_ptr(), off_h.ctypes.data, _stream_handle(stream)))
+    rows = int(off_h[-1])
+    t = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    v = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    check(_lib.pcf_reduce(Xc, B, g.ctypes.data, int(opc), ws.ptr, ws.nbytes, off_d.data_ptr(),
+                          t.data_ptr(), v.data_ptr(), _stream_handle(stream)))
+    ws.planned = None
+    ws.packed_data = None
+    new = object.__new__(PcfSet)
+    new.offsets_host, new.offsets, new.n = off_h, off_d, B
     new.t, new.v = t, v
     return new
 

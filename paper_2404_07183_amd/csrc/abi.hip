@@ -356,6 +356,80 @@ pcf_status check_weight(int weight, double c)
     return fail(PCF_EINVAL, "weight: PCF_WEIGHT_EXP needs c > 0, PCF_WEIGHT_POW c > -1");
 }
 
+// A reduction's host plan: group checks, the tree depth and the workspace
+// layout (group offsets and per-level pair prefixes, item row counts, two
+// ping-pong row buffers, the deviation sums of a standard deviation).
+struct RedPlan {
+    int32_t B = 0;
+    int L = 0;
+    int64_t n = 0, P = 0;
+    std::vector<int64_t> meta;  // groups (B+1), then L arrays of B+1 prefixes
+    size_t off_cnt = 0, off_buf[4] = {0, 0, 0, 0}, off_q = 0, bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
+                    hipStream_t s, RedPlan &rp)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (op < PCF_REDUCE_SUM || op > PCF_REDUCE_STD)
+        return fail(PCF_EINVAL, "unknown reduction op");
+    if (B < 0 || (B > 0 && !groups))
+        return fail(PCF_EINVAL, "B < 0 or group_offsets_host is NULL");
+    const int64_t n = X->n;
+    if (B == 0 ? n != 0 : (groups[0] != 0 || groups[B] != n))
+        return fail(PCF_EINVAL, "the groups must cover the set's PCFs 0 .. n-1");
+    int64_t mmax = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t m = groups[b + 1] - groups[b];
+        if (m < (op == PCF_REDUCE_STD ? 2 : 1))
+            return fail(PCF_EINVAL, "group " + std::to_string(b) + " has " + std::to_string(m) +
+                                        " PCFs (at least 1, 2 for PCF_REDUCE_STD)");
+        mmax = m > mmax ? m : mmax;
+    }
+    std::vector<int64_t> obuf;
+    const int64_t *ho = nullptr;
+    if (n > 0) {
+        st = host_offsets(X, obuf, ho, s);
+        if (st != PCF_OK)
+            return st;
+    }
+    rp.B = B;
+    rp.n = n;
+    rp.P = n > 0 ? ho[n] : 0;
+    rp.L = 0;
+    while (((int64_t)1 << rp.L) < mmax)
+        ++rp.L;
+    if (groups)
+        rp.meta.assign(groups, groups + B + 1);
+    else
+        rp.meta.assign(1, 0);
+    for (int l = 0; l < rp.L; ++l) {
+        const int64_t span = (int64_t)1 << (l + 1);
+        int64_t acc = 0;
+        rp.meta.push_back(0);
+        for (int32_t b = 0; b < B; ++b) {
+            acc += (groups[b + 1] - groups[b] + span - 1) / span;
+            rp.meta.push_back(acc);
+        }
+    }
+    const size_t esz = X->dtype == PCF_F64 ? 8 : 4;
+    size_t off = align256(rp.meta.size() * sizeof(int64_t));
+    rp.off_cnt = off;
+    off += align256((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int k = 0; k < 4; ++k) {
+        rp.off_buf[k] = off;
+        off += align256((size_t)(rp.P > 0 ? rp.P : 1) * esz);
+    }
+    rp.off_q = off;
+    off += align256((size_t)(rp.P > 0 ? rp.P : 1) * esz);
+    rp.bytes = off;
+    return PCF_OK;
+}
+
 // The bounds of a restriction in the set's precision: 0 <= a < b <= inf,
 // both still ordered (and b still finite when given finite) once rounded.
 pcf_status check_range(const pcf_set *X, double a, double b)
@@ -873,6 +947,152 @@ pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
                                     (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "warp kernel launch");
+    return PCF_OK;
+}
+
+pcf_status pcf_reduce_workspace_bytes(const pcf_set *X, int32_t B,
+                                      const int64_t *group_offsets_host, pcf_reduce_op op,
+                                      size_t *bytes)
+{
+    if (!bytes)
+        return fail(PCF_EINVAL, "bytes is NULL");
+    RedPlan rp;
+    pcf_status st = red_plan(X, B, group_offsets_host, (int)op, nullptr, rp);
+    if (st != PCF_OK)
+        return st;
+    *bytes = rp.bytes;
+    return PCF_OK;
+}
+
+namespace {
+
+// The sum tree's roots (or the set itself when no group has two PCFs).
+void red_roots(const pcf_set *X, const RedPlan &rp, unsigned char *w, const void *&rt,
+               const void *&rv)
+{
+    if (rp.L == 0) {
+        rt = X->t;
+        rv = X->v;
+    } else {
+        const int k = (rp.L - 1) % 2;
+        rt = w + rp.off_buf[2 * k];
+        rv = w + rp.off_buf[2 * k + 1];
+    }
+}
+
+}  // namespace
+
+pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
+                           pcf_reduce_op op, void *ws, size_t ws_bytes, int64_t *offsets_out,
+                           int64_t *offsets_out_host, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    RedPlan rp;
+    pcf_status st = red_plan(X, B, group_offsets_host, (int)op, s, rp);
+    if (st != PCF_OK)
+        return st;
+    if (!offsets_out || !offsets_out_host)
+        return fail(PCF_EINVAL, "offsets_out or offsets_out_host is NULL");
+    if (B == 0)
+        return counts_to_offsets(0, offsets_out, offsets_out_host, s, "reduced");
+    if (!ws || ws_bytes < rp.bytes)
+        return fail(PCF_ENOMEM, "workspace too small: need " + std::to_string(rp.bytes) +
+                                    " bytes, got " + std::to_string(ws_bytes));
+    unsigned char *w = (unsigned char *)ws;
+    int64_t *meta = (int64_t *)w, *cnt = (int64_t *)(w + rp.off_cnt);
+    hipError_t e = hipMemcpyAsync(meta, rp.meta.data(), rp.meta.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // rp.meta is a local
+    if (e == hipSuccess)
+        e = launch_red_init(X->offsets, rp.n, cnt, s);
+    const bool f64 = X->dtype == PCF_F64;
+    for (int l = 0; l < rp.L && e == hipSuccess; ++l) {
+        RedLevelArgs a;
+        a.offsets = X->offsets;
+        a.groups = meta;
+        a.items = meta + (size_t)(B + 1) * (size_t)(l + 1);
+        a.B = B;
+        a.level = l;
+        const int ki = (l + 1) % 2, ko = l % 2;  // level l writes buffer pair l % 2
+        a.tin = l == 0 ? X->t : (const void *)(w + rp.off_buf[2 * ki]);
+        a.vin = l == 0 ? X->v : (const void *)(w + rp.off_buf[2 * ki + 1]);
+        a.tout = w + rp.off_buf[2 * ko];
+        a.vout = w + rp.off_buf[2 * ko + 1];
+        a.cnt = cnt;
+        e = launch_red_level(f64, (int)op, a, rp.meta[(size_t)(B + 1) * (size_t)(l + 2) - 1], s);
+    }
+    const void *rt, *rv;
+    red_roots(X, rp, w, rt, rv);
+    if (e == hipSuccess && op == PCF_REDUCE_STD) {
+        RedStdArgs a;
+        a.offsets = X->offsets;
+        a.groups = meta;
+        a.B = B;
+        a.rows = rp.P;
+        a.t = X->t;
+        a.v = X->v;
+        a.rt = rt;
+        a.rv = rv;
+        a.cnt = cnt;
+        a.q = w + rp.off_q;
+        e = launch_red_std(f64, a, s);
+        rv = w + rp.off_q;
+    }
+    if (e == hipSuccess) {
+        RedEmitArgs a;
+        a.offsets = X->offsets;
+        a.groups = meta;
+        a.B = B;
+        a.op = (int)op;
+        a.rt = rt;
+        a.rv = rv;
+        a.cnt = cnt;
+        a.fill = 0;
+        a.counts = offsets_out;
+        a.out_off = nullptr;
+        a.t_out = a.v_out = nullptr;
+        e = launch_red_emit(f64, a, s);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "reduction launch");
+    return counts_to_offsets(B, offsets_out, offsets_out_host, s, "reduced");
+}
+
+pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
+                      pcf_reduce_op op, const void *ws, size_t ws_bytes,
+                      const int64_t *offsets_out, void *t_out, void *v_out, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    RedPlan rp;
+    pcf_status st = red_plan(X, B, group_offsets_host, (int)op, s, rp);
+    if (st != PCF_OK)
+        return st;
+    if (B == 0)
+        return PCF_OK;
+    if (!ws || ws_bytes < rp.bytes)
+        return fail(PCF_ENOMEM, "workspace too small");
+    if (!offsets_out || !t_out || !v_out)
+        return fail(PCF_EINVAL, "an output pointer is NULL");
+    unsigned char *w = (unsigned char *)ws;
+    const void *rt, *rv;
+    red_roots(X, rp, w, rt, rv);
+    RedEmitArgs a;
+    a.offsets = X->offsets;
+    a.groups = (const int64_t *)w;
+    a.B = B;
+    a.op = (int)op;
+    a.rt = rt;
+    a.rv = op == PCF_REDUCE_STD ? (const void *)(w + rp.off_q) : rv;
+    a.cnt = (const int64_t *)(w + rp.off_cnt);
+    a.fill = 1;
+    a.counts = nullptr;
+    a.out_off = offsets_out;
+    a.t_out = t_out;
+    a.v_out = v_out;
+    hipError_t e = launch_red_emit(X->dtype == PCF_F64, a, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "reduction launch");
     return PCF_OK;
 }
 

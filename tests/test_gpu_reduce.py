@@ -1,0 +1,96 @@
+"""GPU parity of the reductions (Section 2.1 reductions; Section 4,
+Algorithm ReducePair and reduction trees) against the oracle's ReducePair
+tree. Both sides pair neighbours level by level and add in the same order,
+so FP64 results are compared row for row, bit for bit; FP32 sums, maxima
+and minima too, FP32 means and standard deviations pointwise within a few
+ulps of the values."""
+import numpy as np
+import pytest
+
+from oracle import reduce as red
+from paper_2404_07183_amd import api, workloads
+from paper_2404_07183_amd._lib import PcfError
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+OPS = ["sum", "mean", "max", "min", "std"]
+
+
+def _rows(S):
+    o = S.offsets_host
+    t, v = S.t.cpu().numpy(), S.v.cpu().numpy()
+    return [(t[o[b]:o[b + 1]], v[o[b]:o[b + 1]]) for b in range(S.n)]
+
+
+def _tied_set(n, seed, dtype=np.float64):
+    """PCFs on a coarse dyadic time grid: many breakpoints shared across PCFs."""
+    rng = np.random.default_rng(seed)
+    pcfs = []
+    for _ in range(n):
+        k = int(rng.integers(1, 20))
+        ts = np.concatenate([[0.0], np.sort(rng.choice(np.arange(1, 64), k - 1, replace=False))]) / 8
+        vs = np.concatenate([rng.standard_normal(k - 1), [0.0]])
+        pcfs.append((ts, vs))
+    o = np.concatenate([[0], np.cumsum([len(p[0]) for p in pcfs])])
+    return (o, np.concatenate([p[0] for p in pcfs]).astype(dtype),
+            np.concatenate([p[1] for p in pcfs]).astype(dtype))
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("data", ["uniform", "tied"])
+def test_reduce_fp64_bit_exact(op, data):
+    if data == "uniform":
+        o, t, v = workloads.uniform_counts(120, 1, 60, seed=101)
+    else:
+        o, t, v = _tied_set(120, seed=102)
+    groups = [0, 1, 3, 6, 13, 29, 45, 78, 79, 120] if op != "std" else \
+        [0, 2, 5, 12, 29, 45, 78, 80, 120]
+    X = api.PcfSet(o, t, v, device=DEV)
+    got = _rows(api.reduce(X, op, groups))
+    want = red.reduce_groups(op, groups, o, t, v)
+    for b, ((gt, gv), (wt, wv)) in enumerate(zip(got, want)):
+        assert np.array_equal(gt, wt), (op, b, len(gt), len(wt))
+        assert np.array_equal(gv, wv), (op, b)
+
+
+def test_reduce_deep_tree_and_one_group():
+    o, t, v = workloads.uniform_counts(1000, 1, 40, seed=103)
+    X = api.PcfSet(o, t, v, device=DEV)
+    for op in ("mean", "max"):
+        (gt, gv), = _rows(api.reduce(X, op))
+        (wt, wv), = red.reduce_groups(op, [0, 1000], o, t, v)
+        assert np.array_equal(gt, wt) and np.array_equal(gv, wv), op
+    # 250 groups of 4 in one call
+    groups = np.arange(0, 1001, 4)
+    got = _rows(api.reduce(X, "std", groups))
+    want = red.reduce_groups("std", groups, o, t, v)
+    assert all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+               for a, b in zip(got, want))
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_reduce_fp32(op):
+    o, t, v = workloads.uniform_counts(90, 1, 50, seed=104, dtype=np.float32)
+    groups = [0, 2, 9, 40, 90]
+    X = api.PcfSet(o, t, v, device=DEV)
+    got = _rows(api.reduce(X, op, groups))
+    want = red.reduce_groups(op, groups, o, t, v, dtype=np.float32)
+    for (gt, gv), (wt, wv) in zip(got, want):
+        if op in ("sum", "max", "min"):
+            assert np.array_equal(gt, wt) and np.array_equal(gv, wv)
+            continue
+        x = np.unique(np.concatenate([gt, wt]))
+        a = red.evaluate((gt, gv), x).astype(np.float64)
+        b = red.evaluate((wt, wv), x).astype(np.float64)
+        assert np.all(np.abs(a - b) <= 4 * np.finfo(np.float32).eps * np.abs(b))
+
+
+def test_reduce_errors():
+    o, t, v = workloads.uniform_counts(10, 1, 20, seed=105)
+    X = api.PcfSet(o, t, v, device=DEV)
+    with pytest.raises(PcfError):
+        api.reduce(X, "mean", [0, 4, 4, 10])  # empty group
+    with pytest.raises(PcfError):
+        api.reduce(X, "std", [0, 1, 10])  # std of one PCF
+    with pytest.raises(PcfError):
+        api.reduce(X, "mean", [0, 5])  # groups must cover the set
