@@ -357,6 +357,60 @@ def run_single(steps, warmup):
                        "tolerance": 1e-12}}
 
 
+def run_reduce(steps, warmup):
+    """Mean of the plain 20,000-PCF set (FP64) as one group: a binary tree of
+    15 levels, each reading and writing about every row once (continuous
+    times share no breakpoints), then the root's rows. Algorithmic bytes:
+    per level, t and v of every input row read and of every output row
+    written; the root read twice (count, fill) and written once. The time is
+    the whole api.reduce call, host round trip for the output size included.
+    Also the std of 1,000 groups of 20 PCFs."""
+    import torch
+
+    from paper_2404_07183_amd import api, workloads
+
+    o, t, v = workloads.config_plain()
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    ws = api.Workspace(device="cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, op, groups in (("mean_one_group", "mean", None),
+                             ("std_1000_groups_of_20", "std", np.arange(0, X.n + 1, 20))):
+        call = lambda: api.reduce(X, op, groups, workspace=ws)
+        for _ in range(warmup):
+            out = call()
+        torch.cuda.synchronize()
+        ms = _events_ms(call, steps, stream)
+        res[name] = {"ms_per_call": ms, "out_rows": int(out.offsets_host[-1])}
+    P = int(o[-1])
+    levels = int(np.ceil(np.log2(X.n)))
+    root = res["mean_one_group"]["out_rows"]
+    nbytes = levels * 2 * P * 16 + 3 * root * 16
+    ms = res["mean_one_group"]["ms_per_call"]
+    # parity at sampled times: the tree's mean against NumPy's, within the
+    # rounding of a 15-level sum
+    out = api.reduce(X, "mean", workspace=ws)
+    gt, gv = out.t.cpu().numpy(), out.v.cpu().numpy()
+    rng = np.random.default_rng(7)
+    x = np.sort(rng.uniform(0.0, float(t.max()) * 1.01, 256))
+    vals = np.stack([v[o[i]:o[i + 1]][np.searchsorted(t[o[i]:o[i + 1]], x, side="right") - 1]
+                     for i in range(X.n)])
+    want = vals.mean(0)
+    got = gv[np.searchsorted(gt, x, side="right") - 1]
+    err = float(np.max(np.abs(got - want) / np.maximum(np.abs(vals).mean(0), 1e-300)))
+    res.update({"workload": "mean of N=20000 PCFs (counts U{50..500}) as one group, FP64; "
+                            "std of 1000 groups of 20",
+                "pcfs": int(X.n), "rows": P, "tree_levels": levels,
+                "pcfs_per_s": X.n / (ms * 1e-3),
+                "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
+                             "peak": 8000.0, "unit": "GB/s",
+                             "frac": nbytes / (ms * 1e-3) / 1e9 / 8000.0,
+                             "bytes_per_call": nbytes},
+                "parity": {"sampled_times": len(x), "max_error_over_scale": err,
+                           "tolerance": 1e-13}})
+    return res
+
+
 def run_grad(steps, warmup, plain_steps_per_s=None):
     """Forward + adjoint of L = sum W_ij d_2(f_i,f_j)^2 + sum U_ij <f_i,f_j>,
     N = 4,096 PCFs, FP64 (two forward matrices, two adjoint passes)."""
@@ -505,6 +559,7 @@ def main():
         res["fwd_bwd"] = run_grad(max(2, args.steps // 2), 1, plain)
         res["cross"] = run_cross(max(2, args.steps // 2), 1, plain)
         res["single"] = run_single(max(2, args.steps // 2), 1)
+        res["reduce"] = run_reduce(max(2, args.steps // 2), 1)
     print(json.dumps(res), flush=True)
 
 

@@ -357,14 +357,17 @@ pcf_status check_weight(int weight, double c)
 }
 
 // A reduction's host plan: group checks, the tree depth and the workspace
-// layout (group offsets and per-level pair prefixes, item row counts, two
-// ping-pong row buffers, the deviation sums of a standard deviation).
+// layout (group offsets and the root pass's chunk table, chunk counts and
+// output offsets, two ping-pong row buffers, the deviation sums of a
+// standard deviation).
+constexpr int64_t kRedChunkRows = 1024;  // the root pass's chunk (reduce.hip)
+
 struct RedPlan {
     int32_t B = 0;
     int L = 0;
-    int64_t n = 0, P = 0;
-    std::vector<int64_t> meta;  // groups (B+1), then L arrays of B+1 prefixes
-    size_t off_cnt = 0, off_buf[4] = {0, 0, 0, 0}, off_q = 0, bytes = 0;
+    int64_t n = 0, P = 0, C = 0;  // PCFs, rows, chunks
+    std::vector<int64_t> meta;    // groups (B+1), chunk rows (C), chunk groups (C)
+    size_t off_ccnt = 0, off_coff = 0, off_buf[4] = {0, 0, 0, 0}, off_q = 0, bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -396,6 +399,9 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
         st = host_offsets(X, obuf, ho, s);
         if (st != PCF_OK)
             return st;
+        for (int64_t i = 0; i < n; ++i)
+            if (ho[i + 1] <= ho[i])
+                return fail(PCF_EINVAL, "PCF " + std::to_string(i) + " has no rows");
     }
     rp.B = B;
     rp.n = n;
@@ -407,19 +413,22 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
         rp.meta.assign(groups, groups + B + 1);
     else
         rp.meta.assign(1, 0);
-    for (int l = 0; l < rp.L; ++l) {
-        const int64_t span = (int64_t)1 << (l + 1);
-        int64_t acc = 0;
-        rp.meta.push_back(0);
-        for (int32_t b = 0; b < B; ++b) {
-            acc += (groups[b + 1] - groups[b] + span - 1) / span;
-            rp.meta.push_back(acc);
+    std::vector<int64_t> crow, cgrp;
+    for (int32_t b = 0; b < B; ++b)
+        for (int64_t r = ho[groups[b]]; r < ho[groups[b + 1]]; r += kRedChunkRows) {
+            crow.push_back(r);
+            cgrp.push_back(b);
         }
-    }
+    rp.C = (int64_t)crow.size();
+    rp.meta.insert(rp.meta.end(), crow.begin(), crow.end());
+    rp.meta.insert(rp.meta.end(), cgrp.begin(), cgrp.end());
     const size_t esz = X->dtype == PCF_F64 ? 8 : 4;
+    const size_t cbytes = align256((size_t)(rp.C > 0 ? rp.C : 1) * sizeof(int64_t));
     size_t off = align256(rp.meta.size() * sizeof(int64_t));
-    rp.off_cnt = off;
-    off += align256((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    rp.off_ccnt = off;
+    off += cbytes;
+    rp.off_coff = off;
+    off += cbytes;
     for (int k = 0; k < 4; ++k) {
         rp.off_buf[k] = off;
         off += align256((size_t)(rp.P > 0 ? rp.P : 1) * esz);
@@ -999,19 +1008,17 @@ pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_off
         return fail(PCF_ENOMEM, "workspace too small: need " + std::to_string(rp.bytes) +
                                     " bytes, got " + std::to_string(ws_bytes));
     unsigned char *w = (unsigned char *)ws;
-    int64_t *meta = (int64_t *)w, *cnt = (int64_t *)(w + rp.off_cnt);
+    int64_t *meta = (int64_t *)w;
     hipError_t e = hipMemcpyAsync(meta, rp.meta.data(), rp.meta.size() * sizeof(int64_t),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);  // rp.meta is a local
-    if (e == hipSuccess)
-        e = launch_red_init(X->offsets, rp.n, cnt, s);
     const bool f64 = X->dtype == PCF_F64;
     for (int l = 0; l < rp.L && e == hipSuccess; ++l) {
         RedLevelArgs a;
         a.offsets = X->offsets;
         a.groups = meta;
-        a.items = meta + (size_t)(B + 1) * (size_t)(l + 1);
+        a.n = rp.n;
         a.B = B;
         a.level = l;
         const int ki = (l + 1) % 2, ko = l % 2;  // level l writes buffer pair l % 2
@@ -1019,8 +1026,7 @@ pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_off
         a.vin = l == 0 ? X->v : (const void *)(w + rp.off_buf[2 * ki + 1]);
         a.tout = w + rp.off_buf[2 * ko];
         a.vout = w + rp.off_buf[2 * ko + 1];
-        a.cnt = cnt;
-        e = launch_red_level(f64, (int)op, a, rp.meta[(size_t)(B + 1) * (size_t)(l + 2) - 1], s);
+        e = launch_red_level(f64, (int)op, a, rp.P, s);
     }
     const void *rt, *rv;
     red_roots(X, rp, w, rt, rv);
@@ -1034,29 +1040,58 @@ pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_off
         a.v = X->v;
         a.rt = rt;
         a.rv = rv;
-        a.cnt = cnt;
         a.q = w + rp.off_q;
         e = launch_red_std(f64, a, s);
         rv = w + rp.off_q;
     }
+    int64_t *ccnt = (int64_t *)(w + rp.off_ccnt), *coff = (int64_t *)(w + rp.off_coff);
     if (e == hipSuccess) {
         RedEmitArgs a;
         a.offsets = X->offsets;
         a.groups = meta;
-        a.B = B;
         a.op = (int)op;
         a.rt = rt;
         a.rv = rv;
-        a.cnt = cnt;
+        a.nchunks = rp.C;
+        a.chunk_row = meta + B + 1;
+        a.chunk_grp = meta + B + 1 + rp.C;
         a.fill = 0;
-        a.counts = offsets_out;
-        a.out_off = nullptr;
+        a.chunk_cnt = ccnt;
+        a.chunk_off = nullptr;
+        a.out_end = nullptr;
         a.t_out = a.v_out = nullptr;
         e = launch_red_emit(f64, a, s);
     }
+    std::vector<int64_t> cc((size_t)rp.C);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cc.data(), ccnt, sizeof(int64_t) * (size_t)rp.C,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
     if (e != hipSuccess)
         return hip_fail(e, "reduction launch");
-    return counts_to_offsets(B, offsets_out, offsets_out_host, s, "reduced");
+    // chunk counts -> chunk output offsets (chunks are in group order) and
+    // per-group offsets
+    const int64_t *cgrp = rp.meta.data() + B + 1 + rp.C;
+    std::vector<int64_t> gc((size_t)B, 0);
+    int64_t acc = 0;
+    for (int64_t c = 0; c < rp.C; ++c) {
+        const int64_t k = cc[(size_t)c];
+        cc[(size_t)c] = acc;
+        acc += k;
+        gc[(size_t)cgrp[c]] += k;
+    }
+    offsets_out_host[0] = 0;
+    for (int32_t b = 0; b < B; ++b)
+        offsets_out_host[b + 1] = offsets_out_host[b] + gc[(size_t)b];
+    e = hipMemcpyAsync(coff, cc.data(), sizeof(int64_t) * (size_t)rp.C, hipMemcpyHostToDevice,
+                       s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(offsets_out, offsets_out_host, sizeof(int64_t) * (size_t)(B + 1),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // cc and offsets_out_host may be locals
+    return e == hipSuccess ? PCF_OK : hip_fail(e, "writing the reduced offsets");
 }
 
 pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
@@ -1075,19 +1110,22 @@ pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_
     if (!offsets_out || !t_out || !v_out)
         return fail(PCF_EINVAL, "an output pointer is NULL");
     unsigned char *w = (unsigned char *)ws;
+    const int64_t *meta = (const int64_t *)w;
     const void *rt, *rv;
     red_roots(X, rp, w, rt, rv);
     RedEmitArgs a;
     a.offsets = X->offsets;
-    a.groups = (const int64_t *)w;
-    a.B = B;
+    a.groups = meta;
     a.op = (int)op;
     a.rt = rt;
     a.rv = op == PCF_REDUCE_STD ? (const void *)(w + rp.off_q) : rv;
-    a.cnt = (const int64_t *)(w + rp.off_cnt);
+    a.nchunks = rp.C;
+    a.chunk_row = meta + B + 1;
+    a.chunk_grp = meta + B + 1 + rp.C;
     a.fill = 1;
-    a.counts = nullptr;
-    a.out_off = offsets_out;
+    a.chunk_cnt = nullptr;
+    a.chunk_off = (const int64_t *)(w + rp.off_coff);
+    a.out_end = offsets_out + B;
     a.t_out = t_out;
     a.v_out = v_out;
     hipError_t e = launch_red_emit(X->dtype == PCF_F64, a, s);

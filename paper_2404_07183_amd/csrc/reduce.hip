@@ -7,21 +7,23 @@
 // 2j and 2j+1 (each covering 2^l consecutive PCFs) are merged into item j of
 // level l+1, and an unpaired last item moves up unchanged. Every group takes
 // the same ceil(log2 M_max) levels, one launch per level for all groups.
-// Item j of a level writes where its first PCF's rows start: the union of
-// two PCFs' breakpoints has at most their total row count, so item ranges
-// never overlap and no per-level scan is needed.
 //
-// Merge. One wave per pair. The merged sequence of the two breakpoint
-// lists (ties: the first list first) is cut into 64 x kMergeK positions per
-// window; each lane finds its start by a merge-path search and walks
-// kMergeK positions. A position opens a cell (a rectangle of ReducePair)
-// when the next breakpoint of either list is later; the cell's value is
-// h(f(x), g(x)). Lanes write their cells in order after a wave scan of the
-// counts. No cell is dropped inside the tree: ReducePair's rule (keep a row
-// when t = 0 or its value differs from the previous one) is applied once,
-// to the root. That gives the same function and the same minimal rows,
-// since the values at each breakpoint do not depend on which rows the
-// intermediate PCFs kept.
+// Merge without compaction. A level keeps every position of the merged
+// breakpoint lists (ties: the first list first), so item j of level l+1
+// holds exactly the rows of its 2^(l+1) PCFs, in the same place: position q
+// of a pair is row offsets[first PCF] + q of the output buffer. Every row
+// with time x carries h(f(x), g(x)): a list's value at x is its next row's
+// when that row also lies at x (all rows at one time carry the same value,
+// by induction from the strictly increasing inputs), else its last row's.
+// Positions are independent given the merge state, so one launch per level
+// covers all rows of all pairs: a lane walks kMergeK consecutive rows after
+// a merge-path search, moving on to the next pair in place when it crosses
+// one. ReducePair's row rule (keep t = 0 and value changes) is applied once,
+// to the root, where runs of rows at one time collapse to their first: the
+// same function and the same minimal rows as pruning at every level, since
+// the values at each breakpoint do not depend on which rows the
+// intermediate PCFs kept. The root pass is cut into chunks of rows; the
+// host turns the chunk counts into output offsets.
 //
 // Standard deviation. For every breakpoint x of the group's root,
 // (f_i(x) - mean(x))^2 is summed over i in the tree's order (a binary
@@ -35,7 +37,8 @@ namespace pcf {
 
 namespace {
 
-constexpr int kMergeK = 4;
+constexpr int kMergeK = 16;
+constexpr int kChunkRows = 1024;  // rows per wave in the root pass
 
 template <typename T, int OP>
 __device__ __forceinline__ T red_op(T a, T b)
@@ -48,13 +51,13 @@ __device__ __forceinline__ T red_op(T a, T b)
         return a + b;
 }
 
-// Group b holding wave item w: the last b with prefix[b] <= w.
-__device__ __forceinline__ int32_t group_of(const int64_t *prefix, int32_t B, int64_t w)
+// Last index k in [0, n) with x[k] <= r (x[0] <= r).
+__device__ __forceinline__ int64_t last_le(const int64_t *x, int64_t n, int64_t r)
 {
-    int32_t lo = 0, hi = B - 1;
+    int64_t lo = 0, hi = n - 1;
     while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= w)
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (x[mid] <= r)
             lo = mid;
         else
             hi = mid - 1;
@@ -62,28 +65,30 @@ __device__ __forceinline__ int32_t group_of(const int64_t *prefix, int32_t B, in
     return lo;
 }
 
-__device__ __forceinline__ int wave_excl_scan(int c, int lane, int &total)
+// The pair of a level that holds a row: its lists' row ranges and the row
+// where the pair's output begins.
+struct PairAt {
+    int64_t b;         // group
+    int64_t iA, iE;    // first PCF of the pair, one past its last PCF
+    int64_t sA, nA, sB, nB;
+};
+
+__device__ __forceinline__ void pair_from(const RedLevelArgs &a, int64_t b, int64_t iA,
+                                          int64_t span, PairAt &p)
 {
-    int incl = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o)
-            incl += y;
-    }
-    total = __shfl(incl, 63, 64);
-    return incl - c;
+    const int64_t ge = a.groups[b + 1];
+    const int64_t iB = iA + span < ge ? iA + span : ge;
+    const int64_t iE = iA + 2 * span < ge ? iA + 2 * span : ge;
+    p.b = b;
+    p.iA = iA;
+    p.iE = iE;
+    p.sA = a.offsets[iA];
+    p.sB = a.offsets[iB];
+    p.nA = p.sB - p.sA;
+    p.nB = a.offsets[iE] - p.sB;
 }
 
 }  // namespace
-
-__global__ void red_init_counts(const int64_t *__restrict__ offsets, int64_t n,
-                                int64_t *__restrict__ cnt)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        cnt[i] = offsets[i + 1] - offsets[i];
-}
 
 template <typename T, int OP>
 __global__ void red_level(RedLevelArgs a)
@@ -92,74 +97,62 @@ __global__ void red_level(RedLevelArgs a)
     const T *__restrict__ vin = reinterpret_cast<const T *>(a.vin);
     T *__restrict__ tout = reinterpret_cast<T *>(a.tout);
     T *__restrict__ vout = reinterpret_cast<T *>(a.vout);
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int64_t nitems = a.items[a.B];
     const int64_t span = (int64_t)1 << a.level;
-    const T inf = (T)INFINITY;
-    for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nitems;
-         w += nwaves) {
-        const int32_t b = group_of(a.items, a.B, w);
-        const int64_t j = w - a.items[b];
-        const int64_t ge = a.groups[b + 1];
-        const int64_t iA = a.groups[b] + 2 * j * span, iB = iA + span;
-        const int64_t sA = a.offsets[iA], nA = a.cnt[iA];
-        if (iB >= ge) {  // unpaired: moves up unchanged
-            for (int64_t k = lane; k < nA; k += 64) {
-                tout[sA + k] = tin[sA + k];
-                vout[sA + k] = vin[sA + k];
+    const int64_t r0g = a.offsets[a.groups[0]], r1g = a.offsets[a.groups[a.B]];
+    for (int64_t r0 = r0g + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kMergeK;
+         r0 < r1g; r0 += (int64_t)gridDim.x * blockDim.x * kMergeK) {
+        const int64_t r1 = r0 + kMergeK < r1g ? r0 + kMergeK : r1g;
+        // the pair holding row r0, and the merge state at its position
+        const int64_t pcf = last_le(a.offsets, a.n + 1, r0);
+        const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
+        PairAt p;
+        pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span), span, p);
+        int64_t q = r0 - p.sA;
+        int64_t i, j;
+        {
+            int64_t lo = q - p.nB > 0 ? q - p.nB : 0, hi = q < p.nA ? q : p.nA;
+            const T *tA = tin + p.sA, *tB = tin + p.sB;
+            while (lo < hi) {  // A's share of the first q merged positions
+                const int64_t mid = (lo + hi) >> 1;
+                if (tA[mid] <= tB[q - 1 - mid])
+                    lo = mid + 1;
+                else
+                    hi = mid;
             }
-            continue;
+            i = lo;
+            j = q - lo;
         }
-        const int64_t sB = a.offsets[iB], nB = a.cnt[iB];
-        const T *tA = tin + sA, *vA = vin + sA, *tB = tin + sB, *vB = vin + sB;
-        const int64_t total = nA + nB;
-        int64_t out = 0;
-        for (int64_t wb = 0; wb < total; wb += 64 * kMergeK) {
-            const int64_t d = wb + (int64_t)lane * kMergeK;
-            T xs[kMergeK], vs[kMergeK];
-            unsigned starts = 0;
-            if (d < total) {
-                int64_t lo = d - nB > 0 ? d - nB : 0, hi = d < nA ? d : nA;
-                while (lo < hi) {  // A's share of the first d merged positions
-                    const int64_t mid = (lo + hi) >> 1;
-                    if (tA[mid] <= tB[d - 1 - mid])
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                int64_t i = lo, jj = d - lo;
-#pragma unroll
-                for (int q = 0; q < kMergeK; ++q) {
-                    if (d + q < total) {
-                        T x;
-                        if (i < nA && (jj >= nB || tA[i] <= tB[jj]))
-                            x = tA[i++];
-                        else
-                            x = tB[jj++];
-                        const T ta = i < nA ? tA[i] : inf, tb = jj < nB ? tB[jj] : inf;
-                        if (x < (ta < tb ? ta : tb)) {
-                            starts |= 1u << q;
-                            xs[q] = x;
-                            vs[q] = red_op<T, OP>(vA[i > 0 ? i - 1 : 0], vB[jj > 0 ? jj - 1 : 0]);
-                        }
-                    }
-                }
+        for (int64_t r = r0; r < r1; ++r) {
+            if (q == p.nA + p.nB) {  // crossed into the next pair (or group)
+                int64_t nb = p.b, ni = p.iE;
+                if (ni == a.groups[nb + 1])
+                    ++nb;
+                pair_from(a, nb, ni, span, p);
+                q = i = j = 0;
             }
-            int wtotal;
-            int64_t pos = out + wave_excl_scan(__popc(starts), lane, wtotal);
-#pragma unroll
-            for (int q = 0; q < kMergeK; ++q) {
-                if (starts & (1u << q)) {
-                    tout[sA + pos] = xs[q];
-                    vout[sA + pos] = vs[q];
-                    ++pos;
-                }
+            const T *tA = tin + p.sA, *vA = vin + p.sA, *tB = tin + p.sB, *vB = vin + p.sB;
+            if (p.nB == 0) {  // unpaired: moves up unchanged
+                tout[r] = tA[q];
+                vout[r] = vA[q];
+                ++q;
+                continue;
             }
-            out += wtotal;
+            T x, fx, gx;
+            if (i < p.nA && (j >= p.nB || tA[i] <= tB[j])) {
+                x = tA[i];
+                fx = vA[i];
+                ++i;
+                gx = (j < p.nB && tB[j] == x) ? vB[j] : vB[j > 0 ? j - 1 : 0];
+            } else {
+                x = tB[j];
+                gx = vB[j];
+                ++j;
+                fx = (i < p.nA && tA[i] == x) ? vA[i] : vA[i > 0 ? i - 1 : 0];
+            }
+            tout[r] = x;
+            vout[r] = red_op<T, OP>(fx, gx);
+            ++q;
         }
-        if (lane == 0)
-            a.cnt[iA] = out;
     }
 }
 
@@ -186,9 +179,6 @@ __global__ void red_std_terms(RedStdArgs a)
                 hi = mid - 1;
         }
         const int64_t gb = a.groups[lo], ge = a.groups[lo + 1];
-        const int64_t u = r - a.offsets[gb];
-        if (u >= a.cnt[gb])
-            continue;
         const T x = rt[r];
         const T mean = rv[r] / (T)(ge - gb);
         T st[64];
@@ -224,7 +214,8 @@ __global__ void red_std_terms(RedStdArgs a)
 }
 
 // Root rows kept by ReducePair's rule (all rows of a one-PCF group), and
-// their values after the group's transformation.
+// their values after the group's transformation. One wave per chunk of at
+// most kChunkRows rows of one group.
 template <typename T>
 __device__ __forceinline__ T red_finish(int op, T x, int64_t m)
 {
@@ -245,30 +236,29 @@ __global__ void red_emit(RedEmitArgs a)
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < a.B;
-         b += nwaves) {
+    for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; c < a.nchunks;
+         c += nwaves) {
+        const int64_t b = a.chunk_grp[c];
         const int64_t gb = a.groups[b], m = a.groups[b + 1] - gb;
-        const int64_t s = a.offsets[gb], c = a.cnt[gb];
-        int64_t w = a.fill ? a.out_off[b] : 0;
-        const int64_t end = a.fill ? a.out_off[b + 1] : 0;
-        for (int64_t base = 0; base < c; base += 64) {
+        const int64_t g0 = a.offsets[gb], g1 = a.offsets[gb + m];
+        const int64_t c0 = a.chunk_row[c];
+        const int64_t c1 = c0 + kChunkRows < g1 ? c0 + kChunkRows : g1;
+        int64_t w = a.fill ? a.chunk_off[c] : 0;
+        const int64_t end = a.fill ? *a.out_end : 0;
+        for (int64_t base = c0; base < c1; base += 64) {
             const int64_t k = base + lane;
-            const bool keep = k < c && (m == 1 || k == 0 || rv[s + k] != rv[s + k - 1]);
+            const bool keep = k < c1 && (m == 1 || k == g0 ||
+                                         (rt[k] != rt[k - 1] && rv[k] != rv[k - 1]));
             const uint64_t mask = __ballot(keep);
-            if (a.fill) {
-                const int64_t pos = w + __popcll(mask & below);
-                if (keep && pos < end) {
-                    t_out[pos] = rt[s + k];
-                    v_out[pos] = red_finish<T>(a.op, rv[s + k], m);
-                }
+            const int64_t pos = w + __popcll(mask & below);
+            if (a.fill && keep && pos < end) {
+                t_out[pos] = rt[k];
+                v_out[pos] = red_finish<T>(a.op, rv[k], m);
             }
             w += __popcll(mask);
         }
-        if (!a.fill && lane == 0) {
-            a.counts[b + 1] = w;
-            if (b == 0)
-                a.counts[0] = 0;
-        }
+        if (!a.fill && lane == 0)
+            a.chunk_cnt[c] = w;
     }
 }
 
@@ -278,21 +268,12 @@ static int64_t grid_for(int64_t units, int64_t per_block, int64_t cap)
     return g < 1 ? 1 : (g > cap ? cap : g);
 }
 
-hipError_t launch_red_init(const int64_t *offsets, int64_t n, int64_t *cnt, hipStream_t s)
-{
-    if (n <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(red_init_counts, dim3((unsigned)grid_for(n, 256, 4096)), dim3(256), 0,
-                       s, offsets, n, cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t nitems,
+hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t rows,
                             hipStream_t s)
 {
-    if (nitems <= 0)
+    if (rows <= 0)
         return hipSuccess;
-    const dim3 g((unsigned)grid_for(nitems, 4, 16384)), blk(256);
+    const dim3 g((unsigned)grid_for((rows + kMergeK - 1) / kMergeK, 256, 16384)), blk(256);
     const int o = op == RO_MAX ? RO_MAX : (op == RO_MIN ? RO_MIN : RO_SUM);
     if (f64) {
         if (o == RO_MAX)
@@ -326,9 +307,9 @@ hipError_t launch_red_std(bool f64, const RedStdArgs &a, hipStream_t s)
 
 hipError_t launch_red_emit(bool f64, const RedEmitArgs &a, hipStream_t s)
 {
-    if (a.B <= 0)
+    if (a.nchunks <= 0)
         return hipSuccess;
-    const dim3 g((unsigned)grid_for(a.B, 4, 8192)), blk(256);
+    const dim3 g((unsigned)grid_for(a.nchunks, 4, 8192)), blk(256);
     if (f64)
         hipLaunchKernelGGL(red_emit<double>, g, blk, 0, s, a);
     else
