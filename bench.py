@@ -31,18 +31,21 @@ PEAK_FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 OPS_PER_STEP = {"l1": 4, "l2sq": 5, "l2": 5, "gram": 4}  # algorithmic FP64 ops
 
 
+# the sources the tile kernel, its launch arguments and its plan are built from
+TILE_SOURCES = ("common.hpp", "kernels.hip", "launch.hpp", "plan.cpp", "plan.hpp", "tile.hpp")
+
+
 def kernel_source_digest():
-    """SHA-256 over the library's device and host sources (file names and
-    contents, sorted by name): identifies the kernel build that counters
-    were taken on."""
+    """SHA-256 over the tile kernel's sources (file names and contents, in
+    TILE_SOURCES order): identifies the kernel build that counters were
+    taken on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2404_07183_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in TILE_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()
 
 

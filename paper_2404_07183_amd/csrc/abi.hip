@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "reduce.hpp"
 #include "pcf.h"
 #include "plan.hpp"
 

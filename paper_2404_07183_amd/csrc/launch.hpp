@@ -71,41 +71,6 @@ hipError_t launch_warp_count(bool f64, const int64_t *offsets, int64_t n, const 
 hipError_t launch_warp_fill(bool f64, const int64_t *offsets, int64_t n, const void *t,
                             const void *v, int wk, double c, const int64_t *out_off,
                             void *t_out, void *v_out, hipStream_t s);
-// Reductions of groups of PCFs (reduce.hip). Ops as in pcf_reduce_op.
-enum { RO_SUM = 0, RO_MEAN = 1, RO_MAX = 2, RO_MIN = 3, RO_STD = 4 };
-struct RedLevelArgs {
-    const int64_t *offsets;  // the set's CSR offsets (device, n+1)
-    const int64_t *groups;   // group offsets (device, B+1)
-    int64_t n;
-    int32_t B;
-    int level;               // inputs are items of 2^level PCFs
-    const void *tin, *vin;
-    void *tout, *vout;
-};
-struct RedStdArgs {
-    const int64_t *offsets, *groups;
-    int32_t B;
-    int64_t rows;            // the set's total rows
-    const void *t, *v;       // the set
-    const void *rt, *rv;     // the sum tree's roots
-    void *q;                 // out: sum of squared deviations per root row
-};
-struct RedEmitArgs {
-    const int64_t *offsets, *groups;
-    int op;
-    const void *rt, *rv;     // roots: times, and the values the rule compares
-    int64_t nchunks;         // chunks of at most 1024 rows of one group
-    const int64_t *chunk_row, *chunk_grp;
-    int fill;                // 0: chunk_cnt[c] = kept rows; 1: write them
-    int64_t *chunk_cnt;
-    const int64_t *chunk_off;
-    const int64_t *out_end;  // device: the output's total rows (fill)
-    void *t_out, *v_out;
-};
-hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t rows,
-                            hipStream_t s);
-hipError_t launch_red_std(bool f64, const RedStdArgs &a, hipStream_t s);
-hipError_t launch_red_emit(bool f64, const RedEmitArgs &a, hipStream_t s);
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);

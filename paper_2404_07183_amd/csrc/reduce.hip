@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
+#include "reduce.hpp"
 
 namespace pcf {
 
