@@ -29,7 +29,7 @@ import subprocess
 import numpy as np
 
 LP, LP_POW, GRAM = 0, 1, 2
-S_INTEGRAL, S_NORM, S_NORM_POW = 0, 1, 2
+S_INTEGRAL, S_NORM, S_NORM_POW, S_NORM_INF = 0, 1, 2, 3
 W_EXP, W_POW = 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

@@ -524,7 +524,8 @@ int orc_backward(int kind, double p, int64_t n_pcf, const int64_t *offsets,
 /*   ORC_S_INTEGRAL  h(v) = v                                               */
 /*   ORC_S_NORM      h(v) = |v|^p, r(x) = x^(1/p)                           */
 /*   ORC_S_NORM_POW  h(v) = |v|^p, r(x) = x                                 */
-enum { ORC_S_INTEGRAL = 0, ORC_S_NORM = 1, ORC_S_NORM_POW = 2 };
+/*   ORC_S_NORM_INF  sup |f| over [a, b): the largest |v| of the segments    */
+enum { ORC_S_INTEGRAL = 0, ORC_S_NORM = 1, ORC_S_NORM_POW = 2, ORC_S_NORM_INF = 3 };
 
 static double h_single(int kind, double p, double v)
 {
@@ -576,6 +577,28 @@ static double segment_sum(int kind, double p, double a, double b, const double *
     return acc;
 }
 
+/* sup over [a, b) of |f|: Algorithm IterateSegments, keeping the largest
+ * |v| of the segments it lists (each has r > l). */
+static double segment_max(double a, double b, const double *t, const double *v, int64_t n)
+{
+    double l = a;
+    int64_t k = piece_at(t, n, a);
+    double val = v[k];
+    double m = 0.0;
+    for (int64_t i = k + 1; i < n; ++i) {
+        double r = t[i] < b ? t[i] : b;
+        if (r > l && fabs(val) > m)
+            m = fabs(val);
+        if (t[i] >= b)
+            return m;
+        l = t[i];
+        val = v[i];
+    }
+    if (b > l && fabs(val) > m)
+        m = fabs(val);
+    return m;
+}
+
 /* F(f_i) for every PCF of a CSR set; abs_out[i] (optional) = sum over
  * segments of |h| * width. Returns 0, or -1 on bad arguments. */
 int orc_single(int kind, double p, double a, double b, int64_t n_pcf,
@@ -591,6 +614,9 @@ int orc_single(int kind, double p, double a, double b, int64_t n_pcf,
         if (n < 1 || !pcf_ok(t + o, v + o, n)) {
             I = NAN;
             ab = NAN;
+        } else if (kind == ORC_S_NORM_INF) {
+            I = segment_max(a, b, t + o, v + o, n);
+            ab = I;
         } else {
             I = segment_sum(kind, p, a, b, t + o, v + o, n, &ab);
         }

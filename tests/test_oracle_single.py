@@ -81,3 +81,27 @@ def test_tail_rule_and_bad_bounds():
     assert oracle.single(oracle.S_INTEGRAL, 1, 0, 4.0, o, t, v)[0] == 1.0
     with pytest.raises(ValueError):
         oracle.single(oracle.S_INTEGRAL, 1, 2.0, 2.0, o, t, v)
+
+
+def test_sup_norm():
+    # f = 2 on [0,1), -3 on [1,4), 0 after
+    o, t, v = _one([0.0, 1.0, 4.0], [2.0, -3.0, 0.0])
+    S = lambda a, b: oracle.single(oracle.S_NORM_INF, 0, a, b, o, t, v)[0]
+    assert S(0, INF) == 3.0
+    assert S(0, 1.0) == 2.0       # [0, 1) never reaches the -3 piece
+    assert S(0.5, 1.0 + 1e-9) == 3.0
+    assert S(4.0, 9.0) == 0.0     # past the last breakpoint
+    assert S(1.0, 4.0) == 3.0 and S(0.0, 0.5) == 2.0
+    # over [0, inf) it is the largest |v| of the rows (NumPy), and over split
+    # ranges the larger of the two parts
+    o, t, v = workloads.uniform_counts(40, 1, 60, seed=9)
+    whole = oracle.single(oracle.S_NORM_INF, 0, 0.0, INF, o, t, v)
+    assert np.array_equal(whole, [np.abs(v[o[i]:o[i + 1]]).max() for i in range(40)])
+    left = oracle.single(oracle.S_NORM_INF, 0, 0.0, 7.5, o, t, v)
+    right = oracle.single(oracle.S_NORM_INF, 0, 7.5, INF, o, t, v)
+    assert np.array_equal(np.maximum(left, right), whole)
+    # the L_p norm tends to the sup norm on a bounded range
+    big = oracle.single(oracle.S_NORM, 64.0, 0.0, 10.0, o, t, v)
+    sup = oracle.single(oracle.S_NORM_INF, 0, 0.0, 10.0, o, t, v)
+    assert np.all(big <= sup * 10.0 ** (1 / 64) * (1 + 1e-12))
+    assert np.all(big >= sup * 0.85)
