@@ -185,6 +185,8 @@ pcf_status pcf_cross_workspace_bytes(const pcf_set *X, const pcf_set *Y,
  *   PCF_INTEGRAL  h(v) = v                         (p ignored)
  *   PCF_NORM      h(v) = |v|^p, r(x) = x^(1/p)     (the L_p norm, p >= 1)
  *   PCF_NORM_POW  h(v) = |v|^p, r(x) = x
+ *   PCF_NORM_INF  sup over [a, b) of |f| (the largest |v| of the segments
+ *                 the iteration lists; p ignored)
  * out[i] (n entries of X's dtype, device) = F(f_i). With b = inf a nonzero
  * last value gives an infinity of the sign of h. Asynchronous on `stream`;
  * no workspace, no host copy. PCF_EINVAL on bad arguments (bounds, p,
@@ -192,7 +194,8 @@ pcf_status pcf_cross_workspace_bytes(const pcf_set *X, const pcf_set *Y,
 typedef enum {
     PCF_INTEGRAL = 0,
     PCF_NORM = 1,
-    PCF_NORM_POW = 2
+    PCF_NORM_POW = 2,
+    PCF_NORM_INF = 3
 } pcf_single_kind;
 
 pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a,

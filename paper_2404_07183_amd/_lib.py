@@ -17,7 +17,7 @@ PCF_F32, PCF_F64 = 0, 1
 PCF_LP, PCF_LP_POW, PCF_GRAM = 0, 1, 2
 PCF_UPPER_ONLY, PCF_VALIDATE, PCF_DETERMINISTIC, PCF_REUSE_PLAN = 1, 2, 4, 8
 PCF_RECORDS_PACKED = 16
-PCF_INTEGRAL, PCF_NORM, PCF_NORM_POW = 0, 1, 2
+PCF_INTEGRAL, PCF_NORM, PCF_NORM_POW, PCF_NORM_INF = 0, 1, 2, 3
 PCF_WEIGHT_EXP, PCF_WEIGHT_POW = 1, 2
 PCF_REDUCE_SUM, PCF_REDUCE_MEAN, PCF_REDUCE_MAX, PCF_REDUCE_MIN, PCF_REDUCE_STD = 0, 1, 2, 3, 4
 

@@ -307,7 +307,10 @@ def integrals(X, a=0.0, b=math.inf, *, out=None, stream=None):
 
 
 def norms(X, p=2.0, a=0.0, b=math.inf, *, power=False, out=None, stream=None):
-    """L_p norms (``power=True``: int |f_i|^p) of the PCFs of ``X`` over [a, b)."""
+    """L_p norms (``power=True``: int |f_i|^p; ``p=inf``: sup |f_i|) of the
+    PCFs of ``X`` over [a, b)."""
+    if p == math.inf:
+        return _single(X, _lib.PCF_NORM_INF, 0.0, a, b, out, stream)
     return _single(X, _lib.PCF_NORM_POW if power else _lib.PCF_NORM, p, a, b, out, stream)
 
 

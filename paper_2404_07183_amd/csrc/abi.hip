@@ -849,9 +849,10 @@ pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a
     pcf_status st = check_set(X);
     if (st != PCF_OK)
         return st;
-    if (kind != PCF_INTEGRAL && kind != PCF_NORM && kind != PCF_NORM_POW)
+    if (kind != PCF_INTEGRAL && kind != PCF_NORM && kind != PCF_NORM_POW &&
+        kind != PCF_NORM_INF)
         return fail(PCF_EINVAL, "unknown single-PCF kind");
-    if (kind != PCF_INTEGRAL && (!(p >= 1.0) || !isfinite(p)))
+    if ((kind == PCF_NORM || kind == PCF_NORM_POW) && (!(p >= 1.0) || !isfinite(p)))
         return fail(PCF_EINVAL, "p must be finite and >= 1");
     if (!(a >= 0.0) || !isfinite(a) || !(b > a))
         return fail(PCF_EINVAL, "the bounds must satisfy 0 <= a < b (b may be inf)");
@@ -869,8 +870,8 @@ pcf_status pcf_single(const pcf_set *X, pcf_single_kind kind, double p, double a
     g.b = b;
     g.p = p;
     int sk;
-    if (kind == PCF_INTEGRAL) {
-        sk = 0;
+    if (kind == PCF_INTEGRAL || kind == PCF_NORM_INF) {
+        sk = kind == PCF_INTEGRAL ? 0 : 4;  // segment sum of v, or sup of |v|
         g.root = 0;
     } else {
         sk = p == 1.0 ? 1 : (p == 2.0 ? 2 : 3);

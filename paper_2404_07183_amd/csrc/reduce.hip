@@ -38,7 +38,13 @@ namespace pcf {
 
 namespace {
 
-constexpr int kMergeK = 16;
+#ifndef PCF_RED_K
+#define PCF_RED_K 4
+#endif
+#ifndef PCF_RED_STAGE
+#define PCF_RED_STAGE 1
+#endif
+constexpr int kMergeK = PCF_RED_K;  // merged positions per lane
 constexpr int kChunkRows = 1024;  // rows per wave in the root pass
 
 template <typename T, int OP>
@@ -91,69 +97,104 @@ __device__ __forceinline__ void pair_from(const RedLevelArgs &a, int64_t b, int6
 
 }  // namespace
 
+// Wave-private ordering of LDS accesses (the staging buffers are per wave).
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A wave takes 64 * kMergeK consecutive rows; lane l walks rows
+// l * kMergeK .. of them. With PCF_RED_STAGE the results go through a
+// wave-private LDS buffer so the stores to memory are coalesced.
 template <typename T, int OP>
-__global__ void red_level(RedLevelArgs a)
+__global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
 {
     const T *__restrict__ tin = reinterpret_cast<const T *>(a.tin);
     const T *__restrict__ vin = reinterpret_cast<const T *>(a.vin);
     T *__restrict__ tout = reinterpret_cast<T *>(a.tout);
     T *__restrict__ vout = reinterpret_cast<T *>(a.vout);
+    constexpr int64_t kPerWave = 64 * kMergeK;
+#if PCF_RED_STAGE
+    __shared__ T st_t[4][kPerWave], st_v[4][kPerWave];
+#endif
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t span = (int64_t)1 << a.level;
     const int64_t r0g = a.offsets[a.groups[0]], r1g = a.offsets[a.groups[a.B]];
-    for (int64_t r0 = r0g + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kMergeK;
-         r0 < r1g; r0 += (int64_t)gridDim.x * blockDim.x * kMergeK) {
-        const int64_t r1 = r0 + kMergeK < r1g ? r0 + kMergeK : r1g;
-        // the pair holding row r0, and the merge state at its position
-        const int64_t pcf = last_le(a.offsets, a.n + 1, r0);
-        const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
-        PairAt p;
-        pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span), span, p);
-        int64_t q = r0 - p.sA;
-        int64_t i, j;
-        {
-            int64_t lo = q - p.nB > 0 ? q - p.nB : 0, hi = q < p.nA ? q : p.nA;
-            const T *tA = tin + p.sA, *tB = tin + p.sB;
-            while (lo < hi) {  // A's share of the first q merged positions
-                const int64_t mid = (lo + hi) >> 1;
-                if (tA[mid] <= tB[q - 1 - mid])
-                    lo = mid + 1;
-                else
-                    hi = mid;
+    for (int64_t wb = r0g + ((int64_t)blockIdx.x * 4 + wv) * kPerWave; wb < r1g;
+         wb += (int64_t)gridDim.x * 4 * kPerWave) {
+        const int64_t r0 = wb + (int64_t)lane * kMergeK;
+        if (r0 < r1g) {
+            const int64_t r1 = r0 + kMergeK < r1g ? r0 + kMergeK : r1g;
+            // the pair holding row r0, and the merge state at its position
+            const int64_t pcf = last_le(a.offsets, a.n + 1, r0);
+            const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
+            PairAt p;
+            pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span), span,
+                      p);
+            int64_t q = r0 - p.sA;
+            int64_t i, j;
+            {
+                int64_t lo = q - p.nB > 0 ? q - p.nB : 0, hi = q < p.nA ? q : p.nA;
+                const T *tA = tin + p.sA, *tB = tin + p.sB;
+                while (lo < hi) {  // A's share of the first q merged positions
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (tA[mid] <= tB[q - 1 - mid])
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                i = lo;
+                j = q - lo;
             }
-            i = lo;
-            j = q - lo;
-        }
-        for (int64_t r = r0; r < r1; ++r) {
-            if (q == p.nA + p.nB) {  // crossed into the next pair (or group)
-                int64_t nb = p.b, ni = p.iE;
-                if (ni == a.groups[nb + 1])
-                    ++nb;
-                pair_from(a, nb, ni, span, p);
-                q = i = j = 0;
-            }
-            const T *tA = tin + p.sA, *vA = vin + p.sA, *tB = tin + p.sB, *vB = vin + p.sB;
-            if (p.nB == 0) {  // unpaired: moves up unchanged
-                tout[r] = tA[q];
-                vout[r] = vA[q];
+            for (int64_t r = r0; r < r1; ++r) {
+                if (q == p.nA + p.nB) {  // crossed into the next pair (or group)
+                    int64_t nb = p.b, ni = p.iE;
+                    if (ni == a.groups[nb + 1])
+                        ++nb;
+                    pair_from(a, nb, ni, span, p);
+                    q = i = j = 0;
+                }
+                const T *tA = tin + p.sA, *vA = vin + p.sA, *tB = tin + p.sB, *vB = vin + p.sB;
+                T x, val;
+                if (p.nB == 0) {  // unpaired: moves up unchanged
+                    x = tA[q];
+                    val = vA[q];
+                } else {
+                    T fx, gx;
+                    if (i < p.nA && (j >= p.nB || tA[i] <= tB[j])) {
+                        x = tA[i];
+                        fx = vA[i];
+                        ++i;
+                        gx = (j < p.nB && tB[j] == x) ? vB[j] : vB[j > 0 ? j - 1 : 0];
+                    } else {
+                        x = tB[j];
+                        gx = vB[j];
+                        ++j;
+                        fx = (i < p.nA && tA[i] == x) ? vA[i] : vA[i > 0 ? i - 1 : 0];
+                    }
+                    val = red_op<T, OP>(fx, gx);
+                }
+#if PCF_RED_STAGE
+                st_t[wv][r - wb] = x;
+                st_v[wv][r - wb] = val;
+#else
+                tout[r] = x;
+                vout[r] = val;
+#endif
                 ++q;
-                continue;
             }
-            T x, fx, gx;
-            if (i < p.nA && (j >= p.nB || tA[i] <= tB[j])) {
-                x = tA[i];
-                fx = vA[i];
-                ++i;
-                gx = (j < p.nB && tB[j] == x) ? vB[j] : vB[j > 0 ? j - 1 : 0];
-            } else {
-                x = tB[j];
-                gx = vB[j];
-                ++j;
-                fx = (i < p.nA && tA[i] == x) ? vA[i] : vA[i > 0 ? i - 1 : 0];
-            }
-            tout[r] = x;
-            vout[r] = red_op<T, OP>(fx, gx);
-            ++q;
         }
+#if PCF_RED_STAGE
+        wave_sync_lds();
+        const int64_t cnt = r1g - wb < kPerWave ? r1g - wb : kPerWave;
+        for (int64_t k = lane; k < cnt; k += 64) {
+            tout[wb + k] = st_t[wv][k];
+            vout[wb + k] = st_v[wv][k];
+        }
+        wave_sync_lds();
+#endif
     }
 }
 
@@ -275,6 +316,7 @@ hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t row
     if (rows <= 0)
         return hipSuccess;
     const dim3 g((unsigned)grid_for((rows + kMergeK - 1) / kMergeK, 256, 16384)), blk(256);
+    static_assert(kMergeK >= 1 && kMergeK <= 32, "positions per lane");
     const int o = op == RO_MAX ? RO_MAX : (op == RO_MIN ? RO_MIN : RO_SUM);
     if (f64) {
         if (o == RO_MAX)

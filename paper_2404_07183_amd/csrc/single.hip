@@ -20,7 +20,8 @@ namespace pcf {
 
 // h of the single-PCF kinds: SK_VALUE h(v) = v; SK_ABS |v|; SK_SQR v^2;
 // SK_POW |v|^p.
-enum { SK_VALUE = 0, SK_ABS = 1, SK_SQR = 2, SK_POW = 3 };
+// SK_SUP: sup |v| over the segments (the L_inf norm), not an integral.
+enum { SK_VALUE = 0, SK_ABS = 1, SK_SQR = 2, SK_POW = 3, SK_SUP = 4 };
 
 template <int SK>
 __device__ __forceinline__ double h_single(double v, double p)
@@ -44,6 +45,16 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
+__device__ __forceinline__ double wave_max(double x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double y = __shfl_xor(x, o, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
 template <typename T, int SK>
 __global__ void single_functional(SingleArgs a)
 {
@@ -63,14 +74,22 @@ __global__ void single_functional(SingleArgs a)
             const double l = tk > a.a ? tk : a.a;
             const double r = tn < a.b ? tn : a.b;
             if (r > l) {
-                const double hv = h_single<SK>((double)v[k], a.p);
-                if (r == INFINITY)
-                    tail = hv > 0.0 ? 1 : (hv < 0.0 ? -1 : 0);
-                else
-                    acc += (r - l) * hv;
+                if constexpr (SK == SK_SUP) {
+                    const double av = fabs((double)v[k]);
+                    acc = av > acc ? av : acc;
+                } else {
+                    const double hv = h_single<SK>((double)v[k], a.p);
+                    if (r == INFINITY)
+                        tail = hv > 0.0 ? 1 : (hv < 0.0 ? -1 : 0);
+                    else
+                        acc += (r - l) * hv;
+                }
             }
         }
-        acc = wave_sum(acc);
+        if constexpr (SK == SK_SUP)
+            acc = wave_max(acc);
+        else
+            acc = wave_sum(acc);
         // the tail is set on one lane at most (the last piece)
         int tl = tail;
 #pragma unroll
@@ -107,6 +126,7 @@ hipError_t launch_single(bool f64, int sk, const SingleArgs &a, hipStream_t s)
         case SK_VALUE: return launch_single_t<double, SK_VALUE>(a, s);
         case SK_ABS: return launch_single_t<double, SK_ABS>(a, s);
         case SK_SQR: return launch_single_t<double, SK_SQR>(a, s);
+        case SK_SUP: return launch_single_t<double, SK_SUP>(a, s);
         default: return launch_single_t<double, SK_POW>(a, s);
         }
     }
@@ -114,6 +134,7 @@ hipError_t launch_single(bool f64, int sk, const SingleArgs &a, hipStream_t s)
     case SK_VALUE: return launch_single_t<float, SK_VALUE>(a, s);
     case SK_ABS: return launch_single_t<float, SK_ABS>(a, s);
     case SK_SQR: return launch_single_t<float, SK_SQR>(a, s);
+    case SK_SUP: return launch_single_t<float, SK_SUP>(a, s);
     default: return launch_single_t<float, SK_POW>(a, s);
     }
 }

@@ -1,5 +1,5 @@
-"""GPU parity of the single-PCF functionals (Section 3.2: integrals and L_p
-norms over [a, b)) against the oracle's segment iteration.
+"""GPU parity of the single-PCF functionals (Section 3.2: integrals, L_p
+norms and the sup norm over [a, b)) against the oracle's segment iteration.
 
 Bars: FP64 |gpu - oracle| <= 1e-12 * scale (scale = sum |h| * width, its
 p-th root for a norm), FP32 against the oracle on the rounded inputs at
@@ -24,6 +24,7 @@ CASES = [  # name, api call, oracle kind, p
     ("norm2", lambda X, a, b: api.norms(X, 2.0, a, b), oracle.S_NORM, 2.0),
     ("norm2pow", lambda X, a, b: api.norms(X, 2.0, a, b, power=True), oracle.S_NORM_POW, 2.0),
     ("norm3.5", lambda X, a, b: api.norms(X, 3.5, a, b), oracle.S_NORM, 3.5),
+    ("norminf", lambda X, a, b: api.norms(X, INF, a, b), oracle.S_NORM_INF, 0.0),
 ]
 BOUNDS = [(0.0, INF), (0.0, 7.5), (3.25, 40.0), (12.0, INF), (500.0, INF)]
 
