@@ -50,6 +50,22 @@ TileShape shape_of(uint32_t flags)
 
 constexpr int HK_ABS = kAbs, HK_SQR = kSqr, HK_PROD = kProd, HK_POW = kPow;
 
+// The forward's h for an L_p kind: exact products for p = 1 and 2, squaring
+// for other integer p and squaring plus one square root for p = k + 1/2 (up
+// to p = 64), pow otherwise.
+int lp_hkind(double p)
+{
+    if (p == 1.0)
+        return HK_ABS;
+    if (p == 2.0)
+        return HK_SQR;
+    if (p <= 64.0 && floor(p) == p)
+        return kPowInt;
+    if (p <= 64.0 && floor(2.0 * p) == 2.0 * p)
+        return kPowHalf;
+    return HK_POW;
+}
+
 int device_cus()
 {
     int dev = 0;
@@ -262,7 +278,7 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
         hk = HK_PROD;
         a.root = 0;
     } else {
-        hk = (p == 1.0) ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW);
+        hk = lp_hkind(p);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
     hipError_t e = launch_forward(X->dtype == PCF_F64, hk, a,
@@ -591,7 +607,7 @@ pcf_status pcf_pairwise_batched(int32_t B, const int64_t *set_offsets_host,
         hk = HK_PROD;
         a.root = 0;
     } else {
-        hk = (p == 1.0) ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW);
+        hk = lp_hkind(p);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
     hipError_t e = launch_forward(all->dtype == PCF_F64, hk, a,
@@ -834,7 +850,7 @@ pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p
         hk = HK_PROD;
         a.root = 0;
     } else {
-        hk = (p == 1.0) ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW);
+        hk = lp_hkind(p);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
     e = launch_forward(X->dtype == PCF_F64, hk, a, tile_grid(&plan, false), s);

@@ -480,7 +480,8 @@ static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
 }
 
 // The (h, root) combinations the entry points use: |a-b| and ab without a
-// root, (a-b)^2 with or without sqrt, |a-b|^p with or without the p-th root.
+// root, (a-b)^2 with or without sqrt, |a-b|^p with or without the p-th root
+// (integer p: squaring; p = k + 1/2: squaring and one sqrt; else pow).
 template <typename T>
 static hipError_t launch_fwd_dtype(int hk, const FwdArgs &a, int grid,
                                    hipStream_t s)
@@ -491,6 +492,12 @@ static hipError_t launch_fwd_dtype(int hk, const FwdArgs &a, int grid,
     case kSqr:
         return a.root == kRootSqrt ? launch_fwd_t<T, kSqr, kRootSqrt>(a, grid, s)
                                    : launch_fwd_t<T, kSqr, kRootNone>(a, grid, s);
+    case kPowHalf:
+        return a.root == kRootPow ? launch_fwd_t<T, kPowHalf, kRootPow>(a, grid, s)
+                                  : launch_fwd_t<T, kPowHalf, kRootNone>(a, grid, s);
+    case kPowInt:
+        return a.root == kRootPow ? launch_fwd_t<T, kPowInt, kRootPow>(a, grid, s)
+                                  : launch_fwd_t<T, kPowInt, kRootNone>(a, grid, s);
     default:
         return a.root == kRootPow ? launch_fwd_t<T, kPow, kRootPow>(a, grid, s)
                                   : launch_fwd_t<T, kPow, kRootNone>(a, grid, s);

@@ -10,7 +10,9 @@
 namespace pcf {
 
 // h codes of the combination integral (Section 2.2 of the paper).
-enum HKind : int { kAbs = 0, kSqr = 1, kProd = 2, kPow = 3 };
+// kPowInt: |a-b|^p for an integer p, by squaring; kPowHalf: p = k + 1/2, by
+// squaring and one square root; kPow: any other p, by pow.
+enum HKind : int { kAbs = 0, kSqr = 1, kProd = 2, kPow = 3, kPowHalf = 4, kPowInt = 5 };
 // r codes of the combination integral.
 enum Root : int { kRootNone = 0, kRootSqrt = 1, kRootPow = 2 };
 

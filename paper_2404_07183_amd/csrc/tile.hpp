@@ -24,6 +24,28 @@ template <typename T> __device__ __forceinline__ T sentinel();
 template <> __device__ __forceinline__ float sentinel<float>() { return FLT_MAX; }
 template <> __device__ __forceinline__ double sentinel<double>() { return DBL_MAX; }
 
+// x^k for a launch-uniform integer k >= 1, by squaring.
+template <typename T>
+__device__ __forceinline__ T ipow(T x, int k)
+{
+    T r = (k & 1) ? x : T(1);
+    for (k >>= 1; k > 0; k >>= 1) {
+        x *= x;
+        if (k & 1)
+            r *= x;
+    }
+    return r;
+}
+
+// x^p for p = k + 1/2 (k >= 0, launch-uniform): x^k by squaring, times
+// sqrt(x).
+template <typename T>
+__device__ __forceinline__ T pow_half(T x, T p)
+{
+    const int k = (int)p;
+    return k > 0 ? ipow(x, k) * sqrt(x) : sqrt(x);
+}
+
 template <typename T, int HK>
 __device__ __forceinline__ T hval(T a, T b, T p)
 {
@@ -34,6 +56,10 @@ __device__ __forceinline__ T hval(T a, T b, T p)
         return d * d;
     } else if constexpr (HK == kProd) {
         return a * b;
+    } else if constexpr (HK == kPowHalf) {
+        return pow_half(fabs(a - b), p);
+    } else if constexpr (HK == kPowInt) {
+        return ipow(fabs(a - b), (int)p);
     } else {
         return pow(fabs(a - b), p);
     }

@@ -26,7 +26,10 @@ KINDS = {  # name -> (api call, oracle kind, p)
     "l2": (lambda X, **k: api.pdist(X, 2.0, **k), oracle.LP, 2.0),
     "l2sq": (lambda X, **k: api.pdist(X, 2.0, power=True, **k), oracle.LP_POW, 2.0),
     "gram": (lambda X, **k: api.gram(X, **k), oracle.GRAM, 0.0),
-    "l3.5": (lambda X, **k: api.pdist(X, 3.5, **k), oracle.LP, 3.5),
+    "l3.5": (lambda X, **k: api.pdist(X, 3.5, **k), oracle.LP, 3.5),  # products and sqrt
+    "l3pow": (lambda X, **k: api.pdist(X, 3.0, power=True, **k), oracle.LP_POW, 3.0),
+    "l1.5": (lambda X, **k: api.pdist(X, 1.5, **k), oracle.LP, 1.5),
+    "l2.7": (lambda X, **k: api.pdist(X, 2.7, **k), oracle.LP, 2.7),  # pow
 }
 
 
@@ -68,7 +71,7 @@ def test_userguide_example_exact():
         assert np.array_equal(api.gram(X32).cpu().numpy(), np.array(g["gram"], dt))
 
 
-@pytest.mark.parametrize("name", ["l1", "l2", "l2sq", "gram", "l3.5"])
+@pytest.mark.parametrize("name", ["l1", "l2", "l2sq", "gram", "l3.5", "l3pow", "l1.5", "l2.7"])
 def test_small_plain_fp64(name):
     # the small plain configuration: N = 200, counts U{10..100}
     o, t, v = workloads.config_plain_small()
@@ -109,7 +112,7 @@ def _dyadic_set(rng, N, nmax, grid=4, tmax=64):
     return o, np.concatenate([a for a, _ in pcfs]), np.concatenate([b for _, b in pcfs])
 
 
-@pytest.mark.parametrize("name", ["l1", "l2sq", "gram"])
+@pytest.mark.parametrize("name", ["l1", "l2sq", "gram", "l3pow"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_dyadic_bitwise(name, dtype):
     # many equal times across PCFs (ties) and repeated values; all arithmetic
@@ -123,7 +126,7 @@ def test_dyadic_bitwise(name, dtype):
     assert np.array_equal(M, R)
 
 
-@pytest.mark.parametrize("name", ["l1", "l2", "gram"])
+@pytest.mark.parametrize("name", ["l1", "l2", "gram", "l3.5", "l2.7"])
 def test_fp32_against_rounded_inputs(name):
     o, t, v = workloads.uniform_counts(400, 50, 500, seed=21, dtype=np.float32)
     _check_full(name, o, t, v, 1e-5)
