@@ -51,9 +51,10 @@ TileShape shape_of(uint32_t flags)
 constexpr int HK_ABS = kAbs, HK_SQR = kSqr, HK_PROD = kProd, HK_POW = kPow;
 
 // The forward's h for an L_p kind: exact products for p = 1 and 2, squaring
-// for other integer p and squaring plus one square root for p = k + 1/2 (up
-// to p = 64), pow otherwise.
-int lp_hkind(double p)
+// for other integer p (up to 64); in FP64 squaring plus one square root for
+// p = k + 1/2 and the pow series otherwise; in FP32 the hardware base-2 log
+// and exp for every non-integer p (faster there than the square root).
+int lp_hkind(double p, bool f64)
 {
     if (p == 1.0)
         return HK_ABS;
@@ -61,6 +62,8 @@ int lp_hkind(double p)
         return HK_SQR;
     if (p <= 64.0 && floor(p) == p)
         return kPowInt;
+    if (!f64)
+        return HK_POW;
     if (p <= 64.0 && floor(2.0 * p) == 2.0 * p)
         return kPowHalf;
     return HK_POW;
@@ -278,7 +281,7 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
         hk = HK_PROD;
         a.root = 0;
     } else {
-        hk = lp_hkind(p);
+        hk = lp_hkind(p, X->dtype == PCF_F64);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
     hipError_t e = launch_forward(X->dtype == PCF_F64, hk, a,
@@ -607,7 +610,7 @@ pcf_status pcf_pairwise_batched(int32_t B, const int64_t *set_offsets_host,
         hk = HK_PROD;
         a.root = 0;
     } else {
-        hk = lp_hkind(p);
+        hk = lp_hkind(p, all->dtype == PCF_F64);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
     hipError_t e = launch_forward(all->dtype == PCF_F64, hk, a,
@@ -850,7 +853,7 @@ pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p
         hk = HK_PROD;
         a.root = 0;
     } else {
-        hk = lp_hkind(p);
+        hk = lp_hkind(p, X->dtype == PCF_F64);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
     e = launch_forward(X->dtype == PCF_F64, hk, a, tile_grid(&plan, false), s);

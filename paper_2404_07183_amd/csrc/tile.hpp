@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "launch.hpp"
+#include "pow64.hpp"
 
 namespace pcf {
 
@@ -46,6 +47,15 @@ __device__ __forceinline__ T pow_half(T x, T p)
     return k > 0 ? ipow(x, k) * sqrt(x) : sqrt(x);
 }
 
+// x^p = 2^(p log2 x) for any other p: FP32 by the hardware base-2 log and
+// exp (v_log_f32, v_exp_f32; relative error a few ulps times |p log2 x|,
+// x = 0 gives 0), FP64 by the series of pow64.hpp.
+__device__ __forceinline__ float pow_any(float x, float p)
+{
+    return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x));
+}
+__device__ __forceinline__ double pow_any(double x, double p) { return pow_series(x, p); }
+
 template <typename T, int HK>
 __device__ __forceinline__ T hval(T a, T b, T p)
 {
@@ -61,7 +71,7 @@ __device__ __forceinline__ T hval(T a, T b, T p)
     } else if constexpr (HK == kPowInt) {
         return ipow(fabs(a - b), (int)p);
     } else {
-        return pow(fabs(a - b), p);
+        return pow_any(fabs(a - b), p);
     }
 }
 
