@@ -20,8 +20,9 @@ from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
                    PCF_VALIDATE, PCF_WEIGHT_EXP, PCF_WEIGHT_POW, PCF_REDUCE_SUM,
                    PCF_REDUCE_MEAN, PCF_REDUCE_MAX, PCF_REDUCE_MIN, PCF_REDUCE_STD, check)
 
-__all__ = ["PcfSet", "Workspace", "pdist", "gram", "pairwise_backward",
+__all__ = ["PcfSet", "Workspace", "pdist", "gram", "cdist", "cross_gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
+           "integrals", "norms", "restrict", "warp", "reduce",
            "autotune", "TILE_SHAPES", "PCF_LP", "PCF_LP_POW", "PCF_GRAM"]
 
 
