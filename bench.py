@@ -540,11 +540,24 @@ def main():
                          "for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and forward+adjoint measurements")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated extra lines to run alone, without the headline "
+                         "(batched, fwd_bwd, cross, single, reduce): for profiling them")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        runs = {"batched": lambda k, w: run_batched(k, w), "fwd_bwd": lambda k, w: run_grad(k, w),
+                "cross": lambda k, w: run_cross(k, w), "single": run_single,
+                "reduce": run_reduce}
+        names = args.only.split(",")
+        bad = [n for n in names if n not in runs]
+        if bad:
+            ap.error("unknown line(s) for --only: %s" % ", ".join(bad))
+        print(json.dumps({n: runs[n](args.steps, args.warmup) for n in names}), flush=True)
+        return
     if args.calibration_copy:
         import torch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
