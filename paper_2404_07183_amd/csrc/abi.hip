@@ -387,7 +387,8 @@ struct RedPlan {
     int L = 0;
     int64_t n = 0, P = 0, C = 0;  // PCFs, rows, chunks
     std::vector<int64_t> meta;    // groups (B+1), chunk rows (C), chunk groups (C)
-    size_t off_ccnt = 0, off_coff = 0, off_buf[4] = {0, 0, 0, 0}, off_q = 0, bytes = 0;
+    size_t off_ccnt = 0, off_coff = 0, off_buf[4] = {0, 0, 0, 0}, off_q = 0, off_map = 0;
+    size_t bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -405,6 +406,8 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
     const int64_t n = X->n;
     if (B == 0 ? n != 0 : (groups[0] != 0 || groups[B] != n))
         return fail(PCF_EINVAL, "the groups must cover the set's PCFs 0 .. n-1");
+    if (n >= ((int64_t)1 << 31))
+        return fail(PCF_EUNSUPPORTED, "reductions take fewer than 2^31 PCFs");
     int64_t mmax = 0;
     for (int32_t b = 0; b < B; ++b) {
         const int64_t m = groups[b + 1] - groups[b];
@@ -455,6 +458,8 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
     }
     rp.off_q = off;
     off += align256((size_t)(rp.P > 0 ? rp.P : 1) * esz);
+    rp.off_map = off;
+    off += align256((size_t)(rp.P > 0 ? rp.P : 1) * sizeof(int32_t));
     rp.bytes = off;
     return PCF_OK;
 }
@@ -1035,10 +1040,14 @@ pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_off
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);  // rp.meta is a local
     const bool f64 = X->dtype == PCF_F64;
+    int32_t *row_pcf = (int32_t *)(w + rp.off_map);
+    if (e == hipSuccess && rp.L > 0)
+        e = launch_red_rowmap(X->offsets, rp.n, row_pcf, s);
     for (int l = 0; l < rp.L && e == hipSuccess; ++l) {
         RedLevelArgs a;
         a.offsets = X->offsets;
         a.groups = meta;
+        a.row_pcf = row_pcf;
         a.n = rp.n;
         a.B = B;
         a.level = l;

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
         if (r0 < r1g) {
             const int64_t r1 = r0 + kMergeK < r1g ? r0 + kMergeK : r1g;
             // the pair holding row r0, and the merge state at its position
-            const int64_t pcf = last_le(a.offsets, a.n + 1, r0);
+            const int64_t pcf = a.row_pcf[r0];
             const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
             PairAt p;
             pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span), span,
@@ -196,6 +196,18 @@ __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
         wave_sync_lds();
 #endif
     }
+}
+
+// row_pcf[r] = the PCF holding row r: one wave per PCF.
+__global__ void red_rowmap(const int64_t *__restrict__ offsets, int64_t n,
+                           int32_t *__restrict__ row_pcf)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves)
+        for (int64_t r = offsets[i] + lane; r < offsets[i + 1]; r += 64)
+            row_pcf[r] = (int32_t)i;
 }
 
 // Sum over i of (f_i(x) - mean(x))^2 at every root breakpoint x, in the
@@ -308,6 +320,15 @@ static int64_t grid_for(int64_t units, int64_t per_block, int64_t cap)
 {
     int64_t g = (units + per_block - 1) / per_block;
     return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
+hipError_t launch_red_rowmap(const int64_t *offsets, int64_t n, int32_t *row_pcf, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(red_rowmap, dim3((unsigned)grid_for(n, 4, 8192)), dim3(256), 0, s,
+                       offsets, n, row_pcf);
+    return hipGetLastError();
 }
 
 hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t rows,

@@ -14,6 +14,7 @@ enum { RO_SUM = 0, RO_MEAN = 1, RO_MAX = 2, RO_MIN = 3, RO_STD = 4 };
 struct RedLevelArgs {
     const int64_t *offsets;  // the set's CSR offsets (device, n+1)
     const int64_t *groups;   // group offsets (device, B+1)
+    const int32_t *row_pcf;  // the PCF of every row (device, P)
     int64_t n;
     int32_t B;
     int level;               // inputs are items of 2^level PCFs
@@ -42,6 +43,7 @@ struct RedEmitArgs {
 };
 hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t rows,
                             hipStream_t s);
+hipError_t launch_red_rowmap(const int64_t *offsets, int64_t n, int32_t *row_pcf, hipStream_t s);
 hipError_t launch_red_std(bool f64, const RedStdArgs &a, hipStream_t s);
 hipError_t launch_red_emit(bool f64, const RedEmitArgs &a, hipStream_t s);
 
