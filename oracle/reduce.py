@@ -14,7 +14,9 @@ reduced by a binary tree: at every level neighbours (2j, 2j+1) are reduced
 and an unpaired last item moves up unchanged. From the sum reduction:
 mean = (1/n) (+) f_i, and the sample standard deviation
 sqrt( (1/(n-1)) (+)_i (f_i - mean)^2 ) (read as 1/(n-1): the printed
-normalisation is garbled). The transformation x -> x/n (or
+normalisation is garbled). A combination of two sets applies ReducePair
+with any combination function h (sum, difference, product, max, min,
+squared difference) to f_i and g_i. The transformation x -> x/n (or
 sqrt(x/(n-1))) is applied to the reduced PCF's values row by row.
 """
 from __future__ import annotations
@@ -98,6 +100,23 @@ def reduce_groups(op, groups, offsets, t, v, dtype=np.float64):
                                    else np.float32(math.sqrt(np.float32(x / dtype(n - 1))))
                                    for x in q_v], dtype=dtype)))
     return out
+
+
+COMBINE = dict(OPS, sub=lambda a, b: a - b, mul=lambda a, b: a * b,
+               sqdiff=lambda a, b: (a - b) * (a - b))
+
+
+def combine_sets(op, xs, ys, dtype=np.float64):
+    """The induced combination h_*(f_i, g_i) of two sets index by index
+    (Section 2.1), each by Algorithm ReducePair; xs and ys are (offsets, t,
+    v) triples with the same number of PCFs."""
+    (xo, xt, xv), (yo, yt, yv) = xs, ys
+    xt, xv = np.asarray(xt, dtype=dtype), np.asarray(xv, dtype=dtype)
+    yt, yv = np.asarray(yt, dtype=dtype), np.asarray(yv, dtype=dtype)
+    h = COMBINE[op]
+    return [reduce_pair((xt[xo[i]:xo[i + 1]], xv[xo[i]:xo[i + 1]]),
+                        (yt[yo[i]:yo[i + 1]], yv[yo[i]:yo[i + 1]]), h, dtype)
+            for i in range(len(xo) - 1)]
 
 
 def evaluate(pcf, x):

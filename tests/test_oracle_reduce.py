@@ -106,3 +106,19 @@ def test_single_pcf_group_and_pairs():
     assert t2.tolist() == [0.0, 2.0, 3.0] and v2.tolist() == [5.0, -1.0, 0.0]
     with pytest.raises(ValueError):
         red.reduce_groups("std", [0, 1], o, t, v)
+
+
+@pytest.mark.parametrize("op", ["sum", "sub", "mul", "max", "min", "sqdiff"])
+def test_combinations_pointwise(op):
+    xs = workloads.uniform_counts(30, 1, 40, seed=93)
+    ys = workloads.uniform_counts(30, 1, 40, seed=94)
+    res = red.combine_sets(op, xs, ys)
+    f = {"sum": np.add, "sub": np.subtract, "mul": np.multiply, "max": np.maximum,
+         "min": np.minimum, "sqdiff": lambda a, b: (a - b) ** 2}[op]
+    for i, pcf in enumerate(res):
+        fi = (xs[1][xs[0][i]:xs[0][i + 1]], xs[2][xs[0][i]:xs[0][i + 1]])
+        gi = (ys[1][ys[0][i]:ys[0][i + 1]], ys[2][ys[0][i]:ys[0][i + 1]])
+        x = np.unique(np.concatenate([fi[0], gi[0]]))
+        x = np.concatenate([x, (x[:-1] + x[1:]) / 2, [x[-1] + 1]])
+        assert np.array_equal(red.evaluate(pcf, x), f(red.evaluate(fi, x), red.evaluate(gi, x)))
+        _check_minimal(pcf)
