@@ -281,6 +281,33 @@ pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_
                       pcf_reduce_op op, const void *ws, size_t ws_bytes,
                       const int64_t *offsets_out, void *t_out, void *v_out, void *stream);
 
+/* Combinations of two sets index by index (Section 2.1: the induced
+ * combination h_*(f, g)(t) = h(f(t), g(t)); Section 4, Algorithm ReducePair):
+ * out_i = h_*(x_i, y_i) for X and Y of one dtype and one PCF count n, with
+ *   PCF_COMBINE_SUM a + b, _SUB a - b, _MUL a b, _MAX, _MIN, _SQDIFF (a - b)^2.
+ * Each result keeps a row at t = 0 and wherever its value changes. Calls as
+ * for the reductions: pcf_combine_workspace_bytes; pcf_combine_rows writes
+ * offsets_out (device, n+1) and offsets_out_host (host, n+1) and
+ * synchronises; pcf_combine (asynchronous) writes t_out and v_out from the
+ * same workspace, passed unchanged with the same X, Y and op. */
+typedef enum {
+    PCF_COMBINE_SUM = 0,
+    PCF_COMBINE_SUB = 1,
+    PCF_COMBINE_MUL = 2,
+    PCF_COMBINE_MAX = 3,
+    PCF_COMBINE_MIN = 4,
+    PCF_COMBINE_SQDIFF = 5
+} pcf_combine_op;
+
+pcf_status pcf_combine_workspace_bytes(const pcf_set *X, const pcf_set *Y, pcf_combine_op op,
+                                       size_t *bytes);
+pcf_status pcf_combine_rows(const pcf_set *X, const pcf_set *Y, pcf_combine_op op, void *ws,
+                            size_t ws_bytes, int64_t *offsets_out, int64_t *offsets_out_host,
+                            void *stream);
+pcf_status pcf_combine(const pcf_set *X, const pcf_set *Y, pcf_combine_op op, const void *ws,
+                       size_t ws_bytes, const int64_t *offsets_out, void *t_out, void *v_out,
+                       void *stream);
+
 /* Many independent full matrices in one persistent launch. `all` is one CSR
  * set holding every problem's PCFs; problem b owns PCFs
  * set_offsets_host[b] .. set_offsets_host[b+1]-1 (HOST array, B+1 entries)

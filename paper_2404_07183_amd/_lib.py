@@ -20,6 +20,8 @@ PCF_RECORDS_PACKED = 16
 PCF_INTEGRAL, PCF_NORM, PCF_NORM_POW, PCF_NORM_INF = 0, 1, 2, 3
 PCF_WEIGHT_EXP, PCF_WEIGHT_POW = 1, 2
 PCF_REDUCE_SUM, PCF_REDUCE_MEAN, PCF_REDUCE_MAX, PCF_REDUCE_MIN, PCF_REDUCE_STD = 0, 1, 2, 3, 4
+(PCF_COMBINE_SUM, PCF_COMBINE_SUB, PCF_COMBINE_MUL, PCF_COMBINE_MAX, PCF_COMBINE_MIN,
+ PCF_COMBINE_SQDIFF) = range(6)
 
 STATUS_NAMES = {0: "PCF_OK", 1: "PCF_EINVAL", 2: "PCF_EDATA", 3: "PCF_EDEVICE",
                 4: "PCF_ENOMEM", 5: "PCF_EUNSUPPORTED"}
@@ -92,6 +94,16 @@ _SIGS = {
                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p]),
+    "pcf_combine_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pcf_set),
+                                                   ctypes.POINTER(pcf_set), ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "pcf_combine_rows": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.POINTER(pcf_set),
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pcf_combine": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.POINTER(pcf_set),
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
     "pcf_warp_rows": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int,
                                      ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p]),
@@ -221,6 +233,23 @@ def pcf_reduce(X, B, groups_ptr, op, ws_ptr, ws_bytes, offsets_out_ptr, t_out_pt
                stream):
     return load().pcf_reduce(ctypes.byref(X), B, groups_ptr, op, ws_ptr, ws_bytes,
                              offsets_out_ptr, t_out_ptr, v_out_ptr, stream)
+
+
+def pcf_combine_workspace_bytes(X, Y, op):
+    out = ctypes.c_size_t(0)
+    check(load().pcf_combine_workspace_bytes(ctypes.byref(X), ctypes.byref(Y), op,
+                                             ctypes.byref(out)))
+    return out.value
+
+
+def pcf_combine_rows(X, Y, op, ws_ptr, ws_bytes, offsets_out_ptr, offsets_out_host_ptr, stream):
+    return load().pcf_combine_rows(ctypes.byref(X), ctypes.byref(Y), op, ws_ptr, ws_bytes,
+                                   offsets_out_ptr, offsets_out_host_ptr, stream)
+
+
+def pcf_combine(X, Y, op, ws_ptr, ws_bytes, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
+    return load().pcf_combine(ctypes.byref(X), ctypes.byref(Y), op, ws_ptr, ws_bytes,
+                              offsets_out_ptr, t_out_ptr, v_out_ptr, stream)
 
 
 def pcf_warp_rows(X, weight, c, offsets_out_ptr, offsets_out_host_ptr, stream):

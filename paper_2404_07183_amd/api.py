@@ -22,7 +22,7 @@ from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
 
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "cdist", "cross_gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
-           "integrals", "norms", "restrict", "warp", "reduce",
+           "integrals", "norms", "restrict", "warp", "reduce", "combine",
            "autotune", "TILE_SHAPES", "PCF_LP", "PCF_LP_POW", "PCF_GRAM"]
 
 
@@ -279,6 +279,34 @@ def reduce(X, op="mean", groups=None, workspace=None, stream=None):
     ws.packed_data = None
     new = object.__new__(PcfSet)
     new.offsets_host, new.offsets, new.n = off_h, off_d, B
+    new.t, new.v = t, v
+    return new
+
+
+_COMBINE_OPS = {"sum": 0, "sub": 1, "mul": 2, "max": 3, "min": 4, "sqdiff": 5}
+
+
+def combine(X, Y, op="sum", workspace=None, stream=None):
+    """The induced combination h_*(x_i, y_i) of two sets index by index
+    (Section 2.1): ``op`` in sum, sub, mul, max, min, sqdiff. Returns a set
+    of n PCFs."""
+    opc = _COMBINE_OPS.get(op, op)
+    Xc, Yc = X.c_struct(), Y.c_struct()
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    ws.ensure(_lib.pcf_combine_workspace_bytes(Xc, Yc, int(opc)))
+    off_h = np.empty(X.n + 1, dtype=np.int64)
+    off_d = torch.empty(X.n + 1, dtype=torch.int64, device=X.t.device)
+    check(_lib.pcf_combine_rows(Xc, Yc, int(opc), ws.ptr, ws.nbytes, off_d.data_ptr(),
+                                off_h.ctypes.data, _stream_handle(stream)))
+    rows = int(off_h[-1])
+    t = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    v = torch.empty(rows, dtype=X.dtype, device=X.t.device)
+    check(_lib.pcf_combine(Xc, Yc, int(opc), ws.ptr, ws.nbytes, off_d.data_ptr(), t.data_ptr(),
+                           v.data_ptr(), _stream_handle(stream)))
+    ws.planned = None
+    ws.packed_data = None
+    new = object.__new__(PcfSet)
+    new.offsets_host, new.offsets, new.n = off_h, off_d, X.n
     new.t, new.v = t, v
     return new
 

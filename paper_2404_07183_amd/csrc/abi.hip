@@ -399,7 +399,7 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
     pcf_status st = check_set(X);
     if (st != PCF_OK)
         return st;
-    if (op < PCF_REDUCE_SUM || op > PCF_REDUCE_STD)
+    if (op < RO_SUM || op > RO_SQDIFF)
         return fail(PCF_EINVAL, "unknown reduction op");
     if (B < 0 || (B > 0 && !groups))
         return fail(PCF_EINVAL, "B < 0 or group_offsets_host is NULL");
@@ -991,6 +991,8 @@ pcf_status pcf_reduce_workspace_bytes(const pcf_set *X, int32_t B,
 {
     if (!bytes)
         return fail(PCF_EINVAL, "bytes is NULL");
+    if (op < PCF_REDUCE_SUM || op > PCF_REDUCE_STD)
+        return fail(PCF_EINVAL, "unknown reduction op");
     RedPlan rp;
     pcf_status st = red_plan(X, B, group_offsets_host, (int)op, nullptr, rp);
     if (st != PCF_OK)
@@ -1017,9 +1019,10 @@ void red_roots(const pcf_set *X, const RedPlan &rp, unsigned char *w, const void
 
 }  // namespace
 
-pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
-                           pcf_reduce_op op, void *ws, size_t ws_bytes, int64_t *offsets_out,
-                           int64_t *offsets_out_host, void *stream)
+static pcf_status reduce_rows_impl(const pcf_set *X, int32_t B,
+                                   const int64_t *group_offsets_host, int op, void *ws,
+                                   size_t ws_bytes, int64_t *offsets_out,
+                                   int64_t *offsets_out_host, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     RedPlan rp;
@@ -1060,7 +1063,7 @@ pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_off
     }
     const void *rt, *rv;
     red_roots(X, rp, w, rt, rv);
-    if (e == hipSuccess && op == PCF_REDUCE_STD) {
+    if (e == hipSuccess && op == RO_STD) {
         RedStdArgs a;
         a.offsets = X->offsets;
         a.groups = meta;
@@ -1124,9 +1127,10 @@ pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_off
     return e == hipSuccess ? PCF_OK : hip_fail(e, "writing the reduced offsets");
 }
 
-pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
-                      pcf_reduce_op op, const void *ws, size_t ws_bytes,
-                      const int64_t *offsets_out, void *t_out, void *v_out, void *stream)
+static pcf_status reduce_fill_impl(const pcf_set *X, int32_t B,
+                                   const int64_t *group_offsets_host, int op, const void *ws,
+                                   size_t ws_bytes, const int64_t *offsets_out, void *t_out,
+                                   void *v_out, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     RedPlan rp;
@@ -1148,7 +1152,7 @@ pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_
     a.groups = meta;
     a.op = (int)op;
     a.rt = rt;
-    a.rv = op == PCF_REDUCE_STD ? (const void *)(w + rp.off_q) : rv;
+    a.rv = op == RO_STD ? (const void *)(w + rp.off_q) : rv;
     a.nchunks = rp.C;
     a.chunk_row = meta + B + 1;
     a.chunk_grp = meta + B + 1 + rp.C;
@@ -1162,6 +1166,175 @@ pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_
     if (e != hipSuccess)
         return hip_fail(e, "reduction launch");
     return PCF_OK;
+}
+
+pcf_status pcf_reduce_rows(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
+                           pcf_reduce_op op, void *ws, size_t ws_bytes, int64_t *offsets_out,
+                           int64_t *offsets_out_host, void *stream)
+{
+    if (op < PCF_REDUCE_SUM || op > PCF_REDUCE_STD)
+        return fail(PCF_EINVAL, "unknown reduction op");
+    return reduce_rows_impl(X, B, group_offsets_host, (int)op, ws, ws_bytes, offsets_out,
+                            offsets_out_host, stream);
+}
+
+pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_host,
+                      pcf_reduce_op op, const void *ws, size_t ws_bytes,
+                      const int64_t *offsets_out, void *t_out, void *v_out, void *stream)
+{
+    if (op < PCF_REDUCE_SUM || op > PCF_REDUCE_STD)
+        return fail(PCF_EINVAL, "unknown reduction op");
+    return reduce_fill_impl(X, B, group_offsets_host, (int)op, ws, ws_bytes, offsets_out,
+                            t_out, v_out, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// A combination of X and Y as a reduction of Z = (X_0, Y_0, X_1, Y_1, ...)
+// in groups of two; Z's offsets and rows sit at the head of the workspace.
+struct CombPlan {
+    int64_t n = 0;
+    std::vector<int64_t> zoff, groups;
+    size_t off_zt = 0, off_zv = 0, off_red = 0, bytes = 0;
+    int ro = RO_SUM;
+    pcf_set Z{};
+    RedPlan rp;
+};
+
+int combine_ro(int op)
+{
+    switch (op) {
+    case PCF_COMBINE_SUM: return RO_SUM;
+    case PCF_COMBINE_SUB: return RO_SUB;
+    case PCF_COMBINE_MUL: return RO_MUL;
+    case PCF_COMBINE_MAX: return RO_MAX;
+    case PCF_COMBINE_MIN: return RO_MIN;
+    case PCF_COMBINE_SQDIFF: return RO_SQDIFF;
+    default: return -1;
+    }
+}
+
+pcf_status comb_plan(const pcf_set *X, const pcf_set *Y, int op, unsigned char *ws,
+                     hipStream_t s, CombPlan &cp)
+{
+    pcf_status st = check_pair(X, Y);
+    if (st != PCF_OK)
+        return st;
+    if (X->n != Y->n)
+        return fail(PCF_EINVAL, "X and Y must hold the same number of PCFs");
+    cp.ro = combine_ro(op);
+    if (cp.ro < 0)
+        return fail(PCF_EINVAL, "unknown combination op");
+    const int64_t n = X->n;
+    if (n >= ((int64_t)1 << 30))
+        return fail(PCF_EUNSUPPORTED, "combinations take fewer than 2^30 PCFs");
+    std::vector<int64_t> xb, yb;
+    const int64_t *xo = nullptr, *yo = nullptr;
+    if (n > 0) {
+        st = host_offsets(X, xb, xo, s);
+        if (st == PCF_OK)
+            st = host_offsets(Y, yb, yo, s);
+        if (st != PCF_OK)
+            return st;
+    }
+    cp.n = n;
+    cp.zoff.assign((size_t)(2 * n + 1), 0);
+    cp.groups.assign((size_t)(n + 1), 0);
+    for (int64_t i = 0; i < n; ++i) {
+        cp.zoff[(size_t)(2 * i + 1)] = cp.zoff[(size_t)(2 * i)] + (xo[i + 1] - xo[i]);
+        cp.zoff[(size_t)(2 * i + 2)] = cp.zoff[(size_t)(2 * i + 1)] + (yo[i + 1] - yo[i]);
+        cp.groups[(size_t)(i + 1)] = 2 * (i + 1);
+    }
+    const int64_t P = cp.zoff.back();
+    const size_t esz = X->dtype == PCF_F64 ? 8 : 4;
+    size_t off = align256(cp.zoff.size() * sizeof(int64_t));
+    cp.off_zt = off;
+    off += align256((size_t)(P > 0 ? P : 1) * esz);
+    cp.off_zv = off;
+    off += align256((size_t)(P > 0 ? P : 1) * esz);
+    cp.off_red = off;
+    cp.Z.n = 2 * n;
+    // without a workspace (a size query) X's pointers stand in; the plan
+    // reads only Z's host offsets
+    cp.Z.offsets = ws ? (const int64_t *)ws : X->offsets;
+    cp.Z.t = ws ? (const void *)(ws + cp.off_zt) : X->t;
+    cp.Z.v = ws ? (const void *)(ws + cp.off_zv) : X->v;
+    cp.Z.dtype = X->dtype;
+    cp.Z.offsets_host = cp.zoff.data();
+    if (n > 0) {
+        st = red_plan(&cp.Z, (int32_t)n, cp.groups.data(), cp.ro, s, cp.rp);
+        if (st != PCF_OK)
+            return st;
+    }
+    cp.bytes = off + cp.rp.bytes;
+    return PCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pcf_status pcf_combine_workspace_bytes(const pcf_set *X, const pcf_set *Y, pcf_combine_op op,
+                                       size_t *bytes)
+{
+    if (!bytes)
+        return fail(PCF_EINVAL, "bytes is NULL");
+    CombPlan cp;
+    pcf_status st = comb_plan(X, Y, (int)op, nullptr, nullptr, cp);
+    if (st != PCF_OK)
+        return st;
+    *bytes = cp.bytes;
+    return PCF_OK;
+}
+
+pcf_status pcf_combine_rows(const pcf_set *X, const pcf_set *Y, pcf_combine_op op, void *ws,
+                            size_t ws_bytes, int64_t *offsets_out, int64_t *offsets_out_host,
+                            void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *w = (unsigned char *)ws;
+    CombPlan cp;
+    pcf_status st = comb_plan(X, Y, (int)op, w, s, cp);
+    if (st != PCF_OK)
+        return st;
+    if (!offsets_out || !offsets_out_host)
+        return fail(PCF_EINVAL, "offsets_out or offsets_out_host is NULL");
+    if (cp.n == 0)
+        return counts_to_offsets(0, offsets_out, offsets_out_host, s, "combined");
+    if (!w || ws_bytes < cp.bytes)
+        return fail(PCF_ENOMEM, "workspace too small: need " + std::to_string(cp.bytes) +
+                                    " bytes, got " + std::to_string(ws_bytes));
+    hipError_t e = hipMemcpyAsync(w, cp.zoff.data(), cp.zoff.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);  // cp.zoff is a local
+    if (e == hipSuccess)
+        e = launch_red_interleave(X->dtype == PCF_F64, cp.n, X->offsets, X->t, X->v,
+                                  Y->offsets, Y->t, Y->v, (const int64_t *)w, w + cp.off_zt,
+                                  w + cp.off_zv, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "combination launch");
+    return reduce_rows_impl(&cp.Z, (int32_t)cp.n, cp.groups.data(), cp.ro, w + cp.off_red,
+                            ws_bytes - cp.off_red, offsets_out, offsets_out_host, stream);
+}
+
+pcf_status pcf_combine(const pcf_set *X, const pcf_set *Y, pcf_combine_op op, const void *ws,
+                       size_t ws_bytes, const int64_t *offsets_out, void *t_out, void *v_out,
+                       void *stream)
+{
+    unsigned char *w = (unsigned char *)ws;
+    CombPlan cp;
+    pcf_status st = comb_plan(X, Y, (int)op, w, (hipStream_t)stream, cp);
+    if (st != PCF_OK)
+        return st;
+    if (cp.n == 0)
+        return PCF_OK;
+    if (!w || ws_bytes < cp.bytes)
+        return fail(PCF_ENOMEM, "workspace too small");
+    return reduce_fill_impl(&cp.Z, (int32_t)cp.n, cp.groups.data(), cp.ro, w + cp.off_red,
+                            ws_bytes - cp.off_red, offsets_out, t_out, v_out, stream);
 }
 
 }  // extern "C"

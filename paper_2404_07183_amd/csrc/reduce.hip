@@ -54,6 +54,12 @@ __device__ __forceinline__ T red_op(T a, T b)
         return a >= b ? a : b;
     else if constexpr (OP == RO_MIN)
         return a <= b ? a : b;
+    else if constexpr (OP == RO_SUB)
+        return a - b;
+    else if constexpr (OP == RO_MUL)
+        return a * b;
+    else if constexpr (OP == RO_SQDIFF)
+        return (a - b) * (a - b);
     else
         return a + b;
 }
@@ -331,6 +337,19 @@ hipError_t launch_red_rowmap(const int64_t *offsets, int64_t n, int32_t *row_pcf
     return hipGetLastError();
 }
 
+template <typename T>
+static void launch_red_level_t(int op, const RedLevelArgs &a, dim3 g, dim3 blk, hipStream_t s)
+{
+    switch (op) {
+    case RO_MAX: hipLaunchKernelGGL((red_level<T, RO_MAX>), g, blk, 0, s, a); break;
+    case RO_MIN: hipLaunchKernelGGL((red_level<T, RO_MIN>), g, blk, 0, s, a); break;
+    case RO_SUB: hipLaunchKernelGGL((red_level<T, RO_SUB>), g, blk, 0, s, a); break;
+    case RO_MUL: hipLaunchKernelGGL((red_level<T, RO_MUL>), g, blk, 0, s, a); break;
+    case RO_SQDIFF: hipLaunchKernelGGL((red_level<T, RO_SQDIFF>), g, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((red_level<T, RO_SUM>), g, blk, 0, s, a); break;  // sum, mean, std
+    }
+}
+
 hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t rows,
                             hipStream_t s)
 {
@@ -338,22 +357,55 @@ hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t row
         return hipSuccess;
     const dim3 g((unsigned)grid_for((rows + kMergeK - 1) / kMergeK, 256, 16384)), blk(256);
     static_assert(kMergeK >= 1 && kMergeK <= 32, "positions per lane");
-    const int o = op == RO_MAX ? RO_MAX : (op == RO_MIN ? RO_MIN : RO_SUM);
-    if (f64) {
-        if (o == RO_MAX)
-            hipLaunchKernelGGL((red_level<double, RO_MAX>), g, blk, 0, s, a);
-        else if (o == RO_MIN)
-            hipLaunchKernelGGL((red_level<double, RO_MIN>), g, blk, 0, s, a);
-        else
-            hipLaunchKernelGGL((red_level<double, RO_SUM>), g, blk, 0, s, a);
-    } else {
-        if (o == RO_MAX)
-            hipLaunchKernelGGL((red_level<float, RO_MAX>), g, blk, 0, s, a);
-        else if (o == RO_MIN)
-            hipLaunchKernelGGL((red_level<float, RO_MIN>), g, blk, 0, s, a);
-        else
-            hipLaunchKernelGGL((red_level<float, RO_SUM>), g, blk, 0, s, a);
+    if (f64)
+        launch_red_level_t<double>(op, a, g, blk, s);
+    else
+        launch_red_level_t<float>(op, a, g, blk, s);
+    return hipGetLastError();
+}
+
+// The rows of X's PCF i and then Y's PCF i at Z's PCFs 2i and 2i+1: one
+// wave per i.
+template <typename T>
+__global__ void red_interleave(int64_t n, const int64_t *__restrict__ xo,
+                               const T *__restrict__ xt, const T *__restrict__ xv,
+                               const int64_t *__restrict__ yo, const T *__restrict__ yt,
+                               const T *__restrict__ yv, const int64_t *__restrict__ zo,
+                               T *__restrict__ zt, T *__restrict__ zv)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves) {
+        const int64_t x0 = xo[i], nx = xo[i + 1] - x0, y0 = yo[i], ny = yo[i + 1] - y0;
+        const int64_t z0 = zo[2 * i], z1 = zo[2 * i + 1];
+        for (int64_t k = lane; k < nx; k += 64) {
+            zt[z0 + k] = xt[x0 + k];
+            zv[z0 + k] = xv[x0 + k];
+        }
+        for (int64_t k = lane; k < ny; k += 64) {
+            zt[z1 + k] = yt[y0 + k];
+            zv[z1 + k] = yv[y0 + k];
+        }
     }
+}
+
+hipError_t launch_red_interleave(bool f64, int64_t n, const int64_t *xo, const void *xt,
+                                 const void *xv, const int64_t *yo, const void *yt,
+                                 const void *yv, const int64_t *zo, void *zt, void *zv,
+                                 hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const dim3 g((unsigned)grid_for(n, 4, 8192)), blk(256);
+    if (f64)
+        hipLaunchKernelGGL(red_interleave<double>, g, blk, 0, s, n, xo, (const double *)xt,
+                           (const double *)xv, yo, (const double *)yt, (const double *)yv, zo,
+                           (double *)zt, (double *)zv);
+    else
+        hipLaunchKernelGGL(red_interleave<float>, g, blk, 0, s, n, xo, (const float *)xt,
+                           (const float *)xv, yo, (const float *)yt, (const float *)yv, zo,
+                           (float *)zt, (float *)zv);
     return hipGetLastError();
 }
 

@@ -10,7 +10,9 @@
 namespace pcf {
 
 // Reductions of groups of PCFs (reduce.hip). Ops as in pcf_reduce_op.
-enum { RO_SUM = 0, RO_MEAN = 1, RO_MAX = 2, RO_MIN = 3, RO_STD = 4 };
+// RO_SUB, RO_MUL and RO_SQDIFF (a - b, ab, (a - b)^2) are combinations of two
+// PCFs only: not associative, so never reduced over more than a pair.
+enum { RO_SUM = 0, RO_MEAN = 1, RO_MAX = 2, RO_MIN = 3, RO_STD = 4, RO_SUB = 5, RO_MUL = 6, RO_SQDIFF = 7 };
 struct RedLevelArgs {
     const int64_t *offsets;  // the set's CSR offsets (device, n+1)
     const int64_t *groups;   // group offsets (device, B+1)
@@ -43,6 +45,10 @@ struct RedEmitArgs {
 };
 hipError_t launch_red_level(bool f64, int op, const RedLevelArgs &a, int64_t rows,
                             hipStream_t s);
+hipError_t launch_red_interleave(bool f64, int64_t n, const int64_t *xo, const void *xt,
+                                 const void *xv, const int64_t *yo, const void *yt,
+                                 const void *yv, const int64_t *zo, void *zt, void *zv,
+                                 hipStream_t s);
 hipError_t launch_red_rowmap(const int64_t *offsets, int64_t n, int32_t *row_pcf, hipStream_t s);
 hipError_t launch_red_std(bool f64, const RedStdArgs &a, hipStream_t s);
 hipError_t launch_red_emit(bool f64, const RedEmitArgs &a, hipStream_t s);

@@ -94,3 +94,31 @@ def test_reduce_errors():
         api.reduce(X, "std", [0, 1, 10])  # std of one PCF
     with pytest.raises(PcfError):
         api.reduce(X, "mean", [0, 5])  # groups must cover the set
+
+
+@pytest.mark.parametrize("op", ["sum", "sub", "mul", "max", "min", "sqdiff"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_combine_bit_exact(op, dtype):
+    # one arithmetic operation per value on each side, so both precisions
+    # agree bit for bit; the tied set shares many breakpoints with itself
+    xs = workloads.uniform_counts(150, 1, 80, seed=106, dtype=dtype)
+    ys = _tied_set(150, seed=107, dtype=dtype)
+    X, Y = api.PcfSet(*xs, device=DEV), api.PcfSet(*ys, device=DEV)
+    got = _rows(api.combine(X, Y, op))
+    want = red.combine_sets(op, xs, ys, dtype=dtype)
+    for i, ((gt, gv), (wt, wv)) in enumerate(zip(got, want)):
+        assert np.array_equal(gt, wt) and np.array_equal(gv, wv), (op, i)
+    # against itself: f - f is the zero PCF, one row
+    Z = _rows(api.combine(X, X, "sub"))
+    assert all(len(t) == 1 and t[0] == 0 and v[0] == 0 for t, v in Z)
+
+
+def test_combine_errors():
+    xs = workloads.uniform_counts(10, 1, 20, seed=108)
+    X = api.PcfSet(*xs, device=DEV)
+    Y = api.PcfSet(*workloads.uniform_counts(11, 1, 20, seed=109), device=DEV)
+    with pytest.raises(PcfError):
+        api.combine(X, Y, "sum")  # different counts
+    Xf = api.PcfSet(xs[0], xs[1].astype(np.float32), xs[2].astype(np.float32), device=DEV)
+    with pytest.raises(PcfError):
+        api.combine(X, Xf, "sum")  # different dtypes
