@@ -71,7 +71,7 @@ typedef enum {
     PCF_EDATA = 2,        /* contract violation found by PCF_VALIDATE     */
     PCF_EDEVICE = 3,      /* HIP runtime error                            */
     PCF_ENOMEM = 4,       /* workspace too small                          */
-    PCF_EUNSUPPORTED = 5  /* valid request this build does not serve      */
+    PCF_EUNSUPPORTED = 5  /* valid request the library does not serve    */
 } pcf_status;
 
 typedef enum { PCF_F32 = 0, PCF_F64 = 1 } pcf_dtype;

@@ -5,7 +5,7 @@
 // once, left to right; every step closes one cell [x, y) of the common
 // refinement with y the earlier of the two next breakpoints, adds
 // h(f(x), g(x)) * (y - x) and moves the pointer(s) whose next breakpoint is
-// y. The paper's pair loop is used as is; what is specific to this build:
+// y. The paper's pair loop is used as is; what is specific to this library:
 //
 //  * Breakpoint records. Row k of a PCF is packed as (t_{k+1}, v_k): the
 //    value of piece k and the time where it ends; the last piece ends at a
