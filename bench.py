@@ -12,7 +12,11 @@ The JSON carries the whole-call throughput (pair integrals per second over
 the N(N-1)/2 upper-triangle pairs), the dominant kernel's roofline entry
 (FP64 VALU lane-operations; its duration from HIP events around calls that
 only launch the tile kernel) and the CPU oracle timed on a bounded sample on
-this host's cores. Extra workloads: --config batched | grad | strip | small.
+this host's cores. Unless --no-extras, it also carries the extra lines:
+batched (512 independent matrices), fwd_bwd (forward + adjoint), cross
+(10,000 x 20,000 cross-set matrix), single (L2 norms) and reduce (mean and
+std by reduction trees). --only NAME[,NAME] runs extra lines alone;
+--config strip the 62,500 x 500,000 strip of the 500,000-PCF set.
 """
 from __future__ import annotations
 
