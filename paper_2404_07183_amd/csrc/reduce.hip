@@ -241,10 +241,13 @@ __global__ void red_std_terms(RedStdArgs a)
         const int64_t gb = a.groups[lo], ge = a.groups[lo + 1];
         const T x = rt[r];
         const T mean = rv[r] / (T)(ge - gb);
-        T st[64];
-        int ht[64];
-        int top = 0;
-        for (int64_t i = gb; i < ge; ++i) {
+        // binary counter over the group's PCFs: after k terms, st[h] holds
+        // the sum of a complete subtree of 2^h terms for every set bit h of
+        // k (the level-by-level pairing); the loops unroll to constant
+        // indices
+        T st[32];
+        int64_t k = 0;
+        for (int64_t i = gb; i < ge; ++i, ++k) {
             const int64_t o = a.offsets[i], ni = a.offsets[i + 1] - o;
             int64_t l = 0, h = ni;  // rows with t <= x
             while (l < h) {
@@ -256,19 +259,27 @@ __global__ void red_std_terms(RedStdArgs a)
             }
             const T d = v[o + (l > 0 ? l - 1 : 0)] - mean;
             T s = d * d;
-            int hs = 0;
-            while (top > 0 && ht[top - 1] == hs) {
-                s = st[top - 1] + s;
-                --top;
-                ++hs;
+#pragma unroll
+            for (int hh = 0; hh < 32; ++hh) {
+                if ((k >> hh) & 1) {
+                    s = st[hh] + s;
+                } else {
+                    st[hh] = s;
+                    break;
+                }
             }
-            st[top] = s;
-            ht[top] = hs;
-            ++top;
         }
-        T acc = st[top - 1];
-        for (int k = top - 2; k >= 0; --k)
-            acc = st[k] + acc;
+        // fold the partial sums from the smallest subtree up
+        const int64_t M = ge - gb;
+        T acc = T(0);
+        bool have = false;
+#pragma unroll
+        for (int hh = 0; hh < 32; ++hh) {
+            if ((M >> hh) & 1) {
+                acc = have ? st[hh] + acc : st[hh];
+                have = true;
+            }
+        }
         q[r] = acc;
     }
 }
