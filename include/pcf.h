@@ -256,7 +256,10 @@ pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
  * level, an unpaired last item moving up), and the result keeps a row at
  * t = 0 and wherever the reduced value changes (ReducePair's rule), before
  * the mean or std transformation of the values; a one-PCF group returns its
- * PCF's rows unchanged. Arithmetic in the set's dtype.
+ * PCF's rows unchanged. Arithmetic in the set's dtype. The tree reads and
+ * writes every row of a group once per level (ceil(log2 m) levels); the std
+ * evaluates every member at every breakpoint of its group (O(rows x m)).
+ * PCF_EINVAL for bad groups or op, PCF_EUNSUPPORTED for 2^31 or more PCFs.
  * Calls: pcf_reduce_workspace_bytes sizes the workspace (device, caller
  * owned); pcf_reduce_rows runs the tree into it, writes the output offsets
  * to offsets_out (device, B+1) and offsets_out_host (host, B+1) and
@@ -285,7 +288,9 @@ pcf_status pcf_reduce(const pcf_set *X, int32_t B, const int64_t *group_offsets_
  * combination h_*(f, g)(t) = h(f(t), g(t)); Section 4, Algorithm ReducePair):
  * out_i = h_*(x_i, y_i) for X and Y of one dtype and one PCF count n, with
  *   PCF_COMBINE_SUM a + b, _SUB a - b, _MUL a b, _MAX, _MIN, _SQDIFF (a - b)^2.
- * Each result keeps a row at t = 0 and wherever its value changes. Calls as
+ * Each result keeps a row at t = 0 and wherever its value changes.
+ * PCF_EINVAL for different dtypes or counts or a bad op, PCF_EUNSUPPORTED for
+ * 2^30 or more PCFs. Calls as
  * for the reductions: pcf_combine_workspace_bytes; pcf_combine_rows writes
  * offsets_out (device, n+1) and offsets_out_host (host, n+1) and
  * synchronises; pcf_combine (asynchronous) writes t_out and v_out from the
