@@ -15,7 +15,8 @@ only launch the tile kernel) and the CPU oracle timed on a bounded sample on
 this host's cores. Unless --no-extras, it also carries the extra lines:
 batched (512 independent matrices), fwd_bwd (forward + adjoint), cross
 (10,000 x 20,000 cross-set matrix), single (L2 norms) and reduce (mean and
-std by reduction trees). --only NAME[,NAME] runs extra lines alone;
+std by reduction trees), bounded_weighted (L1 over a range with a time
+weight). --only NAME[,NAME] runs extra lines alone;
 --config strip the 62,500 x 500,000 strip of the 500,000-PCF set.
 """
 from __future__ import annotations
@@ -418,6 +419,43 @@ def run_reduce(steps, warmup):
     return res
 
 
+def run_bounded_weighted(steps, warmup):
+    """L1 distances over [2.5, 40) with the weight w(t) = exp(-0.1 t) on the
+    plain 20,000-PCF set (FP64): restriction, time warp and the full matrix
+    per call (the restricted and warped set is a new set every call, so its
+    tile plan is rebuilt too). Parity on 256 sampled pairs against the
+    oracle's per-cell sum of H(r) - H(l)."""
+    import torch
+
+    import oracle
+    from paper_2404_07183_amd import api, workloads
+
+    o, t, v = workloads.config_plain()
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    out = torch.empty((X.n, X.n), dtype=torch.float64, device="cuda:0")
+    ws = api.Workspace(device="cuda:0")
+    stream = torch.cuda.current_stream()
+    a, b, c = 2.5, 40.0, 0.1
+    call = lambda: api.pdist(X, 1.0, bounds=(a, b), weight=("exp", c), out=out, workspace=ws)
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    ms = _events_ms(call, steps, stream)
+    rng = np.random.default_rng(11)
+    I, J = rng.integers(0, X.n, 256), rng.integers(0, X.n, 256)
+    ref, ab = oracle.entries_w(oracle.LP, 1.0, oracle.W_EXP, c, o, t, v, I, J, a=a, b=b,
+                               with_abs=True)
+    got = out.cpu().numpy()[I, J]
+    pairs = X.n * (X.n - 1) / 2
+    return {"workload": "L1 over [2.5, 40) with weight exp(-0.1 t), N=20000 PCFs (counts "
+                        "U{50..500}), FP64; restriction + time warp + full matrix per call",
+            "ms_per_call": ms, "pairs_per_s": pairs / (ms * 1e-3),
+            "parity": {"pairs": 256,
+                       "max_error_over_scale": float(np.max(np.abs(got - ref) /
+                                                            np.maximum(ab, 1e-300))),
+                       "tolerance": 1e-12}}
+
+
 def run_grad(steps, warmup, plain_steps_per_s=None):
     """Forward + adjoint of L = sum W_ij d_2(f_i,f_j)^2 + sum U_ij <f_i,f_j>,
     N = 4,096 PCFs, FP64 (two forward matrices, two adjoint passes)."""
@@ -546,7 +584,7 @@ def main():
                     help="skip the batched and forward+adjoint measurements")
     ap.add_argument("--only", default=None,
                     help="comma-separated extra lines to run alone, without the headline "
-                         "(batched, fwd_bwd, cross, single, reduce): for profiling them")
+                         "(batched, fwd_bwd, cross, single, reduce, bounded_weighted)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -555,7 +593,7 @@ def main():
     if args.only:
         runs = {"batched": lambda k, w: run_batched(k, w), "fwd_bwd": lambda k, w: run_grad(k, w),
                 "cross": lambda k, w: run_cross(k, w), "single": run_single,
-                "reduce": run_reduce}
+                "reduce": run_reduce, "bounded_weighted": run_bounded_weighted}
         names = args.only.split(",")
         bad = [n for n in names if n not in runs]
         if bad:
@@ -580,6 +618,7 @@ def main():
         res["cross"] = run_cross(max(2, args.steps // 2), 1, plain)
         res["single"] = run_single(max(2, args.steps // 2), 1)
         res["reduce"] = run_reduce(max(2, args.steps // 2), 1)
+        res["bounded_weighted"] = run_bounded_weighted(max(2, args.steps // 2), 1)
     print(json.dumps(res), flush=True)
 
 
