@@ -125,3 +125,40 @@ def test_planner_rejects_pcf_with_2_pow_30_rows():
     assert "2^30" in str(e.value)
     nb, ns, nt, blocks = _inspect(np.array([0, 3, 2 + (1 << 30)], dtype=np.int64))
     assert nt >= 1
+
+
+def test_reduction_and_combination_arguments_need_no_device():
+    lib = _lib.load()
+    X = _lib.pcf_set(0, None, None, None, _lib.PCF_F64, None)
+    size = ctypes.c_size_t(0)
+    g = np.array([0], dtype=np.int64)
+    # unknown ops
+    assert lib.pcf_reduce_workspace_bytes(ctypes.byref(X), 0, g.ctypes.data, 9,
+                                          ctypes.byref(size)) == _lib.PCF_EINVAL
+    assert lib.pcf_combine_workspace_bytes(ctypes.byref(X), ctypes.byref(X), 9,
+                                           ctypes.byref(size)) == _lib.PCF_EINVAL
+    # the empty set reduces to no groups and combines to nothing
+    assert lib.pcf_reduce_workspace_bytes(ctypes.byref(X), 0, g.ctypes.data,
+                                          _lib.PCF_REDUCE_MEAN, ctypes.byref(size)) == _lib.PCF_OK
+    assert lib.pcf_combine_workspace_bytes(ctypes.byref(X), ctypes.byref(X),
+                                           _lib.PCF_COMBINE_SUM, ctypes.byref(size)) == _lib.PCF_OK
+    # groups that do not cover the set, negative B, NULL groups
+    g2 = np.array([0, 1], dtype=np.int64)
+    assert lib.pcf_reduce_workspace_bytes(ctypes.byref(X), 1, g2.ctypes.data,
+                                          _lib.PCF_REDUCE_SUM, ctypes.byref(size)) == _lib.PCF_EINVAL
+    assert lib.pcf_reduce_workspace_bytes(ctypes.byref(X), -1, g.ctypes.data,
+                                          _lib.PCF_REDUCE_SUM, ctypes.byref(size)) == _lib.PCF_EINVAL
+    assert lib.pcf_reduce_workspace_bytes(ctypes.byref(X), 1, None, _lib.PCF_REDUCE_SUM,
+                                          ctypes.byref(size)) == _lib.PCF_EINVAL
+    # different dtypes
+    Xf = _lib.pcf_set(0, None, None, None, _lib.PCF_F32, None)
+    assert lib.pcf_combine_workspace_bytes(ctypes.byref(X), ctypes.byref(Xf),
+                                           _lib.PCF_COMBINE_SUM, ctypes.byref(size)) == _lib.PCF_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
