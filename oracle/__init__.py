@@ -7,11 +7,15 @@ matrices"). Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg
 of ``bench.py`` may import it. The GPU library shares no code with it and never
 calls it.
 
-Reductions (mean, std, max, min of PCF collections) live in ``reduce.py``
-(plain Python). The pair integrals live in ``pcf_oracle.c`` (built with ``gcc -O2
--ffp-contract=off``); this module only builds that file and marshals NumPy
-arrays to it through ctypes. Kinds: ``LP`` (L_p distance), ``LP_POW`` (d_p^p)
-and ``GRAM`` (L2 inner product).
+Reductions (sum, mean, std, max, min of PCF collections) and pointwise
+combinations of two sets live in ``reduce.py`` (plain Python). The pair
+integrals live in ``pcf_oracle.c`` (built with ``gcc -O2 -ffp-contract=off``);
+this module only builds that file and marshals NumPy arrays to it through
+ctypes. Kinds: ``LP`` (L_p distance), ``LP_POW`` (d_p^p) and ``GRAM`` (L2
+inner product); ``entries_ab`` integrates over a range [a, b) (Section 2.2)
+and ``entries_w`` with a time weight through the antiderivative H (Section 3);
+``single`` gives the single-PCF integrals, L_p norms and sup norms (Section
+3.2).
 
 Parity pins: every function here is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` against printed values, closed forms, exact rational

@@ -34,7 +34,9 @@
  * per multiply and per add (build with -ffp-contract=off, no fast-math).
  *
  * Single-PCF functionals F(f) = r(int_a^b h(f)) (Section 3.2) follow
- * Algorithm IterateSegments: see orc_single below.
+ * Algorithm IterateSegments: see orc_single below. Pair integrals over a
+ * range [a, b) clip every cell to it (integral_ab); a time-dependent
+ * h = h0 w(t) adds H(r) - H(l) per cell with H = h0 W (integral_w).
  *
  * The adjoint (derivatives of F with respect to the values v_k and the
  * breakpoint times t_k, k >= 1) is not in the paper. Its reading:
