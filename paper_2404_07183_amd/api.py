@@ -209,7 +209,8 @@ def cross_gram(X, Y, *, out=None, validate=False, workspace=None, stream=None,
 def restrict(X, a, b, stream=None):
     """The PCFs of ``X`` times the indicator of [a, b) (a new set on the same
     device): any matrix of the result is the matrix of integrals over
-    [a, b) (Section 2.2). ``b`` may be ``inf``."""
+    [a, b) (Section 2.2). ``b`` may be ``inf``. Synchronises the stream
+    once (the output size is read back), so it cannot be graph-captured."""
     Xc = X.c_struct()
     off_h = np.empty(X.n + 1, dtype=np.int64)
     off_d = torch.empty(X.n + 1, dtype=torch.int64, device=X.t.device)
@@ -233,7 +234,8 @@ def warp(X, weight, c, stream=None):
     """The PCFs of ``X`` with every breakpoint t carried to W(t), the
     antiderivative of the weight (``"exp"``: w(t) = exp(-c t); ``"pow"``:
     w(t) = t^c). Any matrix of the result is the matrix of the time-weighted
-    integrals (Section 3, time-dependent h with antiderivative H)."""
+    integrals (Section 3, time-dependent h with antiderivative H).
+    Synchronises the stream once (the output size is read back)."""
     wk = _WEIGHTS.get(weight, weight)
     Xc = X.c_struct()
     off_h = np.empty(X.n + 1, dtype=np.int64)
@@ -259,7 +261,8 @@ def reduce(X, op="mean", groups=None, workspace=None, stream=None):
     """Reduce groups of the PCFs in ``X`` (Section 2.1 reductions, Section 4
     reduction trees): ``op`` in sum, mean, max, min, std (sample, 1/(m-1)).
     ``groups``: B+1 offsets into the set's PCFs (default: one group of all).
-    Returns a set of B PCFs."""
+    Returns a set of B PCFs. Synchronises the stream once (the output size
+    is read back)."""
     opc = _REDUCE_OPS.get(op, op)
     g = np.ascontiguousarray([0, X.n] if groups is None else groups, dtype=np.int64)
     B = len(g) - 1
@@ -289,7 +292,7 @@ _COMBINE_OPS = {"sum": 0, "sub": 1, "mul": 2, "max": 3, "min": 4, "sqdiff": 5}
 def combine(X, Y, op="sum", workspace=None, stream=None):
     """The induced combination h_*(x_i, y_i) of two sets index by index
     (Section 2.1): ``op`` in sum, sub, mul, max, min, sqdiff. Returns a set
-    of n PCFs."""
+    of n PCFs. Synchronises the stream once (the output size is read back)."""
     opc = _COMBINE_OPS.get(op, op)
     Xc, Yc = X.c_struct(), Y.c_struct()
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
