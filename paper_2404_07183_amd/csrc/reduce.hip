@@ -1,7 +1,9 @@
 // reduce.hip -- reductions of groups of PCFs (paper, Section 2.1
 // "Combinations and reductions"; Section 4, reduction trees and Algorithm
 // ReducePair): sum, max and min by the induced reduction, mean = sum / n and
-// the sample standard deviation sqrt(sum_i (f_i - mean)^2 / (n - 1)).
+// the sample standard deviation sqrt(sum_i (f_i - mean)^2 / (n - 1)); and
+// the combinations h_*(x_i, y_i) of two sets (also a - b, ab, (a - b)^2) as
+// reductions of the interleaved set in groups of two.
 //
 // Tree. A group of M PCFs is reduced by a binary tree: at level l the items
 // 2j and 2j+1 (each covering 2^l consecutive PCFs) are merged into item j of
@@ -38,13 +40,8 @@ namespace pcf {
 
 namespace {
 
-#ifndef PCF_RED_K
-#define PCF_RED_K 4
-#endif
-#ifndef PCF_RED_STAGE
-#define PCF_RED_STAGE 1
-#endif
-constexpr int kMergeK = PCF_RED_K;  // merged positions per lane
+// merged positions per lane (4 measured fastest against 2, 8 and 16)
+constexpr int kMergeK = 4;
 constexpr int kChunkRows = 1024;  // rows per wave in the root pass
 
 template <typename T, int OP>
@@ -112,8 +109,8 @@ __device__ __forceinline__ void wave_sync_lds()
 }
 
 // A wave takes 64 * kMergeK consecutive rows; lane l walks rows
-// l * kMergeK .. of them. With PCF_RED_STAGE the results go through a
-// wave-private LDS buffer so the stores to memory are coalesced.
+// l * kMergeK .. of them. The results go through a wave-private LDS buffer
+// so that the stores to memory are coalesced.
 template <typename T, int OP>
 __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
 {
@@ -122,9 +119,7 @@ __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
     T *__restrict__ tout = reinterpret_cast<T *>(a.tout);
     T *__restrict__ vout = reinterpret_cast<T *>(a.vout);
     constexpr int64_t kPerWave = 64 * kMergeK;
-#if PCF_RED_STAGE
     __shared__ T st_t[4][kPerWave], st_v[4][kPerWave];
-#endif
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t span = (int64_t)1 << a.level;
     const int64_t r0g = a.offsets[a.groups[0]], r1g = a.offsets[a.groups[a.B]];
@@ -182,17 +177,11 @@ __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
                     }
                     val = red_op<T, OP>(fx, gx);
                 }
-#if PCF_RED_STAGE
                 st_t[wv][r - wb] = x;
                 st_v[wv][r - wb] = val;
-#else
-                tout[r] = x;
-                vout[r] = val;
-#endif
                 ++q;
             }
         }
-#if PCF_RED_STAGE
         wave_sync_lds();
         const int64_t cnt = r1g - wb < kPerWave ? r1g - wb : kPerWave;
         for (int64_t k = lane; k < cnt; k += 64) {
@@ -200,7 +189,6 @@ __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
             vout[wb + k] = st_v[wv][k];
         }
         wave_sync_lds();
-#endif
     }
 }
 
