@@ -365,10 +365,14 @@ def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream
 
 
 def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=None,
-                     upper_only=False, validate=False, stream=None, shape=None):
+                     upper_only=False, validate=False, stream=None, shape=None,
+                     bounds=None, weight=None):
     """Independent full matrices of the problems ``set_offsets`` cuts ``X``
     into, in one launch. Returns ``(out_flat, out_offsets)``: problem b's
-    s_b x s_b matrix is ``out_flat[out_offsets[b]:][:s_b*s_b]``."""
+    s_b x s_b matrix is ``out_flat[out_offsets[b]:][:s_b*s_b]``.
+    ``bounds`` and ``weight`` as in ``pdist`` (the set is transformed first;
+    PCF indices are kept)."""
+    X = _transform(X, bounds, weight, stream)
     so = np.ascontiguousarray(set_offsets, dtype=np.int64)
     B = len(so) - 1
     sizes = np.diff(so)

@@ -99,3 +99,23 @@ def test_batched_graph_replay():
         torch.cuda.synchronize()
         assert torch.equal(out, eager)
         _ = (X.t * 2).sum().item()  # unrelated eager work between replays
+
+
+def test_batch_with_range_and_weight_vs_oracle():
+    # bounds and a time weight: each problem's matrix against the oracle's
+    # weighted integrals over the range
+    so, o, t, v = _small_batch()
+    X = api.PcfSet(o, t, v, device=DEV)
+    a, b, c = 1.5, 30.0, 0.2
+    out, oo = api.pairwise_batched(so, X, api.PCF_LP, 1.0, bounds=(a, b), weight=("exp", c))
+    out = out.cpu().numpy()
+    for k in range(len(so) - 1):
+        s = so[k + 1] - so[k]
+        if s == 0:
+            continue
+        M = out[oo[k]:oo[k] + s * s].reshape(s, s)
+        oo_, tt, vv = _sub(o, t, v, so[k], so[k + 1])
+        I, J = np.meshgrid(np.arange(s), np.arange(s), indexing="ij")
+        R, ab = oracle.entries_w(oracle.LP, 1.0, oracle.W_EXP, c, oo_, tt, vv, I.ravel(),
+                                 J.ravel(), a=a, b=b, with_abs=True)
+        assert np.all(np.abs(M.ravel() - R) <= 1e-12 * np.maximum(ab, 1e-300)), k
