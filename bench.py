@@ -16,7 +16,8 @@ this host's cores. Unless --no-extras, it also carries the extra lines:
 batched (512 independent matrices), fwd_bwd (forward + adjoint), cross
 (10,000 x 20,000 cross-set matrix), single (L2 norms) and reduce (mean and
 std by reduction trees), bounded_weighted (L1 over a range with a time
-weight). --only NAME[,NAME] runs extra lines alone;
+weight). --only NAME[,NAME] runs extra lines alone (also general_p: d_p^p for
+p = 3, 3.5, 2.7 in both precisions);
 --config strip the 62,500 x 500,000 strip of the 500,000-PCF set.
 """
 from __future__ import annotations
@@ -456,6 +457,42 @@ def run_bounded_weighted(steps, warmup):
                        "tolerance": 1e-12}}
 
 
+def run_general_p(steps, warmup):
+    """d_p^p matrices of the plain 20,000-PCF set for p = 3 (squaring),
+    p = 3.5 (squaring and a square root) and p = 2.7 (FP64: the 2^(p log2 x)
+    series; FP32: the hardware base-2 log and exp), FP64 and FP32; tile plan
+    and packed records reused between calls, as in the headline. Parity on
+    256 sampled pairs against the oracle (FP32: on the rounded inputs)."""
+    import torch
+
+    import oracle
+    from paper_2404_07183_amd import api, workloads
+
+    res = {"workload": "d_p^p matrices, N=20000 PCFs (counts U{50..500}), p = 3, 3.5, 2.7"}
+    rng = np.random.default_rng(12)
+    for dt, name in ((np.float64, "f64"), (np.float32, "f32")):
+        o, t, v = workloads.config_plain(dtype=dt)
+        X = api.PcfSet(o, t, v, device="cuda:0")
+        out = torch.empty((X.n, X.n), dtype=X.dtype, device="cuda:0")
+        ws = api.Workspace(device="cuda:0")
+        stream = torch.cuda.current_stream()
+        I, J = rng.integers(0, X.n, 256), rng.integers(0, X.n, 256)
+        for p in (3.0, 3.5, 2.7):
+            api.pdist(X, p, power=True, out=out, workspace=ws)
+            for _ in range(warmup):
+                api.pdist(X, p, power=True, out=out, workspace=ws, packed=True)
+            torch.cuda.synchronize()
+            ms = _events_ms(lambda: api.pdist(X, p, power=True, out=out, workspace=ws,
+                                              packed=True), steps, stream)
+            ref, ab = oracle.entries(oracle.LP_POW, p, o, t.astype(np.float64),
+                                     v.astype(np.float64), I, J, with_abs=True)
+            got = out.cpu().numpy().astype(np.float64)[I, J]
+            res["p%g_%s" % (p, name)] = {
+                "ms_per_call": ms,
+                "max_error_over_scale": float(np.max(np.abs(got - ref) / np.maximum(ab, 1e-300)))}
+    return res
+
+
 def run_grad(steps, warmup, plain_steps_per_s=None):
     """Forward + adjoint of L = sum W_ij d_2(f_i,f_j)^2 + sum U_ij <f_i,f_j>,
     N = 4,096 PCFs, FP64 (two forward matrices, two adjoint passes)."""
@@ -584,7 +621,8 @@ def main():
                     help="skip the batched and forward+adjoint measurements")
     ap.add_argument("--only", default=None,
                     help="comma-separated extra lines to run alone, without the headline "
-                         "(batched, fwd_bwd, cross, single, reduce, bounded_weighted)")
+                         "(batched, fwd_bwd, cross, single, reduce, bounded_weighted, "
+                         "general_p)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -593,7 +631,8 @@ def main():
     if args.only:
         runs = {"batched": lambda k, w: run_batched(k, w), "fwd_bwd": lambda k, w: run_grad(k, w),
                 "cross": lambda k, w: run_cross(k, w), "single": run_single,
-                "reduce": run_reduce, "bounded_weighted": run_bounded_weighted}
+                "reduce": run_reduce, "bounded_weighted": run_bounded_weighted,
+                "general_p": run_general_p}
         names = args.only.split(",")
         bad = [n for n in names if n not in runs]
         if bad:
