@@ -602,6 +602,16 @@ def run_strip(args):
     }
 
 
+def calibration_copy():
+    """One plain 1 GiB device-to-device copy: a reference for HBM byte counters."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,15 +647,12 @@ def main():
         bad = [n for n in names if n not in runs]
         if bad:
             ap.error("unknown line(s) for --only: %s" % ", ".join(bad))
+        if args.calibration_copy:
+            calibration_copy()
         print(json.dumps({n: runs[n](args.steps, args.warmup) for n in names}), flush=True)
         return
     if args.calibration_copy:
-        import torch
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy()
     if args.config == "strip":
         print(json.dumps(run_strip(args)), flush=True)
         return

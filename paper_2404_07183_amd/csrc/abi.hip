@@ -414,6 +414,8 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
         if (m < (op == PCF_REDUCE_STD ? 2 : 1))
             return fail(PCF_EINVAL, "group " + std::to_string(b) + " has " + std::to_string(m) +
                                         " PCFs (at least 1, 2 for PCF_REDUCE_STD)");
+        if (op == PCF_REDUCE_STD && m >= ((int64_t)1 << 30))
+            return fail(PCF_EUNSUPPORTED, "a standard deviation over 2^30 or more PCFs");
         mmax = m > mmax ? m : mmax;
     }
     std::vector<int64_t> obuf;

@@ -231,9 +231,11 @@ __global__ void red_std_terms(RedStdArgs a)
         const T mean = rv[r] / (T)(ge - gb);
         // binary counter over the group's PCFs: after k terms, st[h] holds
         // the sum of a complete subtree of 2^h terms for every set bit h of
-        // k (the level-by-level pairing); the loops unroll to constant
-        // indices
-        T st[32];
+        // k (the level-by-level pairing), in two levels of 15 heights
+        // (blocks of 2^15 terms, then blocks; groups below 2^30 PCFs) so
+        // that the loops unroll to constant indices into small arrays.
+        constexpr int kIn = 15;
+        T st[kIn], st2[kIn];
         int64_t k = 0;
         for (int64_t i = gb; i < ge; ++i, ++k) {
             const int64_t o = a.offsets[i], ni = a.offsets[i + 1] - o;
@@ -247,13 +249,27 @@ __global__ void red_std_terms(RedStdArgs a)
             }
             const T d = v[o + (l > 0 ? l - 1 : 0)] - mean;
             T s = d * d;
+            bool placed = false;
 #pragma unroll
-            for (int hh = 0; hh < 32; ++hh) {
+            for (int hh = 0; hh < kIn; ++hh) {
                 if ((k >> hh) & 1) {
                     s = st[hh] + s;
                 } else {
                     st[hh] = s;
+                    placed = true;
                     break;
+                }
+            }
+            if (!placed) {  // a complete block of 2^15 terms
+                const int64_t kb = k >> kIn;
+#pragma unroll
+                for (int hh = 0; hh < kIn; ++hh) {
+                    if ((kb >> hh) & 1) {
+                        s = st2[hh] + s;
+                    } else {
+                        st2[hh] = s;
+                        break;
+                    }
                 }
             }
         }
@@ -262,9 +278,16 @@ __global__ void red_std_terms(RedStdArgs a)
         T acc = T(0);
         bool have = false;
 #pragma unroll
-        for (int hh = 0; hh < 32; ++hh) {
+        for (int hh = 0; hh < kIn; ++hh) {
             if ((M >> hh) & 1) {
                 acc = have ? st[hh] + acc : st[hh];
+                have = true;
+            }
+        }
+#pragma unroll
+        for (int hh = 0; hh < kIn; ++hh) {
+            if (((M >> kIn) >> hh) & 1) {
+                acc = have ? st2[hh] + acc : st2[hh];
                 have = true;
             }
         }
