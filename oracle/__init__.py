@@ -19,10 +19,10 @@ and ``entries_w`` with a time weight through the antiderivative H (Section 3);
 
 Parity pins: every function here is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` against printed values, closed forms, exact rational
-arithmetic, an independent brute force and finite differences. The single
-convention with no independent pin is the averaging of one-sided time
-derivatives at an exact cross-PCF time tie (parity unpinned for tied
-breakpoints; the gradient tests use tie-free inputs).
+arithmetic, an independent brute force and finite differences. The averaging
+of one-sided time derivatives at a breakpoint shared by two different PCFs is
+pinned by exact one-sided differences of the forward oracle on dyadic data;
+the FP32 mode of ``reduce.py`` by float32 NumPy evaluation of the same tree.
 """
 from __future__ import annotations
 

@@ -7,8 +7,11 @@
   the inner product, q = p for d_p^p),
 * linearity of the Gram loss: dL/dv_i[k] = integral over piece k of
   sum_j (G_ij + G_ji) f_j, evaluated by dense resampling.
-Inputs are tie-free (continuous random times), where the one-sided time
-derivatives agree.
+These inputs are tie-free (continuous random times), where the one-sided
+time derivatives agree. At a breakpoint shared by two different PCFs the
+oracle takes the mean of the one-sided derivatives; that convention is pinned
+by exact one-sided differences of the forward oracle on dyadic data
+(test_tie_averaged_time_derivative).
 """
 import numpy as np
 import pytest
@@ -109,3 +112,60 @@ def test_gram_linearity_dense():
         for k in range(len(a) - 1):
             exp = float(np.sum(S[i][piece == k]) * 0.25)
             assert gv[off[i] + k] == exp
+
+
+def _dyadic_tied_set(rng, M=6, grid=8, span=3):
+    """PCFs whose interior breakpoints sit on the grid k/grid, so that
+    breakpoints of different PCFs coincide; dyadic values."""
+    counts = rng.integers(4, 10, size=M)
+    off = np.zeros(M + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    t = np.empty(off[-1])
+    v = np.empty(off[-1])
+    for i in range(M):
+        a, b = off[i], off[i + 1]
+        n = b - a
+        t[a] = 0.0
+        t[a + 1:b] = np.sort(rng.choice(np.arange(1, span * grid), n - 1, replace=False)) / grid
+        v[a:b - 1] = rng.integers(-32, 33, size=n - 1) / 8.0
+        v[b - 1] = 0.0
+    return off, t, v
+
+
+@pytest.mark.parametrize("kind,p", [(oracle.LP, 1.0), (oracle.LP_POW, 2.0),
+                                    (oracle.GRAM, 0.0), (oracle.LP_POW, 3.0)])
+def test_tie_averaged_time_derivative(kind, p):
+    """At a breakpoint shared by two different PCFs the loss has a kink in
+    that time; the oracle's reading is the mean of the one-sided derivatives.
+    Both one-sided derivatives are taken here from the forward oracle by
+    one-sided differences: with dyadic times, values and weights and a step
+    h = 1/64 (below the grid spacing 1/8, so no breakpoint is crossed) every
+    integral is exact and the loss is linear on each side of the kink, so the
+    difference quotients are the exact one-sided derivatives."""
+    rng = np.random.default_rng(31 + kind + int(p))
+    off, t, v = _dyadic_tied_set(rng)
+    M = len(off) - 1
+    G = rng.integers(0, 17, size=(M, M)) / 16.0
+    gt, _ = oracle.backward(kind, p, off, t, v, G)
+    h = 1.0 / 64
+    L0 = _loss(kind, p, off, t, v, G)
+    first = set(off[:-1].tolist())
+    owner = np.repeat(np.arange(M), np.diff(off))
+    kinks = 0
+    for k in range(len(t)):
+        if k in first:
+            continue
+        tp, tm = t.copy(), t.copy()
+        tp[k] += h
+        tm[k] -= h
+        right = (_loss(kind, p, off, tp, v, G) - L0) / h
+        left = (L0 - _loss(kind, p, off, tm, v, G)) / h
+        tied = np.any((t == t[k]) & (owner != owner[k]))
+        if not tied:
+            assert right == pytest.approx(left, rel=1e-12, abs=1e-12)
+        elif right != left:
+            kinks += 1
+        assert gt[k] == pytest.approx(0.5 * (right + left), rel=1e-12, abs=1e-12), k
+    # the set really exercises the convention: several tied breakpoints
+    # whose one-sided derivatives differ
+    assert kinks >= 3

@@ -122,3 +122,91 @@ def test_combinations_pointwise(op):
         x = np.concatenate([x, (x[:-1] + x[1:]) / 2, [x[-1] + 1]])
         assert np.array_equal(red.evaluate(pcf, x), f(red.evaluate(fi, x), red.evaluate(gi, x)))
         _check_minimal(pcf)
+
+
+def _tree32(vals, op):
+    """Level-by-level binary tree over float32 arrays (neighbours (2j, 2j+1),
+    an unpaired last item moves up), one NumPy float32 operation per node."""
+    level = list(vals)
+    while len(level) > 1:
+        nxt = [op(level[k], level[k + 1]) for k in range(0, len(level) - 1, 2)]
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    return level[0]
+
+
+@pytest.mark.parametrize("op", ["sum", "mean", "max", "min", "std"])
+def test_pointwise_float32(op):
+    """The FP32 mode: every row of the reduced PCF equals, bit for bit, a
+    float32 NumPy evaluation of the same tree at every breakpoint and between
+    them (each node one float32 add, max or min; mean one float32 division;
+    std the float32 squared differences from that mean, tree-summed, divided
+    by n - 1 and square-rooted in float32)."""
+    f32 = np.float32
+    o, t, v = workloads.uniform_counts(41, 1, 40, seed=95, dtype=np.float32)
+    assert t.dtype == np.float32 and v.dtype == np.float32
+    groups = [0, 2, 4, 10, 25, 41] if op == "std" else [0, 2, 3, 10, 25, 41]
+    res = red.reduce_groups(op, groups, o, t, v, dtype=np.float32)
+    x = _probe_points(o, t)
+    for b, pcf in enumerate(res):
+        assert pcf[0].dtype == np.float32 and pcf[1].dtype == np.float32
+        vals = [red.evaluate((t[o[i]:o[i + 1]], v[o[i]:o[i + 1]]), x).astype(f32)
+                for i in range(groups[b], groups[b + 1])]
+        n = len(vals)
+        if op in ("max", "min"):
+            want = _tree32(vals, np.maximum if op == "max" else np.minimum)
+        else:
+            s = _tree32(vals, np.add)
+            want = s
+            if op in ("mean", "std"):
+                want = (s / f32(n)).astype(f32)
+            if op == "std":
+                m = want
+                sq = [((a - m) * (a - m)).astype(f32) for a in vals]
+                want = np.sqrt((_tree32(sq, np.add) / f32(n - 1)).astype(f32))
+        assert want.dtype == np.float32
+        got = red.evaluate(pcf, x)
+        assert np.array_equal(got, want), (op, b)
+        if n > 1:
+            _check_minimal(pcf)
+
+
+@pytest.mark.parametrize("op", ["sum", "sub", "mul", "max", "min", "sqdiff"])
+def test_combinations_float32(op):
+    """FP32 combinations equal a float32 NumPy evaluation of h(f_i(x), g_i(x))
+    at every breakpoint and between them, bit for bit."""
+    f32 = np.float32
+    xs = workloads.uniform_counts(25, 1, 40, seed=96, dtype=np.float32)
+    ys = workloads.uniform_counts(25, 1, 40, seed=97, dtype=np.float32)
+    res = red.combine_sets(op, xs, ys, dtype=np.float32)
+    f = {"sum": np.add, "sub": np.subtract, "mul": np.multiply, "max": np.maximum,
+         "min": np.minimum, "sqdiff": lambda a, b: (a - b) * (a - b)}[op]
+    for i, pcf in enumerate(res):
+        fi = (xs[1][xs[0][i]:xs[0][i + 1]], xs[2][xs[0][i]:xs[0][i + 1]])
+        gi = (ys[1][ys[0][i]:ys[0][i + 1]], ys[2][ys[0][i]:ys[0][i + 1]])
+        x = np.unique(np.concatenate([fi[0], gi[0]])).astype(np.float64)
+        x = np.concatenate([x, (x[:-1] + x[1:]) / 2, [x[-1] + 1]])
+        want = f(red.evaluate(fi, x).astype(f32), red.evaluate(gi, x).astype(f32))
+        assert want.dtype == np.float32
+        assert np.array_equal(red.evaluate(pcf, x), want)
+        _check_minimal(pcf)
+
+
+def test_dyadic_float32_sums_are_exact():
+    """On dyadic FP32 data every float32 partial sum is exact: the FP32
+    reduction equals the exact (FP64) pointwise sum."""
+    rng = np.random.default_rng(98)
+    pcfs = []
+    for _ in range(19):
+        n = int(rng.integers(1, 12))
+        ts = np.concatenate([[0.0], np.sort(rng.choice(np.arange(1, 200), n - 1, replace=False))]) / 8
+        vs = np.concatenate([rng.integers(-64, 64, n - 1) / 16.0, [0.0]])
+        pcfs.append((ts.astype(np.float32), vs.astype(np.float32)))
+    o = np.concatenate([[0], np.cumsum([len(p[0]) for p in pcfs])])
+    t = np.concatenate([p[0] for p in pcfs])
+    v = np.concatenate([p[1] for p in pcfs])
+    (st, sv), = red.reduce_groups("sum", [0, 19], o, t, v, dtype=np.float32)
+    x = _probe_points(o, t.astype(np.float64))
+    exact = _values(o, t.astype(np.float64), v.astype(np.float64), 0, 19, x).sum(0)
+    assert np.array_equal(red.evaluate((st, sv), x).astype(np.float64), exact)
