@@ -108,6 +108,20 @@ def _flags(upper_only, validate, reuse, shape=None):
     return f
 
 
+def _check_out(out, X, oshape):
+    """A caller's output matrix: the input's dtype and device, row-major,
+    at least ``oshape`` (the library writes rows of ``oshape[1]`` entries at
+    stride ``out.stride(0)``)."""
+    if out.dtype != X.dtype or out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a row-major 2-D tensor of the input dtype")
+    if out.device != X.t.device:
+        raise ValueError("out must be on the device of the set (%s), not %s"
+                         % (X.t.device, out.device))
+    if out.shape[0] < oshape[0] or out.shape[1] < oshape[1]:
+        raise ValueError("out has shape %s; the result needs %s"
+                         % (tuple(out.shape), tuple(oshape)))
+
+
 def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
              packed=False, shape=None):
     Xc = X.c_struct()
@@ -118,10 +132,11 @@ def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
         oshape = (window[1] - window[0], window[3] - window[2])
     if out is None:
         out = torch.zeros(oshape, dtype=X.dtype, device=X.t.device)
-    if out.dtype != X.dtype or out.dim() != 2 or out.stride(1) != 1:
-        raise ValueError("out must be a row-major 2-D tensor of the input dtype")
+    _check_out(out, X, oshape)
     ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
-    key = ("fwd", kind, X.n, id(X.offsets_host), window, upper_only, shape)
+    # the plan depends on the record size (dtype) and on the plan type
+    # (forward here; the adjoint's plan has other blocks)
+    key = ("fwd", kind, X.dtype, X.n, id(X.offsets_host), window, upper_only, shape)
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
     reuse = ws.planned == key
     if not reuse:
@@ -174,10 +189,11 @@ def _cross(X, Y, kind, p, out, validate, workspace, stream, shape=None):
     if X.dtype != Y.dtype:
         raise ValueError("X and Y must share their dtype")
     Xc, Yc = X.c_struct(), Y.c_struct()
+    if Y.t.device != X.t.device:
+        raise ValueError("X and Y must be on one device")
     if out is None:
         out = torch.zeros((X.n, Y.n), dtype=X.dtype, device=X.t.device)
-    if out.dtype != X.dtype or out.dim() != 2 or out.stride(1) != 1:
-        raise ValueError("out must be a row-major 2-D tensor of the input dtype")
+    _check_out(out, X, (X.n, Y.n))
     ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
     ws.ensure(_lib.pcf_cross_workspace_bytes(Xc, Yc))
@@ -382,8 +398,13 @@ def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=
     total = int((sizes ** 2).sum())
     if out is None:
         out = torch.zeros(total, dtype=X.dtype, device=X.t.device)
+    if out.dtype != X.dtype or not out.is_contiguous() or out.device != X.t.device:
+        raise ValueError("out must be a contiguous tensor of the set's dtype and device")
+    if out.numel() < total:
+        raise ValueError("out holds %d entries; the matrices need %d" % (out.numel(), total))
     Xc = X.c_struct()
-    key = ("batched", kind, X.n, id(X.offsets_host), so.tobytes(), upper_only, shape)
+    key = ("batched", kind, X.dtype, X.n, id(X.offsets_host), so.tobytes(), upper_only,
+           shape)
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
     reuse = ws.planned == key
     if not reuse:

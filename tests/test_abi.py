@@ -162,3 +162,71 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_out_tensors_are_checked_before_the_library_is_called(monkeypatch):
+    """A short, wrongly placed or wrongly typed out tensor is refused on the
+    host, before any library call (the C ABI only sees ldo)."""
+    import torch
+    from paper_2404_07183_amd import _lib, api
+
+    def no_call(*a, **k):  # any library call would be a failure here
+        raise AssertionError("library called")
+
+    monkeypatch.setattr(_lib, "pcf_pairwise_lp", no_call, raising=False)
+    monkeypatch.setattr(_lib, "pcf_gram", no_call, raising=False)
+    monkeypatch.setattr(_lib, "pcf_cross", no_call, raising=False)
+    monkeypatch.setattr(_lib, "pcf_pairwise_batched", no_call, raising=False)
+    monkeypatch.setattr(_lib, "pcf_workspace_bytes", lambda *a: 256, raising=False)
+    monkeypatch.setattr(_lib, "pcf_cross_workspace_bytes", lambda *a: 256, raising=False)
+    monkeypatch.setattr(_lib, "pcf_batched_workspace_bytes", lambda *a: 256, raising=False)
+    o = np.array([0, 2, 5, 7], dtype=np.int64)
+    t = np.array([0, 1, 0, 1, 2, 0, 3], dtype=np.float64)
+    v = np.array([1, 0, 2, 1, 0, 5, 0], dtype=np.float64)
+    X = api.PcfSet(o, t, v, device="cpu")
+    ws = api.Workspace(device="cpu")
+    with pytest.raises(ValueError, match="shape"):
+        api.pdist(X, out=torch.zeros((2, 3), dtype=torch.float64), workspace=ws)
+    with pytest.raises(ValueError, match="shape"):
+        api.gram(X, window=(0, 3, 1, 3), out=torch.zeros((3, 1), dtype=torch.float64),
+                 workspace=ws)
+    with pytest.raises(ValueError, match="device"):
+        api.pdist(X, out=torch.zeros((3, 3), dtype=torch.float64, device="meta"),
+                  workspace=ws)
+    with pytest.raises(ValueError, match="dtype"):
+        api.pdist(X, out=torch.zeros((3, 3), dtype=torch.float32), workspace=ws)
+    with pytest.raises(ValueError, match="shape"):
+        api.cdist(X, X, out=torch.zeros((3, 2), dtype=torch.float64), workspace=ws)
+    with pytest.raises(ValueError, match="need"):
+        api.pairwise_batched([0, 1, 3], X, out=torch.zeros(4, dtype=torch.float64),
+                             workspace=ws)
+
+
+def test_plan_key_separates_dtypes(monkeypatch):
+    """Two sets sharing one offsets array but differing in dtype never reuse
+    each other's plan through one Workspace (the record size differs): the
+    second call must not pass PCF_REUSE_PLAN; a repeat call on the same set
+    does."""
+    import torch
+    from paper_2404_07183_amd import _lib, api
+    seen = []
+
+    def fake_lp(Xc, kind, p, out, ldo, win, ws, nbytes, flags, stream):
+        seen.append((Xc.dtype, bool(flags & _lib.PCF_REUSE_PLAN)))
+        return 0
+
+    monkeypatch.setattr(_lib, "pcf_pairwise_lp", fake_lp, raising=False)
+    monkeypatch.setattr(_lib, "pcf_workspace_bytes", lambda *a: 256, raising=False)
+    monkeypatch.setattr(api, "_stream_handle", lambda s=None: None)
+    o = np.array([0, 2, 5], dtype=np.int64)
+    t = np.array([0, 1, 0, 1, 2], dtype=np.float64)
+    v = np.array([1, 0, 2, 1, 0], dtype=np.float64)
+    X64 = api.PcfSet(o, t, v, device="cpu")
+    X32 = api.PcfSet(X64.offsets_host, t.astype(np.float32), v.astype(np.float32),
+                     device="cpu")
+    assert X32.offsets_host is X64.offsets_host
+    ws = api.Workspace(device="cpu")
+    api.pdist(X32, workspace=ws)
+    api.pdist(X64, workspace=ws)
+    api.pdist(X64, workspace=ws)
+    assert seen == [(_lib.PCF_F32, False), (_lib.PCF_F64, False), (_lib.PCF_F64, True)]
