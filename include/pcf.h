@@ -124,7 +124,11 @@ pcf_status pcf_workspace_bytes(const pcf_set *X, pcf_kind kind,
 
 /* L_p distance matrix of X (PCF_LP, p >= 1) or its p-th power
  * (PCF_LP_POW): out[i][j] = F(f_i, f_j) (Section 3.1 with h = |a-b|^p,
- * Section 2.2). p = 1 and p = 2 use exact products; other p use pow.
+ * Section 2.2). p = 1 and p = 2 use exact products, other integer p
+ * squaring; in FP64 p = k + 1/2 adds one square root and any other p is
+ * 2^(p log2 |a-b|) by a series (relative error within a few units of the
+ * last place times |p log2 |a-b||), in FP32 every non-integer p uses the
+ * hardware base-2 log and exp.
  * Errors: PCF_EINVAL (null pointers, n < 0, p < 1 or not finite, bad
  * window, ldo too small, kind not an L_p kind), PCF_ENOMEM (ws_bytes too
  * small), PCF_EDATA (PCF_VALIDATE found a violation; the index of the first

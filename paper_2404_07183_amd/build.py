@@ -30,7 +30,10 @@ def compile_flags():
         "-O3",
         "-std=c++17",
         "-fPIC",
-        # no packed FP32 instructions anywhere in device code
+        # no packed FP32 instructions anywhere in device code; hipcc has no
+        # device-only spelling of this -Xclang pair (-Xarch_device refuses
+        # it, -mno-packed-fp32-ops does not remove the instructions), so the
+        # host pass sees it too and prints that it ignores the feature
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         # the tile queue's single-lane ticket atomic stays a plain atomic:
         # the wave-aggregating rewrite would wait for its return right away,

@@ -474,15 +474,10 @@ template <int HK>
 static hipError_t launch_bwd_t(const BwdArgs &a, int grid, hipStream_t s)
 {
     const size_t shm = tile_shared_bytes(16, true);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&pairwise_adjoint_tiles<HK>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    const hipError_t e = ensure_dynamic_lds(
+        reinterpret_cast<const void *>(&pairwise_adjoint_tiles<HK>), (int)shm);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL((pairwise_adjoint_tiles<HK>), dim3(grid), dim3(kThreads),
                        shm, s, a);
     return hipGetLastError();

@@ -39,6 +39,10 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "common.hpp"
 #include "launch.hpp"
 #include "tile.hpp"
@@ -455,6 +459,23 @@ hipError_t launch_validate(const int64_t *offsets, int64_t n, const void *t,
     return hipGetLastError();
 }
 
+hipError_t ensure_dynamic_lds(const void *kernel, int bytes)
+{
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;  // (kernel, device)
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({kernel, dev}))
+        return hipSuccess;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        done.insert({kernel, dev});
+    return e;
+}
+
 hipError_t launch_reset(unsigned char *ws, hipStream_t s)
 {
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, ws);
@@ -465,15 +486,10 @@ template <typename T, int HK, int RT>
 static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
 {
     const size_t shm = tile_shared_bytes((int)sizeof(Rec<T>), false);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&pairwise_tiles<T, HK, RT>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    const hipError_t e = ensure_dynamic_lds(
+        reinterpret_cast<const void *>(&pairwise_tiles<T, HK, RT>), (int)shm);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL((pairwise_tiles<T, HK, RT>), dim3(grid), dim3(kThreads),
                        shm, s, a);
     return hipGetLastError();
@@ -481,7 +497,8 @@ static hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
 
 // The (h, root) combinations the entry points use: |a-b| and ab without a
 // root, (a-b)^2 with or without sqrt, |a-b|^p with or without the p-th root
-// (integer p: squaring; p = k + 1/2: squaring and one sqrt; else pow).
+// (integer p: squaring; p = k + 1/2: squaring and one sqrt; any other p:
+// 2^(p log2 |a-b|)).
 template <typename T>
 static hipError_t launch_fwd_dtype(int hk, const FwdArgs &a, int grid,
                                    hipStream_t s)

@@ -11,7 +11,8 @@ namespace pcf {
 
 // h codes of the combination integral (Section 2.2 of the paper).
 // kPowInt: |a-b|^p for an integer p, by squaring; kPowHalf: p = k + 1/2, by
-// squaring and one square root; kPow: any other p, by pow.
+// squaring and one square root; kPow: any other p, as 2^(p log2 |a-b|) (FP64:
+// the series of pow64.hpp; FP32: the hardware base-2 log and exp).
 enum HKind : int { kAbs = 0, kSqr = 1, kProd = 2, kPow = 3, kPowHalf = 4, kPowInt = 5 };
 // r codes of the combination integral.
 enum Root : int { kRootNone = 0, kRootSqrt = 1, kRootPow = 2 };
@@ -78,6 +79,9 @@ hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);
 hipError_t launch_backward(int hk, const BwdArgs &a, int grid, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+// Raises a kernel's dynamic-LDS limit to `bytes` once per device (thread
+// safe: concurrent first calls from several host threads all wait for it).
+hipError_t ensure_dynamic_lds(const void *kernel, int bytes);
 size_t tile_shared_bytes(int rec_bytes, bool backward);
 
 }  // namespace pcf
