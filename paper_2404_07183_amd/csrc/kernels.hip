@@ -133,22 +133,6 @@ __global__ void validate_rows(const int64_t *__restrict__ offsets, int64_t n,
 // step: one full-wave LDS read, no divergent branch. The end time of the
 // piece that goes on is max(P.t, Q.t), which saves two selects.
 
-// Record pointers: LDS (32-bit addresses) or global memory.
-template <typename T> struct LdsSrc {
-    typedef const __attribute__((address_space(3))) typename RecVec<T>::type *ptr;
-    __device__ __forceinline__ static ptr at(const Rec<T> *base, int32_t i)
-    {
-        return (ptr)(size_t)lds_address(base + i);
-    }
-};
-template <typename T> struct GlobalSrc {
-    typedef const typename RecVec<T>::type *ptr;
-    __device__ __forceinline__ static ptr at(const Rec<T> *base, int32_t i)
-    {
-        return reinterpret_cast<ptr>(base + i);
-    }
-};
-
 // v_min / v_max without the quieting of signalling NaNs that fmin/fmax
 // would add (the data contract excludes NaN).
 __device__ __forceinline__ double min_raw(double a, double b)
@@ -176,31 +160,112 @@ __device__ __forceinline__ float max_raw(float a, float b)
     return r;
 }
 
-template <typename T, typename Src>
+// Record addresses of a chain's two pieces. Global mode keeps both
+// pointers. LDS mode keeps one 32-bit address and a sum instead: every step
+// loads exactly one record, the successor of the piece that ends, so
+// addr(P) + addr(Q) grows by one record per step. With S that sum at the
+// start of a block of kStepBlock steps and q = addr(P) - k * rec at step k
+// of the block (rec = record bytes), addr(Q) - k * rec = |S - q| - k * rec
+// (one v_sad_u32); the ending piece's address minus k * rec is a select of
+// the two and becomes the next q, and its successor is read at that plus
+// (k + 1) * rec, a constant offset of the LDS read. Two VALU instructions
+// per step instead of three.
+template <typename T> struct LdsWalk {
+    typedef typename RecVec<T>::type V;
+    typedef const __attribute__((address_space(3))) V *ptr;
+    static constexpr uint32_t kRec = sizeof(Rec<T>);
+    uint32_t q, S;
+
+    __device__ __forceinline__ void set(const Rec<T> *base, int32_t iP, int32_t iQ)
+    {
+        q = lds_address(base + iP);
+        S = q + lds_address(base + iQ);
+    }
+    __device__ __forceinline__ static V at(const Rec<T> *base, int32_t i)
+    {
+        return *(ptr)(size_t)lds_address(base + i);
+    }
+    template <int K>
+    __device__ __forceinline__ V advance(bool p_ends)
+    {
+        uint32_t b;
+        asm("v_sad_u32 %0, %1, %2, %3"
+            : "=v"(b)
+            : "v"(S), "v"(q), "s"((uint32_t)(0u - K * kRec)));
+        const uint32_t m = p_ends ? q : b;
+        q = m;
+        return *(ptr)(size_t)(m + (uint32_t)(K + 1) * kRec);
+    }
+    __device__ __forceinline__ void end_block()
+    {
+        q += kStepBlock * kRec;
+        S += kStepBlock * kRec;
+    }
+};
+template <typename T> struct GlobalWalk {
+    typedef typename RecVec<T>::type V;
+    const V *pP, *pQ;
+
+    __device__ __forceinline__ void set(const Rec<T> *base, int32_t iP, int32_t iQ)
+    {
+        pP = reinterpret_cast<const V *>(base + iP);
+        pQ = reinterpret_cast<const V *>(base + iQ);
+    }
+    __device__ __forceinline__ static V at(const Rec<T> *base, int32_t i)
+    {
+        return *reinterpret_cast<const V *>(base + i);
+    }
+    template <int K>
+    __device__ __forceinline__ V advance(bool p_ends)
+    {
+        const V *n = p_ends ? pP : pQ;
+        pQ = p_ends ? pQ : pP;
+        pP = n + 1;
+        return *pP;
+    }
+    __device__ __forceinline__ void end_block() {}
+};
+
+template <typename T, typename Walk>
 struct Chain {
-    typename RecVec<T>::type P, Q;
-    typename Src::ptr pP, pQ;
+    typename RecVec<T>::type P;  // piece loaded last: (end time, value)
+    T tQ, vQ;                    // the other piece
+    Walk w;                      // record addresses
     T x;          // start of the current cell
     double acc;   // sum over the current pair (FP64 for both types)
     int32_t left; // steps left in the current pair (rows < 2^30 per PCF)
     int32_t r, c;            // current pair (row, column) of the tile
     int32_t rb, rn, cb, cn;  // record base and rows of its two PCFs
+
+    __device__ __forceinline__ void load(const Rec<T> *base, int32_t iP, int32_t iQ)
+    {
+        w.set(base, iP, iQ);
+        P = Walk::at(base, iP);
+        const typename RecVec<T>::type Q = Walk::at(base, iQ);
+        tQ = Q.x;
+        vQ = Q.y;
+    }
 };
 
-template <typename T, int HK, typename Src>
-__device__ __forceinline__ void chain_step(Chain<T, Src> &ch, T &part, T p)
+template <int K, typename T, int HK, typename Walk>
+__device__ __forceinline__ void chain_step(Chain<T, Walk> &ch, T &part, T p)
 {
-    const T tP = ch.P.x, tQ = ch.Q.x;
+    const T tP = ch.P.x, tQ = ch.tQ;
     const T y = min_raw(tP, tQ);
-    part = fma(hval<T, HK>(ch.P.y, ch.Q.y, p), y - ch.x, part);
+    part = fma(hval<T, HK>(ch.P.y, ch.vQ, p), y - ch.x, part);
     ch.x = y;
     const bool c = tP <= tQ;
-    const typename Src::ptr pN = c ? ch.pP : ch.pQ;
-    ch.pQ = c ? ch.pQ : ch.pP;
-    ch.Q.x = max_raw(tP, tQ);
-    ch.Q.y = c ? ch.Q.y : ch.P.y;
-    ch.pP = pN + 1;
-    ch.P = *ch.pP;
+    ch.vQ = c ? ch.vQ : ch.P.y;
+    ch.tQ = max_raw(tP, tQ);
+    ch.P = ch.w.template advance<K>(c);
+}
+
+template <typename T, int HK, typename Walk, int... Ks>
+__device__ __forceinline__ void chain_block(Chain<T, Walk> &ch, T &part, T p,
+                                            std::integer_sequence<int, Ks...>)
+{
+    (chain_step<Ks, T, HK>(ch, part, p), ...);
+    ch.w.end_block();
 }
 
 // Padded merge steps of a pair of PCFs with na and nb rows (as in the scan;
@@ -211,8 +276,8 @@ __device__ __forceinline__ int32_t pair_steps(int32_t na, int32_t nb)
 }
 
 // Starting state at step d of pair k (merge-path split).
-template <typename T, typename Src, typename Shared>
-__device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
+template <typename T, typename Walk, typename Shared>
+__device__ __forceinline__ void chain_begin(Chain<T, Walk> &ch, const Shared &sh,
                                             const Rec<T> *base, int32_t k,
                                             int64_t d, int32_t C)
 {
@@ -226,10 +291,7 @@ __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
     int32_t i0, j0;
     T x;
     pair_start<T>(base, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
-    ch.pP = Src::at(base, i0);
-    ch.pQ = Src::at(base, j0);
-    ch.P = *ch.pP;
-    ch.Q = *ch.pQ;
+    ch.load(base, i0, j0);
     ch.x = x;
     ch.acc = 0.0;
     ch.left = pair_steps(ch.rn, ch.cn) - (int32_t)d;
@@ -241,8 +303,8 @@ __device__ __forceinline__ void chain_begin(Chain<T, Src> &ch, const Shared &sh,
 // padding; only the next PCF's row count is read. On diagonal tiles a row's
 // live pairs start at column r + 1 (r with `gram`). The caller has steps
 // left, so a next pair with steps exists and the loop ends there.
-template <typename T, typename Src, typename Shared>
-__device__ __forceinline__ void chain_next_pair(Chain<T, Src> &ch, const Shared &sh,
+template <typename T, typename Walk, typename Shared>
+__device__ __forceinline__ void chain_next_pair(Chain<T, Walk> &ch, const Shared &sh,
                                                 const Rec<T> *base, int32_t C,
                                                 bool diag, int gram)
 {
@@ -269,10 +331,7 @@ __device__ __forceinline__ void chain_next_pair(Chain<T, Src> &ch, const Shared 
     ch.rn = rn;
     ch.cb = cb;
     ch.cn = cn;
-    ch.pP = Src::at(base, rb);
-    ch.pQ = Src::at(base, cb);
-    ch.P = *ch.pP;
-    ch.Q = *ch.pQ;
+    ch.load(base, rb, cb);
     ch.x = T(0);
     ch.acc = 0.0;
     ch.left = pair_steps(rn, cn);
@@ -281,14 +340,15 @@ __device__ __forceinline__ void chain_next_pair(Chain<T, Src> &ch, const Shared 
 // This lane's share of the tile: nblk blocks of kStepBlock steps (pair
 // boundaries fall between blocks), starting at step d0 of pair k; its
 // partial sum of pair k' goes to sh.part[k' + vl].
-template <typename T, int HK, typename Src, typename Shared>
+template <typename T, int HK, typename Walk, typename Shared>
 __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
                                            int64_t d0, int32_t nblk, int32_t k,
                                            int32_t vl, int32_t C, bool diag,
-                                           int gram, T p)
+                                           int gram, T p, PhaseClock &pc)
 {
-    Chain<T, Src> ch;
+    Chain<T, Walk> ch;
     chain_begin(ch, sh, base, k, d0, C);
+    pc.mark(kPhaseStart);
     for (int32_t blk = nblk; blk > 0; --blk) {
         if (ch.left == 0) {
             // next pair (a rare, divergent branch)
@@ -296,9 +356,7 @@ __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
             chain_next_pair(ch, sh, base, C, diag, gram);
         }
         T part = T(0);
-#pragma unroll
-        for (int u = 0; u < kStepBlock; ++u)
-            chain_step<T, HK>(ch, part, p);
+        chain_block<T, HK>(ch, part, p, std::make_integer_sequence<int, kStepBlock>());
         ch.acc += (double)part;
         ch.left -= kStepBlock;
     }
@@ -320,8 +378,10 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     const T p = (T)args.p;
     T *out = reinterpret_cast<T *>(args.out);
 
+    PhaseClock pc;
     TileLoop loop;
     loop.start<T, false>(sh, ws, offsets, lrec, grec);
+    pc.mark(-1);
     while (loop.live(sh, ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
@@ -329,6 +389,8 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         const int32_t C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = pw_at(sh, pw64, npairs);
+        pc.mark(kPhaseScan);
+        pc.tile(total);
 
         loop.take_next(ws);
         // this lane's share of the tile's steps
@@ -339,60 +401,87 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
             const int64_t d0 = s0 - pw_at(sh, pw64, k0);
             const int32_t nblk = (int32_t)((e0 - s0) / kStepBlock);
             if (gmode)
-                lane_chain<T, HK, GlobalSrc<T>>(sh, grec, d0, nblk, k0, tid, C,
-                                                diag, args.gram, p);
+                lane_chain<T, HK, GlobalWalk<T>>(sh, grec, d0, nblk, k0, tid, C,
+                                                 diag, args.gram, p, pc);
             else
-                lane_chain<T, HK, LdsSrc<T>>(sh, lrec, d0, nblk, k0, tid, C,
-                                             diag, args.gram, p);
+                lane_chain<T, HK, LdsWalk<T>>(sh, lrec, d0, nblk, k0, tid, C,
+                                              diag, args.gram, p, pc);
+        } else {
+            pc.mark(kPhaseStart);
         }
-        sync_lds();
-        loop.decode_next(sh, ws, offsets);
-        // the next tile's staging loads fly while this tile is finished
-        // (finishing reads neither records nor block metadata)
+        pc.mark(kPhaseMerge);
+        // the next tile's staging loads, issued as soon as this wave's merge
+        // work is done (they only fill registers; the records are stored to
+        // LDS after the barrier and the finishing reads)
         const bool has_next = loop.has_next(sh, ws);
         StageRegs<T, false> next;
         if (has_next)
             stage_load<T, false>(next, sh.desc[loop.nxt()], grec, offsets, lrec);
+        sync_lds();
+        pc.mark(kPhaseMergeWait);
+        loop.decode_next(sh, ws, offsets);
+        pc.mark(kPhaseStageIssue);
 
-        // finish: unbounded-tail rule, root; write (i, j) row-major
-        for (int k = tid; k < npairs; k += kThreads) {
+        // finish: unbounded-tail rule, root. A tile has at most kThreads
+        // pairs, so a thread finishes at most one; its results are stored
+        // after the staging below, so that the staging's wait for its loads
+        // does not also wait for these stores.
+        static_assert(kMaxPairs <= kThreads, "one pair per thread when finishing");
+        bool wr = false, wr_mirror = false;
+        T res = T(0);
+        int64_t at0 = 0, at1 = 0;
+        if (tid < npairs) {
+            const int k = tid;
             const int r = div_by_c(k, D.cmag), c = k - r * C;
-            if (diag && r > c)
-                continue;
-            // the lanes holding the pair's first and last steps (none for a
-            // pair without steps)
-            const int64_t b0 = pw_at(sh, pw64, k), b1 = pw_at(sh, pw64, k + 1);
-            int32_t l = 0, l1 = -1;
-            if (b1 > b0) {
-                l = lane_of(sh, b0);
-                l1 = lane_of(sh, b1 - 1);
+            if (!(diag && r > c)) {
+                // the lanes holding the pair's first and last steps (none for
+                // a pair without steps)
+                const int64_t b0 = pw_at(sh, pw64, k), b1 = pw_at(sh, pw64, k + 1);
+                int32_t l = 0, l1 = -1;
+                if (b1 > b0) {
+                    l = lane_of(sh, b0);
+                    l1 = lane_of(sh, b1 - 1);
+                }
+                const T lr = (T)sh.rlast[r], lc = (T)sh.clast[c];
+                // the pair's partial sums in lane order, loads batched
+                double val = 0.0;
+                for (; l + 3 <= l1; l += 4) {
+                    const double q0 = sh.part[k + l], q1 = sh.part[k + l + 1];
+                    const double q2 = sh.part[k + l + 2], q3 = sh.part[k + l + 3];
+                    val = (((val + q0) + q1) + q2) + q3;
+                }
+                for (; l <= l1; ++l)
+                    val += sh.part[k + l];
+                const T ht = hval<T, HK>(lr, lc, p);
+                if (ht != T(0))
+                    val = ht > T(0) ? INFINITY : -INFINITY;
+                if constexpr (RT == kRootSqrt)
+                    val = sqrt(val);
+                else if constexpr (RT == kRootPow)
+                    val = pow(val, args.inv_p);
+                const int64_t i = D.r_lo + r, j = D.c_lo + c;
+                res = (T)val;
+                wr = true;
+                at0 = D.obase + (i - D.row0) * D.ldo + (j - D.col0);
+                wr_mirror = D.mirror && !(diag && r == c);
+                at1 = D.obase + (j - D.row0) * D.ldo + (i - D.col0);
             }
-            const T lr = (T)sh.rlast[r], lc = (T)sh.clast[c];
-            // the pair's partial sums in lane order, loads batched
-            double val = 0.0;
-            for (; l + 3 <= l1; l += 4) {
-                const double q0 = sh.part[k + l], q1 = sh.part[k + l + 1];
-                const double q2 = sh.part[k + l + 2], q3 = sh.part[k + l + 3];
-                val = (((val + q0) + q1) + q2) + q3;
-            }
-            for (; l <= l1; ++l)
-                val += sh.part[k + l];
-            const T ht = hval<T, HK>(lr, lc, p);
-            if (ht != T(0))
-                val = ht > T(0) ? INFINITY : -INFINITY;
-            if constexpr (RT == kRootSqrt)
-                val = sqrt(val);
-            else if constexpr (RT == kRootPow)
-                val = pow(val, args.inv_p);
-            const int64_t i = D.r_lo + r, j = D.c_lo + c;
-            out[D.obase + (i - D.row0) * D.ldo + (j - D.col0)] = (T)val;
-            if (D.mirror && !(diag && r == c))
-                out[D.obase + (j - D.row0) * D.ldo + (i - D.col0)] = (T)val;
         }
+        pc.mark(kPhaseFinish);
         if (has_next)
             stage_store<T, false>(sh, next, sh.desc[loop.nxt()], lrec);
+        pc.mark(kPhaseStageStore);
+        // (i, j) and, mirrored, (j, i); nothing waits for these stores until
+        // the next tile's staging
+        if (wr) {
+            out[at0] = res;
+            if (wr_mirror)
+                out[at1] = res;
+        }
         loop.advance();
+        pc.mark(kPhaseAdvance);
     }
+    pc.flush(tid == 0 ? 0 : (tid == kQueueLane ? 1 : -1));
 }
 
 // ---------------------------------------------------------------------------
@@ -545,3 +634,20 @@ template hipError_t launch_validate<double>(const int64_t *, int64_t,
 
 }  // namespace pcf
 
+#ifdef PCF_PHASE_TIMING
+// Timing builds only: copies out (and with `reset` clears) the per-phase
+// cycle sums of the tile kernel (see PhaseClock).
+extern "C" int pcf_debug_phase(unsigned long long *host, int reset)
+{
+    if (hipMemcpyFromSymbol(host, HIP_SYMBOL(pcf::g_phase_cycles),
+                            sizeof(pcf::g_phase_cycles)) != hipSuccess)
+        return -1;
+    if (reset) {
+        static const unsigned long long zero[sizeof(pcf::g_phase_cycles) / 8] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(pcf::g_phase_cycles), zero, sizeof(zero)) !=
+            hipSuccess)
+            return -2;
+    }
+    return 0;
+}
+#endif

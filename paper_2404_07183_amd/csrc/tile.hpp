@@ -9,6 +9,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "common.hpp"
 #include "launch.hpp"
 #include "pow64.hpp"
@@ -74,6 +76,52 @@ __device__ __forceinline__ T hval(T a, T b, T p)
         return pow_any(fabs(a - b), p);
     }
 }
+
+// ---------------------------------------------------------------------------
+// Per-phase cycle counters of the tile loop, compiled in only with
+// -DPCF_PHASE_TIMING (a measurement build; the library's own build has empty
+// inline members). The shader-clock counter is read at each phase boundary;
+// the first thread of wave 0 and the queue lane add their sums to
+// g_phase_cycles at the end (slots 16 * who + phase, tiles at + 8, steps at
+// + 9).
+enum Phase : int {
+    kPhaseScan = 0, kPhaseStart = 1, kPhaseMerge = 2, kPhaseMergeWait = 3,
+    kPhaseStageIssue = 4, kPhaseFinish = 5, kPhaseStageStore = 6, kPhaseAdvance = 7
+};
+#ifdef PCF_PHASE_TIMING
+__device__ unsigned long long g_phase_cycles[32];
+struct PhaseClock {
+    unsigned long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long last = 0, tiles = 0, steps = 0;
+    __device__ __forceinline__ void mark(int q)
+    {
+        const unsigned long long now = __builtin_readcyclecounter();
+        if (q >= 0)
+            acc[q] += now - last;
+        last = now;
+    }
+    __device__ __forceinline__ void tile(int64_t s)
+    {
+        ++tiles;
+        steps += (unsigned long long)s;
+    }
+    __device__ __forceinline__ void flush(int who)
+    {
+        if (who < 0)
+            return;
+        for (int q = 0; q < 8; ++q)
+            atomicAdd(&g_phase_cycles[16 * who + q], acc[q]);
+        atomicAdd(&g_phase_cycles[16 * who + 8], tiles);
+        atomicAdd(&g_phase_cycles[16 * who + 9], steps);
+    }
+};
+#else
+struct PhaseClock {
+    __device__ __forceinline__ void mark(int) {}
+    __device__ __forceinline__ void tile(int64_t) {}
+    __device__ __forceinline__ void flush(int) {}
+};
+#endif
 
 // ---------------------------------------------------------------------------
 // Workspace access
