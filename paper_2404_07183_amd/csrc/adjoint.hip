@@ -334,12 +334,13 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     const int tid = threadIdx.x;
     const double p = args.p;
 
+    PhaseClock pc;  // (cycle counters only in timing builds)
     TileLoop loop;
     loop.start<double, true>(sh, args.ws, offsets, lrec, grec);
     while (loop.live(sh, args.ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
-        tile_scan<double>(sh, D, args.gram, gmode ? grec : lrec, pw64);
+        tile_scan<double>(sh, D, args.gram, gmode ? grec : lrec, pw64, pc);
         const int32_t R = D.R, C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = pw_at(sh, pw64, npairs);

@@ -234,7 +234,7 @@ struct Chain {
     T x;          // start of the current cell
     double acc;   // sum over the current pair (FP64 for both types)
     int32_t left; // steps left in the current pair (rows < 2^30 per PCF)
-    int32_t r, c;            // current pair (row, column) of the tile
+    int32_t k, r, c;         // current pair: index r * C + c, row, column
     int32_t rb, rn, cb, cn;  // record base and rows of its two PCFs
 
     __device__ __forceinline__ void load(const Rec<T> *base, int32_t iP, int32_t iQ)
@@ -282,6 +282,7 @@ __device__ __forceinline__ void chain_begin(Chain<T, Walk> &ch, const Shared &sh
                                             int64_t d, int32_t C)
 {
     const int r = div_by_c(k, sh.cmag), c = k - r * C;
+    ch.k = k;
     ch.r = r;
     ch.c = c;
     ch.rb = sh.rb[r];
@@ -300,38 +301,54 @@ __device__ __forceinline__ void chain_begin(Chain<T, Walk> &ch, const Shared &sh
 // Moves a chain that finished its pair to the next pair with steps, in the
 // tile's row-major pair order. Blocks of consecutive PCFs are contiguous in
 // the record arrays, so the next PCF's records start right after this one's
-// padding; only the next PCF's row count is read. On diagonal tiles a row's
-// live pairs start at column r + 1 (r with `gram`). The caller has steps
-// left, so a next pair with steps exists and the loop ends there.
+// padding. In the common case (next column, same row) the new pair's first
+// two records are read together with the new column's row count (one LDS
+// round trip); a row change reads the new row's metadata first. On diagonal
+// tiles a row's live pairs start at column r + 1 (r with `gram`). A pair
+// without steps (two one-row PCFs) is skipped; the caller has steps left,
+// so a next pair with steps exists.
 template <typename T, typename Walk, typename Shared>
 __device__ __forceinline__ void chain_next_pair(Chain<T, Walk> &ch, const Shared &sh,
                                                 const Rec<T> *base, int32_t C,
                                                 bool diag, int gram)
 {
-    int32_t r = ch.r, c = ch.c, rb = ch.rb, rn = ch.rn, cb = ch.cb, cn = ch.cn;
-    do {
-        if (c + 1 < C) {
-            cb += cn + kPad;
-            ++c;
-            cn = sh.cn[c];
-        } else {
-            // next row: a row holding a later pair with steps has a live
-            // first column below C
+    int32_t k = ch.k + 1, r = ch.r, c = ch.c + 1, rb = ch.rb, rn = ch.rn;
+    int32_t cb = ch.cb + ch.cn + kPad;
+    if (c >= C) {
+        // next row (k was (r - 1) * C + C = r * C)
+        rb += rn + kPad;
+        ++r;
+        rn = sh.rn[r];
+        c = diag ? (gram ? r : r + 1) : 0;
+        k += c;
+        cb = sh.cb[c];
+    }
+    // the new column's row count and the pair's first records, together
+    int32_t cn = sh.cn[c];
+    ch.load(base, rb, cb);
+    while (pair_steps(rn, cn) == 0) {
+        // a pair without steps (two one-row PCFs): skip it (rare)
+        ++k;
+        ++c;
+        cb += cn + kPad;
+        if (c >= C) {
             rb += rn + kPad;
             ++r;
             rn = sh.rn[r];
             c = diag ? (gram ? r : r + 1) : 0;
+            k += c;
             cb = sh.cb[c];
-            cn = sh.cn[c];
         }
-    } while (pair_steps(rn, cn) == 0);
+        cn = sh.cn[c];
+        ch.load(base, rb, cb);
+    }
+    ch.k = k;
     ch.r = r;
     ch.c = c;
     ch.rb = rb;
     ch.rn = rn;
     ch.cb = cb;
     ch.cn = cn;
-    ch.load(base, rb, cb);
     ch.x = T(0);
     ch.acc = 0.0;
     ch.left = pair_steps(rn, cn);
@@ -350,17 +367,20 @@ __device__ __forceinline__ void lane_chain(Shared &sh, const Rec<T> *base,
     chain_begin(ch, sh, base, k, d0, C);
     pc.mark(kPhaseStart);
     for (int32_t blk = nblk; blk > 0; --blk) {
+        const unsigned long long t0 = pc.now();
+        const bool sw = __builtin_amdgcn_ballot_w64(ch.left == 0) != 0;
         if (ch.left == 0) {
             // next pair (a rare, divergent branch)
-            sh.part[ch.r * C + ch.c + vl] = ch.acc;
+            sh.part[ch.k + vl] = ch.acc;
             chain_next_pair(ch, sh, base, C, diag, gram);
         }
+        pc.sw_add(t0, sw);
         T part = T(0);
         chain_block<T, HK>(ch, part, p, std::make_integer_sequence<int, kStepBlock>());
         ch.acc += (double)part;
         ch.left -= kStepBlock;
     }
-    sh.part[ch.r * C + ch.c + vl] = ch.acc;
+    sh.part[ch.k + vl] = ch.acc;
 }
 
 template <typename T, int HK, int RT>
@@ -385,26 +405,27 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
     while (loop.live(sh, ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
-        tile_scan<T>(sh, D, args.gram, gmode ? grec : lrec, pw64);
+        tile_scan<T>(sh, D, args.gram, gmode ? grec : lrec, pw64, pc);
         const int32_t C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = pw_at(sh, pw64, npairs);
+        const int32_t run = tid;  // the run of steps this lane executes
         pc.mark(kPhaseScan);
         pc.tile(total);
 
         loop.take_next(ws);
         // this lane's share of the tile's steps
         int64_t s0, e0;
-        lane_steps(sh, tid, total, s0, e0);
-        const int32_t k0 = s0 < e0 ? sh.pairof[tid] : 0;
+        lane_steps(sh, run, total, s0, e0);
+        const int32_t k0 = s0 < e0 ? sh.pairof[run] : 0;
         if (s0 < e0) {
             const int64_t d0 = s0 - pw_at(sh, pw64, k0);
             const int32_t nblk = (int32_t)((e0 - s0) / kStepBlock);
             if (gmode)
-                lane_chain<T, HK, GlobalWalk<T>>(sh, grec, d0, nblk, k0, tid, C,
+                lane_chain<T, HK, GlobalWalk<T>>(sh, grec, d0, nblk, k0, run, C,
                                                  diag, args.gram, p, pc);
             else
-                lane_chain<T, HK, LdsWalk<T>>(sh, lrec, d0, nblk, k0, tid, C,
+                lane_chain<T, HK, LdsWalk<T>>(sh, lrec, d0, nblk, k0, run, C,
                                               diag, args.gram, p, pc);
         } else {
             pc.mark(kPhaseStart);
@@ -481,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         loop.advance();
         pc.mark(kPhaseAdvance);
     }
-    pc.flush(tid == 0 ? 0 : (tid == kQueueLane ? 1 : -1));
+    pc.flush((tid & 63) == 0 ? tid >> 6 : -1);
 }
 
 // ---------------------------------------------------------------------------

@@ -81,18 +81,31 @@ __device__ __forceinline__ T hval(T a, T b, T p)
 // Per-phase cycle counters of the tile loop, compiled in only with
 // -DPCF_PHASE_TIMING (a measurement build; the library's own build has empty
 // inline members). The shader-clock counter is read at each phase boundary;
-// the first thread of wave 0 and the queue lane add their sums to
-// g_phase_cycles at the end (slots 16 * who + phase, tiles at + 8, steps at
-// + 9).
+// the first lane of every wave adds its sums to g_phase_cycles at the end
+// (slots 16 * wave + phase, tiles at + 8, steps at + 9, pair-switch cycles
+// and count at + 10 and + 11; wave 15 holds the queue lane).
 enum Phase : int {
     kPhaseScan = 0, kPhaseStart = 1, kPhaseMerge = 2, kPhaseMergeWait = 3,
     kPhaseStageIssue = 4, kPhaseFinish = 5, kPhaseStageStore = 6, kPhaseAdvance = 7
 };
 #ifdef PCF_PHASE_TIMING
-__device__ unsigned long long g_phase_cycles[32];
+__device__ unsigned long long g_phase_cycles[16 * 16];
 struct PhaseClock {
     unsigned long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    unsigned long long last = 0, tiles = 0, steps = 0;
+    unsigned long long last = 0, tiles = 0, steps = 0, sw = 0, swn = 0;
+    unsigned long long subacc[3] = {0, 0, 0};
+    // time from the last phase boundary to sub-phase point q of the scan
+    __device__ __forceinline__ void sub(int q) { subacc[q] += now() - last; }
+    __device__ __forceinline__ unsigned long long now() const
+    {
+        return __builtin_readcyclecounter();
+    }
+    // time spent in a wave's pair-switch branch, and how often it is taken
+    __device__ __forceinline__ void sw_add(unsigned long long t0, bool taken)
+    {
+        sw += now() - t0;
+        swn += taken ? 1 : 0;
+    }
     __device__ __forceinline__ void mark(int q)
     {
         const unsigned long long now = __builtin_readcyclecounter();
@@ -113,10 +126,17 @@ struct PhaseClock {
             atomicAdd(&g_phase_cycles[16 * who + q], acc[q]);
         atomicAdd(&g_phase_cycles[16 * who + 8], tiles);
         atomicAdd(&g_phase_cycles[16 * who + 9], steps);
+        atomicAdd(&g_phase_cycles[16 * who + 10], sw);
+        atomicAdd(&g_phase_cycles[16 * who + 11], swn);
+        for (int q = 0; q < 3; ++q)
+            atomicAdd(&g_phase_cycles[16 * who + 12 + q], subacc[q]);
     }
 };
 #else
 struct PhaseClock {
+    __device__ __forceinline__ void sub(int) {}
+    __device__ __forceinline__ unsigned long long now() const { return 0; }
+    __device__ __forceinline__ void sw_add(unsigned long long, bool) {}
     __device__ __forceinline__ void mark(int) {}
     __device__ __forceinline__ void tile(int64_t) {}
     __device__ __forceinline__ void flush(int) {}
@@ -553,7 +573,7 @@ constexpr int kGroups = kThreads / 256;
 constexpr int kGroupLanes = 256;
 // Weights measured on MI355X (per-wave completion times of equal runs):
 // FP64 records, FP32 records.
-constexpr int64_t kGroupWeights[2][4] = {{64, 60, 54, 40}, {64, 60, 54, 46}};
+constexpr int64_t kGroupWeights[2][4] = {{66, 61, 53, 38}, {64, 60, 55, 45}};
 template <typename T>
 __device__ __forceinline__ int64_t group_weight(int g)
 {
@@ -685,7 +705,8 @@ static_assert((int64_t)kMaxBlock * (kLdsRecordBytes / 8) + 8 * (int64_t)kMaxPair
 // Needs the staged tile; ends with a barrier.
 template <typename T>
 __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
-                                          int gram, const Rec<T> *src, int64_t *pw64)
+                                          int gram, const Rec<T> *src, int64_t *pw64,
+                                          PhaseClock &pc)
 {
     const int tid = threadIdx.x;
     if (tid < d.R)
@@ -714,8 +735,10 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
         int32_t t32;
         const int32_t excl =
             block_scan<int32_t>((int32_t)wp, reinterpret_cast<int32_t *>(sh.wsum), &t32);
+        pc.sub(0);
         total = t32;
         sp.make_small(t32);
+        pc.sub(1);
         if (tid < npairs) {
             sh.pw[tid] = excl;
             // lanes whose first step lies in [excl, excl + wp)
@@ -751,6 +774,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
             }
         }
     }
+    pc.sub(2);
     if (tid == 0) {
         const bool wide = !(bound < ((int64_t)1 << 30));
         if (wide)
