@@ -16,8 +16,10 @@ this host's cores. Unless --no-extras, it also carries the extra lines:
 batched (512 independent matrices), fwd_bwd (forward + adjoint), cross
 (10,000 x 20,000 cross-set matrix), single (L2 norms) and reduce (mean and
 std by reduction trees), bounded_weighted (L1 over a range with a time
-weight). --only NAME[,NAME] runs extra lines alone (also general_p: d_p^p for
-p = 3, 3.5, 2.7 in both precisions);
+weight), small (per-call latency of the 200-PCF matrix). Every line carries
+its parity against the oracle as max, 99th percentile and median of the
+error over the entry's scale. --only NAME[,NAME] runs extra lines alone (also
+general_p: d_p^p for p = 3, 3.5, 2.7 in both precisions);
 --config strip the 62,500 x 500,000 strip of the 500,000-PCF set.
 """
 from __future__ import annotations
@@ -35,6 +37,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 OPS_PER_STEP = {"l1": 4, "l2sq": 5, "l2": 5, "gram": 4}  # algorithmic FP64 ops
+# algorithmic FP64 ops of one adjoint step: compare, width, the two value
+# derivatives accumulated (d_2^2: a difference, two scaled FMAs; Gram: two
+# FMAs), the time derivative of the ending breakpoint (d_2^2: two squared
+# differences, their difference; Gram: a difference and a product) weighted
+# and accumulated
+ADJ_OPS = {"l2sq": 12, "gram": 8}
 
 
 # the sources the tile kernel, its launch arguments and its plan are built from
@@ -72,6 +80,26 @@ def measured_traffic(key):
     return entry.get("bytes_per_launch")
 
 
+def err_stats(err):
+    """max, 99th percentile and median of per-entry errors over their scale."""
+    err = np.asarray(err, dtype=np.float64)
+    return {"max_error_over_scale": float(err.max()),
+            "p99_error_over_scale": float(np.percentile(err, 99)),
+            "median_error_over_scale": float(np.median(err))}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def merge_steps_full(o):
     """sum over pairs i<j of (n_i - 1) + (n_j - 1): finite cells without ties."""
     n = np.diff(o).astype(np.float64)
@@ -91,11 +119,13 @@ def cpu_baseline(o, t, v, kind_name, seconds=12.0, seed=123):
 
     kind, p = {"l1": (oracle.LP, 1.0), "l2": (oracle.LP, 2.0), "l2sq": (oracle.LP_POW, 2.0),
                "gram": (oracle.GRAM, 0.0)}[kind_name]
+    # host threads: the cores this process may run on, at most 16 (the host
+    # share that comes with one GPU on the machines this runs on)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
     N = len(o) - 1
-    # calibrate on one thread
-    I, J = workloads.random_pairs(N, 400, seed=seed)
+    # one thread: the single-thread rate, also used to size the sample
+    I, J = workloads.random_pairs(N, 4000, seed=seed)
     t0 = time.perf_counter()
     oracle.entries(kind, p, o, t, v, I, J)
     per_pair = (time.perf_counter() - t0) / len(I)
@@ -109,7 +139,7 @@ def cpu_baseline(o, t, v, kind_name, seconds=12.0, seed=123):
     dt = time.perf_counter() - t0
     ref = np.concatenate([g[0] for g in got])
     ab = np.concatenate([g[1] for g in got])
-    return len(I) / dt, len(I), cores, dt, (I, J, ref, ab)
+    return len(I) / dt, len(I), cores, dt, (I, J, ref, ab), 1.0 / per_pair
 
 
 def run_plain(args):
@@ -190,11 +220,14 @@ def run_plain(args):
         },
     }
     if not args.no_cpu:
-        pps, npairs, cores, dt, (I, J, ref, ab) = cpu_baseline(o, t, v, args.kind)
+        pps, npairs, cores, dt, (I, J, ref, ab), pps1 = cpu_baseline(o, t, v, args.kind)
         res["cpu_baseline"] = {"value": pps, "unit": "pairs/s", "cores": cores,
                                "kind": "oracle",
                                "sample": "%d random pairs of the same workload, %.1f s on %d "
-                                         "host threads" % (npairs, dt, cores)}
+                                         "host threads" % (npairs, dt, cores),
+                               "single_thread_value": pps1,
+                               "single_thread_merge_steps_per_s": pps1 * steps / pairs,
+                               "cpu_model": cpu_model()}
         # the same pairs of the benchmarked matrix against the oracle: error
         # over the scale sum |h|·width (its p-th root for d_p)
         got = out[torch.as_tensor(I, device="cuda:0"),
@@ -202,9 +235,9 @@ def run_plain(args):
         root = {"l1": 1.0, "l2": 2.0, "l2sq": 1.0, "gram": 1.0}[args.kind]
         scale = np.maximum(ab, 1e-300) ** (1.0 / root)
         err = np.abs(got - ref) / scale
-        res["parity"] = {"pairs": int(len(I)), "max_error_over_scale": float(err.max()),
-                         "tolerance": 1e-12 if args.dtype == "f64" else 1e-5,
-                         "reference": "oracle on the cpu_baseline pairs"}
+        res["parity"] = dict(pairs=int(len(I)), **err_stats(err),
+                             tolerance=1e-12 if args.dtype == "f64" else 1e-5,
+                             reference="oracle on the cpu_baseline pairs")
     return res
 
 
@@ -252,6 +285,10 @@ def run_batched(steps, warmup, plain_steps_per_s=None):
     stream.wait_stream(s)
     torch.cuda.synchronize()
     ms_graph = _events_ms(g.replay, steps, stream)
+    # the tile kernel alone (plan reused, records already packed)
+    ms_kernel = _events_ms(lambda: api.pairwise_batched(so, X, api.PCF_LP, 2.0, out=out,
+                                                        workspace=ws, shape=shape, packed=True),
+                           steps, stream)
     pairs = float(np.sum(sizes * (sizes - 1) / 2))
     n = np.diff(o).astype(np.float64)
     msteps = 0.0
@@ -259,13 +296,34 @@ def run_batched(steps, warmup, plain_steps_per_s=None):
         nb = n[so[b]:so[b + 1]]
         msteps += (len(nb) - 1) * np.sum(nb - 1)
     ms = min(ms_eager, ms_graph)
+    # sampled parity: 3,000 random entries over the problems, by pair count
+    import oracle
+    rng = np.random.default_rng(31)
+    npb = sizes * (sizes - 1) // 2
+    bsel = rng.choice(len(sizes), size=3000, p=npb / npb.sum())
+    li = np.array([rng.integers(0, sizes[b]) for b in bsel])
+    lj = np.array([rng.integers(0, sizes[b]) for b in bsel])
+    oo = np.zeros(len(sizes), dtype=np.int64)
+    oo[1:] = np.cumsum(sizes[:-1] ** 2)
+    flat = oo[bsel] + li * sizes[bsel] + lj
+    got = out[torch.as_tensor(flat, device="cuda:0")].cpu().numpy()
+    ref, ab = oracle.entries(oracle.LP, 2.0, o, t, v, so[bsel] + li, so[bsel] + lj,
+                             with_abs=True)
+    err = np.abs(got - ref) / np.maximum(np.sqrt(ab), 1e-300)
+    ops = msteps * OPS_PER_STEP["l2"]
     res = {"workload": "512 independent L2 distance matrices, sizes round(exp(U(ln16,ln2048))), "
                        "counts Geometric(1/200) capped 5000, FP64",
            "problems": int(len(sizes)), "pcfs": int(X.n), "pairs": pairs, "merge_steps": msteps,
            "ms_per_step_eager": ms_eager, "ms_per_step_graph": ms_graph,
            "pairs_per_s": pairs / (ms * 1e-3), "merge_steps_per_s": msteps / (ms * 1e-3),
            "tile_shape": list(shape) if shape else None,
-           "autotune_ms": {str(k): v for k, v in times.items()}}
+           "autotune_ms": {str(k): v for k, v in times.items()},
+           "roofline": {"bound": "alu", "achieved": ops / (ms_kernel * 1e-3) / 1e12,
+                        "peak": PEAK_FP64_LANE_OPS / 1e12, "unit": "TOP/s",
+                        "frac": ops / (ms_kernel * 1e-3) / PEAK_FP64_LANE_OPS,
+                        "kernel": "pairwise_tiles<double,l2>", "kernel_ms": ms_kernel,
+                        "ops_per_step": OPS_PER_STEP["l2"]},
+           "parity": dict(pairs=3000, **err_stats(err), tolerance=1e-12)}
     if plain_steps_per_s:
         res["vs_plain_merge_steps_per_s"] = res["merge_steps_per_s"] / plain_steps_per_s
     return res
@@ -311,10 +369,9 @@ def run_cross(steps, warmup, plain_steps_per_s=None):
            "rows": int(X.n), "cols": int(Y.n), "pairs": pairs, "merge_steps": msteps,
            "ms_per_call": ms, "pairs_per_s": pairs / (ms * 1e-3),
            "merge_steps_per_s": msteps / (ms * 1e-3),
-           "parity": {"pairs": int(len(I)),
-                      "max_error_over_scale": float(np.max(np.abs(got - ref) /
-                                                           np.maximum(ab, 1e-300))),
-                      "tolerance": 1e-12}}
+           "parity": dict(pairs=int(len(I)),
+                          **err_stats(np.abs(got - ref) / np.maximum(ab, 1e-300)),
+                          tolerance=1e-12)}
     if plain_steps_per_s:
         res["vs_plain_merge_steps_per_s"] = res["merge_steps_per_s"] / plain_steps_per_s
     return res
@@ -360,10 +417,9 @@ def run_single(steps, warmup):
                          "peak": 8000.0, "unit": "GB/s",
                          "frac": nbytes / (ms * 1e-3) / 1e9 / 8000.0,
                          "bytes_per_call": nbytes},
-            "parity": {"pcfs": int(X.n),
-                       "max_error_over_scale": float(np.max(np.abs(got - ref) /
-                                                            np.maximum(np.sqrt(ab), 1e-300))),
-                       "tolerance": 1e-12}}
+            "parity": dict(pcfs=int(X.n),
+                           **err_stats(np.abs(got - ref) / np.maximum(np.sqrt(ab), 1e-300)),
+                           tolerance=1e-12)}
 
 
 def run_reduce(steps, warmup):
@@ -406,7 +462,7 @@ def run_reduce(steps, warmup):
                      for i in range(X.n)])
     want = vals.mean(0)
     got = gv[np.searchsorted(gt, x, side="right") - 1]
-    err = float(np.max(np.abs(got - want) / np.maximum(np.abs(vals).mean(0), 1e-300)))
+    err = np.abs(got - want) / np.maximum(np.abs(vals).mean(0), 1e-300)
     res.update({"workload": "mean of N=20000 PCFs (counts U{50..500}) as one group, FP64; "
                             "std of 1000 groups of 20",
                 "pcfs": int(X.n), "rows": P, "tree_levels": levels,
@@ -415,8 +471,7 @@ def run_reduce(steps, warmup):
                              "peak": 8000.0, "unit": "GB/s",
                              "frac": nbytes / (ms * 1e-3) / 1e9 / 8000.0,
                              "bytes_per_call": nbytes},
-                "parity": {"sampled_times": len(x), "max_error_over_scale": err,
-                           "tolerance": 1e-13}})
+                "parity": dict(sampled_times=len(x), **err_stats(err), tolerance=1e-13)})
     return res
 
 
@@ -451,10 +506,8 @@ def run_bounded_weighted(steps, warmup):
     return {"workload": "L1 over [2.5, 40) with weight exp(-0.1 t), N=20000 PCFs (counts "
                         "U{50..500}), FP64; restriction + time warp + full matrix per call",
             "ms_per_call": ms, "pairs_per_s": pairs / (ms * 1e-3),
-            "parity": {"pairs": 256,
-                       "max_error_over_scale": float(np.max(np.abs(got - ref) /
-                                                            np.maximum(ab, 1e-300))),
-                       "tolerance": 1e-12}}
+            "parity": dict(pairs=256, **err_stats(np.abs(got - ref) / np.maximum(ab, 1e-300)),
+                           tolerance=1e-12)}
 
 
 def run_general_p(steps, warmup):
@@ -531,7 +584,98 @@ def run_grad(steps, warmup, plain_steps_per_s=None):
            "merge_steps_per_s_fwd_plus_bwd": 2 * fwd_steps / (ms * 1e-3)}
     if plain_steps_per_s:
         res["vs_plain_merge_steps_per_s"] = res["merge_steps_per_s_fwd_plus_bwd"] / plain_steps_per_s
+    # the adjoint kernels alone (plan reused, records packed; each call also
+    # clears the two gradient arrays): d_2^2 with weights 2W (the upper
+    # triangle's pairs once, each with G_ij + G_ji) and Gram with 2U
+    one_steps = (N - 1) * np.sum(n - 1)          # pairs i < j
+    adj = {}
+    for name, kind, p, G, k_ops, extra in (("l2sq", api.PCF_LP_POW, 2.0, Wt, ADJ_OPS["l2sq"], 0),
+                                           ("gram", api.PCF_GRAM, 0.0, Ut, ADJ_OPS["gram"],
+                                            np.sum(n - 1))):
+        ws = api.Workspace(device="cuda:0")
+        api.pairwise_backward(X, kind, p, G, workspace=ws)
+        k_ms = _events_ms(lambda: api.pairwise_backward(X, kind, p, G, workspace=ws,
+                                                        packed=True), steps, stream)
+        ops = (one_steps + extra) * k_ops
+        adj[name] = {"kernel": "pairwise_adjoint_tiles<%s>" % name, "kernel_ms": k_ms,
+                     "merge_steps": one_steps + extra, "ops_per_step": k_ops,
+                     "achieved": ops / (k_ms * 1e-3) / 1e12,
+                     "frac": ops / (k_ms * 1e-3) / PEAK_FP64_LANE_OPS}
+    tot_ops = sum(a["merge_steps"] * a["ops_per_step"] for a in adj.values())
+    tot_ms = sum(a["kernel_ms"] for a in adj.values())
+    res["roofline"] = {"bound": "alu", "achieved": tot_ops / (tot_ms * 1e-3) / 1e12,
+                       "peak": PEAK_FP64_LANE_OPS / 1e12, "unit": "TOP/s",
+                       "frac": tot_ops / (tot_ms * 1e-3) / PEAK_FP64_LANE_OPS,
+                       "kernel": "pairwise_adjoint_tiles (both matrices)",
+                       "kernel_ms": tot_ms, "per_kernel": adj}
+    if plain_steps_per_s:
+        res["adjoint_vs_plain_merge_steps_per_s"] = (
+            sum(a["merge_steps"] for a in adj.values()) / (tot_ms * 1e-3) / plain_steps_per_s)
+    # parity: the full gradients of four PCFs against the oracle's adjoint
+    # of the same loss (only the pairs that involve each PCF matter to it)
+    import oracle
+    step()
+    torch.cuda.synchronize()
+    gt, gv = tt.grad.cpu().numpy(), vv.grad.cpu().numpy()
+    errs = []
+    for i in (0, 1, 2047, N - 1):
+        Wi = np.zeros_like(W)
+        Ui = np.zeros_like(U)
+        Wi[i, :], Wi[:, i] = W[i, :], W[:, i]
+        Ui[i, :], Ui[:, i] = U[i, :], U[:, i]
+        rt1, rv1 = oracle.backward(oracle.LP_POW, 2.0, o, t, v, Wi)
+        rt2, rv2 = oracle.backward(oracle.GRAM, 0.0, o, t, v, Ui)
+        a, b = o[i], o[i + 1]
+        for g, r in ((gt[a:b], rt1[a:b] + rt2[a:b]), (gv[a:b], rv1[a:b] + rv2[a:b])):
+            errs.append(np.abs(g - r) / max(np.max(np.abs(r)), 1e-300))
+    res["parity"] = dict(pcfs=4, entries=int(sum(len(e) for e in errs)),
+                         **err_stats(np.concatenate(errs)), tolerance=1e-11,
+                         reference="oracle adjoint; error over the largest |gradient| of "
+                                   "each PCF's t or v")
     return res
+
+
+def run_small(steps, warmup):
+    """The 200-PCF L1 matrix (FP64, counts U{10..100}): per-call latency of a
+    whole call (plan, upload, pack, kernel; synchronised after every call),
+    of a call that reuses the plan and the packed records, and the oracle's
+    single-threaded time for the same matrix on this host (the paper finds
+    the CPU ahead at small sizes)."""
+    import torch
+
+    import oracle
+    from paper_2404_07183_amd import api, workloads
+
+    o, t, v = workloads.config_plain_small()
+    X = api.PcfSet(o, t, v, device="cuda:0")
+    out = torch.empty((X.n, X.n), dtype=torch.float64, device="cuda:0")
+    reps = max(20, steps * 5)
+
+    def per_call_us(fn):
+        for _ in range(warmup + 2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+            torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e6
+
+    full = per_call_us(lambda: api.pdist(X, 1.0, out=out))
+    ws = api.Workspace(device="cuda:0")
+    api.pdist(X, 1.0, out=out, workspace=ws)
+    reuse = per_call_us(lambda: api.pdist(X, 1.0, out=out, workspace=ws, packed=True))
+    t0 = time.perf_counter()
+    ref = oracle.matrix(oracle.LP, 1.0, o, t, v)
+    cpu_us = (time.perf_counter() - t0) * 1e6
+    got = out.cpu().numpy()
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    pairs = X.n * (X.n - 1) / 2
+    return {"workload": "L1 matrix of N=200 PCFs, counts U{10..100}, FP64",
+            "pairs": pairs, "us_per_call_full": full, "us_per_call_plan_reused": reuse,
+            "oracle_single_thread_us_full_matrix": cpu_us,
+            "pairs_per_s_full": pairs / (full * 1e-6),
+            "parity": dict(entries=int(got.size), **err_stats(err[ref > 0]), tolerance=1e-12)}
 
 
 def run_strip(args):
@@ -632,7 +776,7 @@ def main():
     ap.add_argument("--only", default=None,
                     help="comma-separated extra lines to run alone, without the headline "
                          "(batched, fwd_bwd, cross, single, reduce, bounded_weighted, "
-                         "general_p)")
+                         "general_p, small)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -640,6 +784,7 @@ def main():
         sys.exit(2)
     if args.only:
         runs = {"batched": lambda k, w: run_batched(k, w), "fwd_bwd": lambda k, w: run_grad(k, w),
+                "small": run_small,
                 "cross": lambda k, w: run_cross(k, w), "single": run_single,
                 "reduce": run_reduce, "bounded_weighted": run_bounded_weighted,
                 "general_p": run_general_p}
@@ -665,6 +810,7 @@ def main():
         res["single"] = run_single(max(2, args.steps // 2), 1)
         res["reduce"] = run_reduce(max(2, args.steps // 2), 1)
         res["bounded_weighted"] = run_bounded_weighted(max(2, args.steps // 2), 1)
+        res["small"] = run_small(max(2, args.steps // 2), 1)
     print(json.dumps(res), flush=True)
 
 

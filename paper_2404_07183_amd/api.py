@@ -362,32 +362,48 @@ def norms(X, p=2.0, a=0.0, b=math.inf, *, power=False, out=None, stream=None):
     return _single(X, _lib.PCF_NORM_POW if power else _lib.PCF_NORM, p, a, b, out, stream)
 
 
-def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None):
-    """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, FP64)."""
+def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None,
+                      packed=False):
+    """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, FP64).
+    A ``workspace`` that served the previous backward call on the same set
+    keeps its plan; ``packed=True`` as in ``pdist``."""
     Xc = X.c_struct()
     grad_out = grad_out.to(torch.float64).contiguous()
+    if grad_out.shape != (X.n, X.n) or grad_out.device != X.t.device:
+        raise ValueError("grad_out must be an n x n tensor on the set's device")
     gt = torch.empty_like(X.t)
     gv = torch.empty_like(X.v)
+    key = ("bwd", kind, X.dtype, X.n, id(X.offsets_host))
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
-    ws.ensure(_lib.pcf_workspace_bytes(Xc, kind, None, 1))
+    reuse = ws.planned == key
+    if not reuse:
+        ws.ensure(_lib.pcf_workspace_bytes(Xc, kind, None, 1))
+    flags = PCF_REUSE_PLAN if reuse else 0
+    if packed:
+        if not reuse or ws.packed_data != (X.t.data_ptr(), X.v.data_ptr()):
+            raise ValueError("packed=True needs an earlier call on the same set, "
+                             "data and workspace")
+        flags |= PCF_RECORDS_PACKED
     fptr, ldf = (fwd_out.data_ptr(), fwd_out.stride(0)) if fwd_out is not None else (None, 0)
     st = _lib.pcf_pairwise_backward(Xc, kind, float(p), grad_out.data_ptr(),
                                     grad_out.stride(0), fptr, ldf, gt.data_ptr(),
-                                    gv.data_ptr(), ws.ptr, ws.nbytes, 0,
+                                    gv.data_ptr(), ws.ptr, ws.nbytes, flags,
                                     _stream_handle(stream))
     check(st)
-    ws.planned = None
+    ws.planned = key
+    ws.planned_ref = X.offsets_host
+    ws.packed_data = (X.t.data_ptr(), X.v.data_ptr())
     return gt, gv
 
 
 def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=None,
                      upper_only=False, validate=False, stream=None, shape=None,
-                     bounds=None, weight=None):
+                     bounds=None, weight=None, packed=False):
     """Independent full matrices of the problems ``set_offsets`` cuts ``X``
     into, in one launch. Returns ``(out_flat, out_offsets)``: problem b's
     s_b x s_b matrix is ``out_flat[out_offsets[b]:][:s_b*s_b]``.
     ``bounds`` and ``weight`` as in ``pdist`` (the set is transformed first;
-    PCF indices are kept)."""
+    PCF indices are kept). ``packed=True`` as in ``pdist``."""
     X = _transform(X, bounds, weight, stream)
     so = np.ascontiguousarray(set_offsets, dtype=np.int64)
     B = len(so) - 1
@@ -409,13 +425,19 @@ def pairwise_batched(set_offsets, X, kind=PCF_LP, p=1.0, *, out=None, workspace=
     reuse = ws.planned == key
     if not reuse:
         ws.ensure(_lib.pcf_batched_workspace_bytes(B, so.ctypes.data, Xc))
+    flags = _flags(upper_only, validate, reuse, shape)
+    if packed:
+        if not reuse or ws.packed_data != (X.t.data_ptr(), X.v.data_ptr()):
+            raise ValueError("packed=True needs an earlier call on the same set, "
+                             "data and workspace")
+        flags |= PCF_RECORDS_PACKED
     st = _lib.pcf_pairwise_batched(B, so.ctypes.data, Xc, kind, float(p), out.data_ptr(),
-                                   oo.ctypes.data, ws.ptr, ws.nbytes,
-                                   _flags(upper_only, validate, reuse, shape),
+                                   oo.ctypes.data, ws.ptr, ws.nbytes, flags,
                                    _stream_handle(stream))
     check(st)
     ws.planned = key
     ws.planned_ref = X.offsets_host
+    ws.packed_data = (X.t.data_ptr(), X.v.data_ptr())
     return out, oo
 
 

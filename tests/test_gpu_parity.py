@@ -274,3 +274,41 @@ def test_huge_pcf_wide_step_prefix():
         ref, ab = oracle.entries(okind, p, o, t, v, pick_i, pick_j, with_abs=True)
         err = np.abs(M[pick_i, pick_j] - ref)
         assert np.all(err <= 1e-12 * np.maximum(ab, 1e-300)), (name, err, ref)
+
+
+@pytest.fixture(scope="module")
+def plain_sets():
+    """The N = 20,000 configuration in both precisions (FP32: the FP64 draws
+    rounded, duplicates dropped), resident on the GPU."""
+    sets = {}
+    for dt in (np.float64, np.float32):
+        o, t, v = workloads.config_plain(dtype=dt)
+        sets[dt] = (o, t, v, api.PcfSet(o, t, v, device=DEV))
+    return sets
+
+
+@pytest.mark.parametrize("name,dt,tol", [("l2", np.float64, 1e-12), ("gram", np.float64, 1e-12),
+                                         ("l1", np.float32, 1e-5), ("l2", np.float32, 1e-5),
+                                         ("gram", np.float32, 1e-5)])
+def test_plain_full_size_sampled_kinds(plain_sets, name, dt, tol):
+    # the N = 20,000 configuration at full size in the benchmark's launch
+    # configuration: 3,000 random entries plus the whole first row against
+    # the oracle (FP32: on the rounded inputs), and properties of the whole
+    # matrix
+    o, t, v, X = plain_sets[dt]
+    fn, okind, p = KINDS[name]
+    M = fn(X)
+    assert M.dtype == X.dtype
+    assert torch.equal(M, M.T)
+    assert torch.isfinite(M).all()
+    if okind != oracle.GRAM:
+        assert torch.all(torch.diagonal(M) == 0)
+    I, J = workloads.random_pairs(X.n, 3000, seed=78)
+    I = np.concatenate([I, np.zeros(X.n, dtype=I.dtype)])
+    J = np.concatenate([J, np.arange(X.n, dtype=J.dtype)])
+    got = M[torch.as_tensor(I, device=DEV), torch.as_tensor(J, device=DEV)]
+    got = got.double().cpu().numpy()
+    ref, ab = oracle.entries(okind, p, o, t.astype(np.float64), v.astype(np.float64), I, J,
+                             with_abs=True)
+    err = np.abs(got - ref) / np.maximum(_scale(okind, p, ab), 1e-300)
+    assert err.max() <= tol, (name, dt, err.max(), np.argmax(err))
