@@ -144,6 +144,24 @@ pcf_status pcf_gram(const pcf_set *X, void *out, int64_t ldo,
                     const pcf_window *w, void *ws, size_t ws_bytes,
                     uint32_t flags, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * pcf_pairwise_lp (kind PCF_LP or PCF_LP_POW) and pcf_gram (kind PCF_GRAM)
+ * with the workspace taken from a device array the library holds, of
+ * PCF_NOALLOC_SCRATCH_BYTES bytes on every GPU it runs on (held from module
+ * load until the process ends), instead of a caller buffer. Same arguments,
+ * results and errors as pcf_pairwise_lp, without ws and ws_bytes; calls no
+ * allocating routine. PCF_ENOMEM (before any device work when
+ * X->offsets_host is given) when the call's plan and packed records exceed
+ * the array; PCF_EINVAL for PCF_REUSE_PLAN or PCF_RECORDS_PACKED, since every
+ * call on a device shares that device's array and overwrites what it held.
+ * Calls that overlap on one device (other streams or host threads) race;
+ * calls in one stream are ordered. */
+#define PCF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pcf_status pcf_pairwise_lp_noalloc(const pcf_set *X, pcf_kind kind, double p,
+                                   void *out, int64_t ldo, const pcf_window *w,
+                                   uint32_t flags, void *stream);
+
 /* Adjoint of a full-matrix call (not in the paper; the paper's Section 3
  * aside only notes that derivatives are analytic). Given grad_out = dL/dF
  * (n x n, leading dimension ldg) and, for PCF_LP with p != 1, the forward

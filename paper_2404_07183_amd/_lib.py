@@ -58,6 +58,10 @@ _SIGS = {
                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.POINTER(pcf_window), ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p]),
+    "pcf_pairwise_lp_noalloc": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_void_p,
+                                               ctypes.c_int64, ctypes.POINTER(pcf_window),
+                                               ctypes.c_uint32, ctypes.c_void_p]),
     "pcf_gram": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_void_p, ctypes.c_int64,
                                 ctypes.POINTER(pcf_window), ctypes.c_void_p,
                                 ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p]),

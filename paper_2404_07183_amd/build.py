@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcf.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "single.hip", "reduce.hip", "abi.hip", "plan.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "single.hip", "reduce.hip", "abi.hip", "noalloc.hip",
+           "plan.cpp"]
 ARCH = "gfx950"
 
 

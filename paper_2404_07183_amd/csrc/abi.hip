@@ -482,6 +482,47 @@ pcf_status check_range(const pcf_set *X, double a, double b)
 
 }  // namespace
 
+namespace pcf {
+
+// Used by noalloc.hip (the allocation-free entry point).
+pcf_status noalloc_fail(pcf_status s, const std::string &msg) { return fail(s, msg); }
+
+pcf_status noalloc_forward(const pcf_set *X, pcf_kind kind, double p, void *out,
+                           int64_t ldo, const pcf_window *w, void *ws,
+                           size_t ws_bytes, uint32_t flags, void *stream)
+{
+    return forward_common(X, kind, p, out, ldo, w, ws, ws_bytes, flags, stream);
+}
+
+// Exact workspace of a forward call's plan (the size forward_common uploads
+// and packs), without touching a device when X->offsets_host is given.
+pcf_status noalloc_plan_bytes(const pcf_set *X, const pcf_window *w, int64_t ldo,
+                              uint32_t flags, int64_t *bytes)
+{
+    pcf_status st = check_set(X);
+    if (st != PCF_OK)
+        return st;
+    if (w && (w->row0 < 0 || w->row1 < w->row0 || w->row1 > X->n || w->col0 < 0 ||
+              w->col1 < w->col0 || w->col1 > X->n))
+        return fail(PCF_EINVAL, "window out of range");
+    std::vector<int64_t> obuf;
+    const int64_t *ho = nullptr;
+    st = host_offsets(X, obuf, ho, nullptr);
+    if (st != PCF_OK)
+        return st;
+    Plan plan;
+    std::string err;
+    if (!plan_matrix(X->n, ho, rec_bytes_of(X->dtype), false, w != nullptr,
+                     w ? w->row0 : 0, w ? w->row1 : 0, w ? w->col0 : 0, w ? w->col1 : 0,
+                     (flags & PCF_UPPER_ONLY) != 0, ldo > 0 ? ldo : 1, shape_of(flags), plan,
+                     err))
+        return fail(PCF_EINVAL, err);
+    *bytes = plan_workspace_bytes(plan, rec_bytes_of(X->dtype));
+    return PCF_OK;
+}
+
+}  // namespace pcf
+
 extern "C" {
 
 const char *pcf_last_error(void) { return g_err.c_str(); }

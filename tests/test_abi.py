@@ -230,3 +230,23 @@ def test_plan_key_separates_dtypes(monkeypatch):
     api.pdist(X64, workspace=ws)
     api.pdist(X64, workspace=ws)
     assert seen == [(_lib.PCF_F32, False), (_lib.PCF_F64, False), (_lib.PCF_F64, True)]
+
+
+def test_noalloc_refuses_oversized_sets_before_device_work():
+    """pcf_pairwise_lp_noalloc sizes the call's plan on the host (offsets_host
+    given) and refuses one beyond the library's array with PCF_ENOMEM before
+    touching a device; it refuses plan reuse; it exports the array's size."""
+    lib = _lib.load()
+    n = 40000
+    counts = np.full(n, 200, dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced on these paths
+    X = _lib.pcf_set(n, fake, fake, fake, _lib.PCF_F64, off.ctypes.data)
+    st = lib.pcf_pairwise_lp_noalloc(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, n, None, 0, None)
+    assert st == _lib.PCF_ENOMEM
+    assert "scratch" in _lib.last_error() and str(64 << 20) in _lib.last_error()
+    st = lib.pcf_pairwise_lp_noalloc(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, n, None,
+                                     _lib.PCF_REUSE_PLAN, None)
+    assert st == _lib.PCF_EINVAL
+    src = open(os.path.join(ROOT, "include", "pcf.h")).read()
+    assert "#define PCF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in src
