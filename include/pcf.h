@@ -98,7 +98,11 @@ typedef struct {
 enum {
     PCF_UPPER_ONLY = 1u,    /* write only (i,j) with i <= j of symmetric parts */
     PCF_VALIDATE = 2u,      /* check the data contract first (synchronises)   */
-    PCF_DETERMINISTIC = 4u, /* reserved: accepted, currently a no-op          */
+    PCF_DETERMINISTIC = 4u, /* bit-identical results run to run: always true
+                                of the matrix calls (fixed-order partial sums
+                                for a given plan); refused by
+                                pcf_pairwise_backward (PCF_EUNSUPPORTED),
+                                whose gradient sums use atomics            */
     PCF_REUSE_PLAN = 8u,    /* reuse the plan already in ws (see above)       */
     PCF_RECORDS_PACKED = 16u /* with PCF_REUSE_PLAN: ws also still holds the
                                 packed records of these very t and v (e.g. an
@@ -174,7 +178,8 @@ pcf_status pcf_pairwise_lp_noalloc(const pcf_set *X, pcf_kind kind, double p,
  * the one-sided time derivatives is used. Each pair's merge is recomputed;
  * nothing is stored between forward and backward. FP64 only
  * (PCF_EUNSUPPORTED for FP32). Gradient sums use atomics: the summation
- * order, and the last bits, may vary between runs. */
+ * order, and the last bits, may vary between runs, so PCF_DETERMINISTIC is
+ * refused (PCF_EUNSUPPORTED, before any device work). */
 pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
                                  const void *grad_out, int64_t ldg,
                                  const void *fwd_out, int64_t ldf,

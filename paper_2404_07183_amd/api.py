@@ -136,7 +136,7 @@ def _forward(X, kind, p, window, out, upper_only, validate, workspace, stream,
     ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
     # the plan depends on the record size (dtype) and on the plan type
     # (forward here; the adjoint's plan has other blocks)
-    key = ("fwd", kind, X.dtype, X.n, id(X.offsets_host), window, upper_only, shape)
+    key = ("fwd", kind, X.dtype, X.n, id(X.offsets_host), window, upper_only, shape, ldo)
     ws = workspace if workspace is not None else Workspace(device=X.t.device)
     reuse = ws.planned == key
     if not reuse:

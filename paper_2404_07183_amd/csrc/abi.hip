@@ -7,7 +7,9 @@
 #include <string.h>
 
 #include <limits>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -119,9 +121,81 @@ pcf_status host_offsets(const pcf_set *X, std::vector<int64_t> &buf,
     return PCF_OK;
 }
 
+// What plan each workspace holds (the last one this library uploaded into
+// it): the call it was made for, with everything that shapes its tiles and
+// output mapping. A call with PCF_REUSE_PLAN is refused unless its workspace
+// holds a plan made for that very call (same kind of call, record size,
+// number of PCFs, window, leading dimension, upper-only and tile-shape
+// flags; for a batched call the number of problems). The offsets' contents
+// cannot be compared without reading them; the caller keeps them unchanged.
+enum PlanKind { kPlanForward = 0, kPlanBackward = 1, kPlanBatched = 2, kPlanCross = 3 };
+struct PlanTag {
+    int kind = -1;
+    int rec_bytes = 0;
+    int64_t n = 0, r0 = 0, r1 = 0, c0 = 0, c1 = 0, ldo = 0;
+    uint32_t shape_flags = 0;
+    bool operator==(const PlanTag &o) const
+    {
+        return kind == o.kind && rec_bytes == o.rec_bytes && n == o.n && r0 == o.r0 &&
+               r1 == o.r1 && c0 == o.c0 && c1 == o.c1 && ldo == o.ldo &&
+               shape_flags == o.shape_flags;
+    }
+};
+std::mutex g_plan_mu;
+std::unordered_map<const void *, PlanTag> g_plan_tags;
+
+PlanTag plan_tag(int kind, const pcf_set *X, const pcf_window *w, int64_t ldo, uint32_t flags)
+{
+    PlanTag t;
+    t.kind = kind;
+    t.rec_bytes = rec_bytes_of(X->dtype);
+    t.n = X->n;
+    if (w) {
+        t.r0 = w->row0;
+        t.r1 = w->row1;
+        t.c0 = w->col0;
+        t.c1 = w->col1;
+    } else {
+        t.r1 = t.c1 = -1;
+    }
+    t.ldo = ldo;
+    t.shape_flags = flags & (PCF_UPPER_ONLY | 0x000fff00u);
+    return t;
+}
+
+void remember_plan(const void *ws, const PlanTag &tag)
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plan_tags[ws] = tag;
+}
+
+pcf_status check_reused_plan(const void *ws, const PlanTag &tag)
+{
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_plan_tags.find(ws);
+    if (it == g_plan_tags.end())
+        return fail(PCF_EINVAL, "PCF_REUSE_PLAN: this workspace holds no plan made by "
+                                "this library");
+    const PlanTag &h = it->second;
+    if (h.kind != tag.kind) {
+        static const char *names[] = {"a matrix call", "pcf_pairwise_backward",
+                                      "pcf_pairwise_batched", "pcf_cross"};
+        return fail(PCF_EINVAL, std::string("PCF_REUSE_PLAN: the workspace holds a plan "
+                                            "for ") + names[h.kind]);
+    }
+    if (h.rec_bytes != tag.rec_bytes)
+        return fail(PCF_EINVAL, std::string("PCF_REUSE_PLAN: the workspace's plan was made "
+                                            "for ") + (h.rec_bytes == 16 ? "FP64" : "FP32") +
+                                    " data");
+    if (!(h == tag))
+        return fail(PCF_EINVAL, "PCF_REUSE_PLAN: the workspace's plan was made for another "
+                                "set size, window, leading dimension or tile shape");
+    return PCF_OK;
+}
+
 // Copy a plan's header, blocks and segments into the workspace.
 pcf_status upload_plan(const Plan &plan, int rec_bytes, void *ws,
-                       size_t ws_bytes, hipStream_t s)
+                       size_t ws_bytes, hipStream_t s, const PlanTag &tag)
 {
     const int64_t need = plan_workspace_bytes(plan, rec_bytes);
     if ((int64_t)ws_bytes < need)
@@ -140,6 +214,7 @@ pcf_status upload_plan(const Plan &plan, int rec_bytes, void *ws,
         e = hipStreamSynchronize(s);  // buf is a local
     if (e != hipSuccess)
         return hip_fail(e, "uploading the tile plan");
+    remember_plan(ws, tag);
     return PCF_OK;
 }
 
@@ -175,14 +250,18 @@ struct Call {
 
 pcf_status prepare(const pcf_set *X, const Plan *plan, void *ws,
                    size_t ws_bytes, uint32_t flags, hipStream_t s, Call &c,
-                   const int64_t *ho)
+                   const int64_t *ho, const PlanTag &tag)
 {
     c.reuse = (flags & PCF_REUSE_PLAN) != 0;
     c.validate = (flags & PCF_VALIDATE) != 0;
     c.P = ho ? ho[X->n] : -1;
     if (!c.reuse) {
         pcf_status st = upload_plan(*plan, rec_bytes_of(X->dtype), ws,
-                                    ws_bytes, s);
+                                    ws_bytes, s, tag);
+        if (st != PCF_OK)
+            return st;
+    } else {
+        pcf_status st = check_reused_plan(ws, tag);
         if (st != PCF_OK)
             return st;
     }
@@ -265,7 +344,8 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
             return fail(PCF_EINVAL, err);
     }
     Call c;
-    st = prepare(X, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho);
+    st = prepare(X, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho,
+                 plan_tag(kPlanForward, X, w, ldo, flags));
     if (st != PCF_OK)
         return st;
 
@@ -643,7 +723,11 @@ pcf_status pcf_pairwise_batched(int32_t B, const int64_t *set_offsets_host,
             return fail(PCF_EINVAL, err);
     }
     Call c;
-    st = prepare(all, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho);
+    {
+        PlanTag tag = plan_tag(kPlanBatched, all, nullptr, 0, flags);
+        tag.ldo = B;
+        st = prepare(all, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho, tag);
+    }
     if (st != PCF_OK)
         return st;
     FwdArgs a;
@@ -741,6 +825,9 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
         return fail(PCF_EINVAL, "p must be finite and >= 1");
     if (X->dtype != PCF_F64)
         return fail(PCF_EUNSUPPORTED, "the adjoint is implemented for FP64 only");
+    if (flags & PCF_DETERMINISTIC)
+        return fail(PCF_EUNSUPPORTED, "the adjoint accumulates gradients with atomics: "
+                                      "PCF_DETERMINISTIC is not available for it");
     if (X->n == 0)
         return PCF_OK;
     const bool chain = kind == PCF_LP && p != 1.0;
@@ -765,7 +852,8 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
             return fail(PCF_EINVAL, err);
     }
     Call c;
-    st = prepare(X, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho);
+    st = prepare(X, reuse ? nullptr : &plan, ws, ws_bytes, flags, s, c, ho,
+                 plan_tag(kPlanBackward, X, nullptr, X->n, flags));
     if (st != PCF_OK)
         return st;
     const int64_t P = ho ? ho[X->n] : -1;
@@ -850,7 +938,7 @@ pcf_status pcf_cross(const pcf_set *X, const pcf_set *Y, pcf_kind kind, double p
     if ((int64_t)ws_bytes < need)
         return fail(PCF_ENOMEM, "workspace too small: need " + std::to_string(need) +
                                     " bytes, got " + std::to_string(ws_bytes));
-    st = upload_plan(plan, rb, ws, ws_bytes, s);
+    st = upload_plan(plan, rb, ws, ws_bytes, s, plan_tag(kPlanCross, X, nullptr, ldo, flags));
     if (st != PCF_OK)
         return st;
     unsigned char *w = (unsigned char *)ws;

@@ -250,3 +250,29 @@ def test_noalloc_refuses_oversized_sets_before_device_work():
     assert st == _lib.PCF_EINVAL
     src = open(os.path.join(ROOT, "include", "pcf.h")).read()
     assert "#define PCF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in src
+
+
+def test_backward_refuses_deterministic_flag():
+    """The adjoint's atomic gradient sums are not bit-reproducible, so the
+    backward call refuses PCF_DETERMINISTIC before touching a device."""
+    lib = _lib.load()
+    off = np.array([0, 2, 4], dtype=np.int64)
+    fake = ctypes.c_void_p(0x1000)
+    X = _lib.pcf_set(2, fake, fake, fake, _lib.PCF_F64, off.ctypes.data)
+    st = lib.pcf_pairwise_backward(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, 2, None, 0, fake,
+                                   fake, fake, 1 << 20, _lib.PCF_DETERMINISTIC, None)
+    assert st == _lib.PCF_EUNSUPPORTED
+    assert "DETERMINISTIC" in _lib.last_error()
+
+
+def test_plan_reuse_refused_without_a_matching_plan():
+    """PCF_REUSE_PLAN on a workspace this library never planned into is
+    refused before any device work."""
+    lib = _lib.load()
+    off = np.array([0, 2, 4], dtype=np.int64)
+    fake = ctypes.c_void_p(0x2000)
+    ws = ctypes.c_void_p(0x7000)  # never planned into
+    X = _lib.pcf_set(2, fake, fake, fake, _lib.PCF_F64, off.ctypes.data)
+    st = lib.pcf_pairwise_lp(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, 2, None, ws, 1 << 20,
+                             _lib.PCF_REUSE_PLAN, None)
+    assert st == _lib.PCF_EINVAL and "holds no plan" in _lib.last_error()

@@ -312,3 +312,36 @@ def test_plain_full_size_sampled_kinds(plain_sets, name, dt, tol):
                              with_abs=True)
     err = np.abs(got - ref) / np.maximum(_scale(okind, p, ab), 1e-300)
     assert err.max() <= tol, (name, dt, err.max(), np.argmax(err))
+
+
+def test_plan_reuse_across_dtypes_and_calls():
+    # FP32 then FP64 sets sharing one offsets array and one Workspace: the
+    # second call re-plans (records of another size) and matches the oracle;
+    # the C layer refuses to reuse a plan made for the other dtype or for
+    # another kind of call
+    import ctypes
+    from paper_2404_07183_amd import _lib
+    o, t, v = workloads.uniform_counts(120, 2, 90, seed=31)
+    X64 = api.PcfSet(o, t, v, device=DEV)
+    X32 = api.PcfSet(X64.offsets_host, t.astype(np.float32), v.astype(np.float32), device=DEV)
+    ws = api.Workspace(device=DEV)
+    api.pdist(X32, 1.0, workspace=ws)
+    M = api.pdist(X64, 1.0, workspace=ws).cpu().numpy()
+    n = X64.n
+    I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ref, ab = oracle.entries(oracle.LP, 1.0, o, t, v, I.ravel(), J.ravel(), with_abs=True)
+    assert np.all(np.abs(M.ravel() - ref) <= 1e-12 * np.maximum(ab, 1e-300))
+    lib = _lib.load()
+    out = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    Xc = X32.c_struct()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    st = lib.pcf_pairwise_lp(ctypes.byref(Xc), _lib.PCF_LP, 1.0, out.data_ptr(), n, None,
+                             ws.ptr, ws.nbytes, _lib.PCF_REUSE_PLAN, stream)
+    assert st == _lib.PCF_EINVAL and "FP64" in _lib.last_error()
+    api.pairwise_backward(X64, api.PCF_LP_POW, 2.0, torch.ones((n, n), dtype=torch.float64,
+                                                                device=DEV), workspace=ws)
+    Xc = X64.c_struct()
+    out64 = torch.empty((n, n), dtype=torch.float64, device=DEV)
+    st = lib.pcf_pairwise_lp(ctypes.byref(Xc), _lib.PCF_LP, 1.0, out64.data_ptr(), n, None,
+                             ws.ptr, ws.nbytes, _lib.PCF_REUSE_PLAN, stream)
+    assert st == _lib.PCF_EINVAL and "pcf_pairwise_backward" in _lib.last_error()
