@@ -461,6 +461,7 @@ pcf_status check_weight(int weight, double c)
 // output offsets, two ping-pong row buffers, the deviation sums of a
 // standard deviation).
 constexpr int64_t kRedChunkRows = 1024;  // the root pass's chunk (reduce.hip)
+constexpr int64_t kRedStdSlots = 64;     // the std pass's bounds per chunk (reduce.hip)
 
 struct RedPlan {
     int32_t B = 0;
@@ -468,6 +469,7 @@ struct RedPlan {
     int64_t n = 0, P = 0, C = 0;  // PCFs, rows, chunks
     std::vector<int64_t> meta;    // groups (B+1), chunk rows (C), chunk groups (C)
     size_t off_ccnt = 0, off_coff = 0, off_buf[4] = {0, 0, 0, 0}, off_q = 0, off_map = 0;
+    size_t off_kb = 0;  // PCF_REDUCE_STD: each chunk's first rows (64 per chunk)
     size_t bytes = 0;
 };
 
@@ -542,6 +544,10 @@ pcf_status red_plan(const pcf_set *X, int32_t B, const int64_t *groups, int op,
     off += align256((size_t)(rp.P > 0 ? rp.P : 1) * esz);
     rp.off_map = off;
     off += align256((size_t)(rp.P > 0 ? rp.P : 1) * sizeof(int32_t));
+    if (op == PCF_REDUCE_STD) {
+        rp.off_kb = off;
+        off += align256((size_t)(rp.C > 0 ? rp.C : 1) * kRedStdSlots * sizeof(int64_t));
+    }
     rp.bytes = off;
     return PCF_OK;
 }
@@ -1205,7 +1211,18 @@ static pcf_status reduce_rows_impl(const pcf_set *X, int32_t B,
         a.rt = rt;
         a.rv = rv;
         a.q = w + rp.off_q;
-        e = launch_red_std(f64, a, s);
+        a.nchunks = rp.C;
+        a.chunk_row = meta + B + 1;
+        a.chunk_grp = meta + B + 1 + rp.C;
+        a.chunk_first = (int64_t *)(w + rp.off_kb);
+        // groups of at most 64 PCFs by red_std_small, larger ones (if any)
+        // by red_std_terms
+        bool large = false;
+        for (int32_t b = 0; b < B && !large; ++b)
+            large = group_offsets_host[b + 1] - group_offsets_host[b] > 64;
+        e = launch_red_std_small(f64, a, s);
+        if (e == hipSuccess && large)
+            e = launch_red_std(f64, a, s);
         rv = w + rp.off_q;
     }
     int64_t *ccnt = (int64_t *)(w + rp.off_ccnt), *coff = (int64_t *)(w + rp.off_coff);

@@ -43,6 +43,7 @@ namespace {
 // merged positions per lane (4 measured fastest against 2, 8 and 16)
 constexpr int kMergeK = 4;
 constexpr int kChunkRows = 1024;  // rows per wave in the root pass
+constexpr int64_t kStdSmall = 64;  // groups of at most this many PCFs: red_std_small
 
 template <typename T, int OP>
 __device__ __forceinline__ T red_op(T a, T b)
@@ -205,7 +206,8 @@ __global__ void red_rowmap(const int64_t *__restrict__ offsets, int64_t n,
 }
 
 // Sum over i of (f_i(x) - mean(x))^2 at every root breakpoint x, in the
-// tree's order.
+// tree's order, for the rows of groups of more than kStdSmall PCFs: a binary
+// search of every PCF of the group per root row.
 template <typename T>
 __global__ void red_std_terms(RedStdArgs a)
 {
@@ -227,6 +229,8 @@ __global__ void red_std_terms(RedStdArgs a)
                 hi = mid - 1;
         }
         const int64_t gb = a.groups[lo], ge = a.groups[lo + 1];
+        if (ge - gb <= kStdSmall)
+            continue;  // red_std_small's rows
         const T x = rt[r];
         const T mean = rv[r] / (T)(ge - gb);
         // binary counter over the group's PCFs: after k terms, st[h] holds
@@ -292,6 +296,228 @@ __global__ void red_std_terms(RedStdArgs a)
             }
         }
         q[r] = acc;
+    }
+}
+
+// The same sums for groups of at most kStdSmall PCFs: one block per chunk of
+// root rows (the root pass's chunks).
+//
+// The root of a group holds every row of its PCFs once (the levels keep all
+// merged positions). For chunk [c0, c1) with first time xf, and x1 the first
+// time of the group's next chunk, the rows of PCF i that the chunk's times
+// can select lie between its row at or before xf and its row at or before x1
+// (its last row for the group's last chunk): together at most
+// (c1 - c0) + 2m - 1 rows over the group (one per root row c0 + 1 .. c1,
+// m - 1 more that tie with x1 past it, and the m rows at or before xf).
+// red_std_bounds bisects every PCF once per chunk for the rows at or before
+// xf; red_std_small stages the window of (t, v) records in LDS. Thread j
+// then takes root rows c0 + Rj .. c0 + Rj + R - 1: for every PCF i of the
+// group (i = 0, 1, .. in order) it finds the record at or before its first
+// row by bisection of PCF i's records, walks forward for the others, and adds
+// (f_i(x) - mean(x))^2 to a binary counter per row, which sums the m terms in
+// the reduction tree's order (pairs (2j, 2j + 1), then pairs of pairs, an
+// unpaired last block moving up), as red_std_terms.
+constexpr int kStdThreads = 512;
+constexpr int kStdRowsPerThread = kChunkRows / kStdThreads;
+constexpr int kStdWindow = kChunkRows + 2 * (int)kStdSmall;
+constexpr int kStdHeights = 7;  // subtree heights 0 .. 6: up to 127 >= kStdSmall terms
+static_assert(kChunkRows % kStdThreads == 0 && kStdSmall == 64 && (1 << kStdHeights) > kStdSmall,
+              "red_std_small's layout");
+
+// chunk_first[64c + i] = the last row of PCF i (i < m) with t at or before
+// the first root time of chunk c, for the chunks of groups of at most
+// kStdSmall PCFs.
+template <typename T>
+__global__ void red_std_bounds(RedStdArgs a)
+{
+    const T *__restrict__ t = reinterpret_cast<const T *>(a.t);
+    const T *__restrict__ rt = reinterpret_cast<const T *>(a.rt);
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < a.nchunks * kStdSmall;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = u / kStdSmall, i = u % kStdSmall;
+        const int64_t b = a.chunk_grp[c];
+        const int64_t gb = a.groups[b], m = a.groups[b + 1] - gb;
+        if (m > kStdSmall || i >= m)
+            continue;
+        const T x = rt[a.chunk_row[c]];
+        const int64_t o = a.offsets[gb + i], n = a.offsets[gb + i + 1] - o;
+        int64_t lo = 0, hi = n - 1;  // t[o] = 0 <= x
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (t[o + mid] <= x)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        a.chunk_first[u] = lo;
+    }
+}
+
+template <typename T>
+struct StdRecord {
+    T t, v;
+};
+
+// Term s[k] joins the subtrees of heights 0 .. H-1 (smallest first, each on
+// the left) and is kept as the subtree of height H.
+template <typename T, int R, int H>
+__device__ __forceinline__ void std_counter_add(T (&st)[R][kStdHeights], T (&s)[R])
+{
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+            s[k] = st[k][h] + s[k];
+        st[k][H] = s[k];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStdThreads) void red_std_small(RedStdArgs a)
+{
+#pragma clang fp contract(off)
+    constexpr int R = kStdRowsPerThread;
+    const T *__restrict__ t = reinterpret_cast<const T *>(a.t);
+    const T *__restrict__ v = reinterpret_cast<const T *>(a.v);
+    const T *__restrict__ rt = reinterpret_cast<const T *>(a.rt);
+    const T *__restrict__ rv = reinterpret_cast<const T *>(a.rv);
+    T *__restrict__ q = reinterpret_cast<T *>(a.q);
+    __shared__ StdRecord<T> rec[kStdWindow];
+    __shared__ int64_t row0[kStdSmall];
+    __shared__ int32_t wbase[kStdSmall + 1];
+    __shared__ int32_t bad;
+    const int tid = threadIdx.x;
+    const T inf = __builtin_inf();
+    for (int64_t c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
+        const int64_t b = a.chunk_grp[c];
+        const int64_t gb = a.groups[b];
+        const int m = (int)(a.groups[b + 1] - gb);
+        if (m > kStdSmall)
+            continue;  // red_std_terms' rows (block-uniform)
+        const int64_t c0 = a.chunk_row[c], g1 = a.offsets[gb + m];
+        const int64_t c1 = c0 + kChunkRows < g1 ? c0 + kChunkRows : g1;
+        // window offsets: an inclusive scan of the record counts in wave 0
+        if (tid < 64) {
+            int64_t len = 0;
+            if (tid < m) {
+                const int64_t o = a.offsets[gb + tid], n = a.offsets[gb + tid + 1] - o;
+                const int64_t k0 = a.chunk_first[kStdSmall * c + tid];
+                const int64_t k1 =
+                    c1 < g1 ? a.chunk_first[kStdSmall * (c + 1) + tid] : n - 1;
+                row0[tid] = o + k0;
+                len = k1 - k0 + 1;
+            }
+            int32_t s = len < 1 || len > kStdWindow ? kStdWindow + 1 : (int32_t)len;
+            for (int h = 1; h < 64; h <<= 1) {
+                const int32_t o = __shfl_up(s, h, 64);
+                if (tid >= h)
+                    s += o;
+            }
+            wbase[tid + 1] = s;
+            // a window over the bound only comes from times that do not
+            // increase (PCF rules broken): the chunk's sums become NaN
+            const uint64_t over = __ballot(tid < m && s > kStdWindow);
+            if (tid == 0) {
+                wbase[0] = 0;
+                bad = over != 0;
+            }
+        }
+        __syncthreads();
+        const int32_t L = wbase[m];
+        const bool ok = bad == 0;
+        if (ok) {
+            for (int32_t e = tid; e < L; e += kStdThreads) {
+                int32_t lo = 0, hi = m - 1;  // the PCF whose window holds record e
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (wbase[mid] <= e)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int64_t r = row0[lo] + (e - wbase[lo]);
+                rec[e].t = t[r];
+                rec[e].v = v[r];
+            }
+        }
+        // this thread's root rows and their means (rows past the chunk repeat
+        // its last time and are not written)
+        const int64_t r0 = c0 + (int64_t)R * tid;
+        T x[R], mean[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int64_t r = r0 + k < c1 ? r0 + k : c1 - 1;
+            x[k] = rt[r];
+            mean[k] = rv[r] / (T)m;
+        }
+        __syncthreads();
+        T st[R][kStdHeights];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+            for (int h = 0; h < kStdHeights; ++h)
+                st[k][h] = T(0);
+        if (ok) {
+            for (int i = 0; i < m; ++i) {
+                const int32_t lo = __builtin_amdgcn_readfirstlane(wbase[i]);
+                const int32_t end = __builtin_amdgcn_readfirstlane(wbase[i + 1]);
+                // last record of PCF i at or before x[0] (rec[lo].t <= x[0])
+                int32_t p = lo;
+                int32_t step = 1;
+                while (2 * step <= end - lo - 1)
+                    step <<= 1;
+                for (int32_t s = end - lo > 1 ? step : 0; s > 0; s >>= 1) {
+                    const int32_t j = p + s < end ? p + s : end - 1;
+                    if (p + s < end && rec[j].t <= x[0])
+                        p = j;
+                }
+                T val[R];
+                val[0] = rec[p].v;
+                T nt = p + 1 < end ? rec[p + 1].t : inf;
+#pragma unroll
+                for (int k = 1; k < R; ++k) {
+                    while (nt <= x[k]) {
+                        ++p;
+                        nt = p + 1 < end ? rec[p + 1].t : inf;
+                    }
+                    val[k] = rec[p].v;
+                }
+                T s[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const T d = val[k] - mean[k];
+                    s[k] = d * d;
+                }
+                // binary counter: after i + 1 terms st[k][h] holds a complete
+                // subtree of 2^h terms for every set bit h of i + 1; term i
+                // joins the subtrees below the lowest clear bit of i
+                switch (__builtin_ctz(~(unsigned)i)) {
+                case 0: std_counter_add<T, R, 0>(st, s); break;
+                case 1: std_counter_add<T, R, 1>(st, s); break;
+                case 2: std_counter_add<T, R, 2>(st, s); break;
+                case 3: std_counter_add<T, R, 3>(st, s); break;
+                case 4: std_counter_add<T, R, 4>(st, s); break;
+                case 5: std_counter_add<T, R, 5>(st, s); break;
+                default: std_counter_add<T, R, 6>(st, s); break;
+                }
+            }
+        }
+        // fold the subtrees from the smallest up and store
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            T acc = T(0);
+            bool have = false;
+#pragma unroll
+            for (int h = 0; h < kStdHeights; ++h) {
+                if ((m >> h) & 1) {
+                    acc = have ? st[k][h] + acc : st[k][h];
+                    have = true;
+                }
+            }
+            if (r0 + k < c1)
+                q[r0 + k] = ok ? acc : __builtin_nan("");
+        }
+        __syncthreads();  // the records and window table are rewritten next
     }
 }
 
@@ -440,6 +666,22 @@ hipError_t launch_red_std(bool f64, const RedStdArgs &a, hipStream_t s)
         hipLaunchKernelGGL(red_std_terms<double>, g, blk, 0, s, a);
     else
         hipLaunchKernelGGL(red_std_terms<float>, g, blk, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_red_std_small(bool f64, const RedStdArgs &a, hipStream_t s)
+{
+    if (a.nchunks <= 0)
+        return hipSuccess;
+    const dim3 gb((unsigned)grid_for(a.nchunks * kStdSmall, 256, 16384)), bb(256);
+    const dim3 g((unsigned)grid_for(a.nchunks, 1, 16384)), blk(kStdThreads);
+    if (f64) {
+        hipLaunchKernelGGL(red_std_bounds<double>, gb, bb, 0, s, a);
+        hipLaunchKernelGGL(red_std_small<double>, g, blk, 0, s, a);
+    } else {
+        hipLaunchKernelGGL(red_std_bounds<float>, gb, bb, 0, s, a);
+        hipLaunchKernelGGL(red_std_small<float>, g, blk, 0, s, a);
+    }
     return hipGetLastError();
 }
 

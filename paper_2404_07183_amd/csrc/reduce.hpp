@@ -30,6 +30,10 @@ struct RedStdArgs {
     const void *t, *v;       // the set
     const void *rt, *rv;     // the sum tree's roots
     void *q;                 // out: sum of squared deviations per root row
+    int64_t nchunks;         // the root pass's chunks (red_std_small)
+    const int64_t *chunk_row, *chunk_grp;
+    int64_t *chunk_first;    // scratch, 64 per chunk: PCF i's row at or before
+                             // the chunk's first time
 };
 struct RedEmitArgs {
     const int64_t *offsets, *groups;
@@ -50,7 +54,11 @@ hipError_t launch_red_interleave(bool f64, int64_t n, const int64_t *xo, const v
                                  const void *yv, const int64_t *zo, void *zt, void *zv,
                                  hipStream_t s);
 hipError_t launch_red_rowmap(const int64_t *offsets, int64_t n, int32_t *row_pcf, hipStream_t s);
+// groups of more than 64 PCFs (a search per PCF and root row)
 hipError_t launch_red_std(bool f64, const RedStdArgs &a, hipStream_t s);
+// groups of at most 64 PCFs (a block per chunk of root rows, the PCF rows
+// it selects staged in LDS)
+hipError_t launch_red_std_small(bool f64, const RedStdArgs &a, hipStream_t s);
 hipError_t launch_red_emit(bool f64, const RedEmitArgs &a, hipStream_t s);
 
 }  // namespace pcf

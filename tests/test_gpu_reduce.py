@@ -122,3 +122,89 @@ def test_combine_errors():
     Xf = api.PcfSet(xs[0], xs[1].astype(np.float32), xs[2].astype(np.float32), device=DEV)
     with pytest.raises(PcfError):
         api.combine(X, Xf, "sum")  # different dtypes
+
+
+@pytest.mark.parametrize("data", ["uniform", "tied"])
+def test_std_small_and_large_groups_bit_exact(data):
+    # groups of up to 64 PCFs take the chunked kernel (PCF rows staged per
+    # chunk of root rows), larger ones the per-row search; both in one call,
+    # bit for bit against the oracle's tree in FP64
+    if data == "uniform":
+        o, t, v = workloads.uniform_counts(400, 1, 40, seed=106)
+    else:
+        o, t, v = _tied_set(400, seed=107)
+    groups = [0, 2, 5, 9, 17, 33, 66, 130, 195, 260, 400]  # 2..64, 65, 65, 140
+    X = api.PcfSet(o, t, v, device=DEV)
+    got = _rows(api.reduce(X, "std", groups))
+    want = red.reduce_groups("std", groups, o, t, v)
+    for b, ((gt, gv), (wt, wv)) in enumerate(zip(got, want)):
+        assert np.array_equal(gt, wt), (data, b, len(gt), len(wt))
+        assert np.array_equal(gv, wv), (data, b)
+
+
+def test_std_group_past_two_to_the_fifteen():
+    # one group of 2^15 + 3 PCFs (the second level of the std's subtree
+    # counter) next to a small group, bit for bit against the oracle. The
+    # PCFs have one or two rows on a grid of eight times, so that the
+    # oracle's per-PCF squared deviations stay a few rows long.
+    rng = np.random.default_rng(108)
+    big = (1 << 15) + 3
+    pcfs = []
+    for _ in range(big + 5):
+        if rng.random() < 0.2:
+            pcfs.append((np.array([0.0]), np.array([0.0])))
+        else:
+            t1 = float(rng.integers(1, 9))
+            pcfs.append((np.array([0.0, t1]), np.array([float(rng.integers(-8, 9)) / 4, 0.0])))
+    o = np.concatenate([[0], np.cumsum([len(p[0]) for p in pcfs])]).astype(np.int64)
+    t = np.concatenate([p[0] for p in pcfs])
+    v = np.concatenate([p[1] for p in pcfs])
+    groups = [0, 5, 5 + big]
+    X = api.PcfSet(o, t, v, device=DEV)
+    got = _rows(api.reduce(X, "std", groups))
+    want = red.reduce_groups("std", groups, o, t, v)
+    for b, ((gt, gv), (wt, wv)) in enumerate(zip(got, want)):
+        assert np.array_equal(gt, wt), (b, gt, wt)
+        assert np.array_equal(gv, wv), (b, gv, wv)
+
+
+def test_std_tie_runs_across_chunk_edges():
+    # PCFs of a group that share every breakpoint: the root holds runs of m
+    # equal times, and the 1,024-row chunk edges of the standard deviation's
+    # root pass fall inside them (1024 is not a multiple of 60 or 63). This is
+    # the largest window of PCF rows a chunk can select; bit for bit against
+    # the oracle.
+    rng = np.random.default_rng(109)
+    pcfs = []
+    for m, k in ((60, 50), (63, 40), (2, 700), (64, 17)):
+        ts = np.arange(k, dtype=np.float64) / 4
+        for _ in range(m):
+            vs = np.concatenate([rng.integers(-16, 17, size=k - 1) / 8, [0.0]])
+            pcfs.append((ts, vs))
+    o = np.concatenate([[0], np.cumsum([len(p[0]) for p in pcfs])]).astype(np.int64)
+    t = np.concatenate([p[0] for p in pcfs])
+    v = np.concatenate([p[1] for p in pcfs])
+    groups = [0, 60, 123, 125, 189]
+    X = api.PcfSet(o, t, v, device=DEV)
+    got = _rows(api.reduce(X, "std", groups))
+    want = red.reduce_groups("std", groups, o, t, v)
+    for b, ((gt, gv), (wt, wv)) in enumerate(zip(got, want)):
+        assert np.array_equal(gt, wt), (b, len(gt), len(wt))
+        assert np.array_equal(gv, wv), b
+
+
+def test_std_full_size_groups_of_twenty():
+    # the 20,000-PCF set (counts 50..500) in 1,000 groups of 20, as timed;
+    # five groups (the first, the last and three drawn at random) bit for bit
+    # against the oracle run on those groups alone
+    o, t, v = workloads.config_plain()
+    groups = np.arange(0, len(o), 20)
+    X = api.PcfSet(o, t, v, device=DEV)
+    got = _rows(api.reduce(X, "std", groups))
+    rng = np.random.default_rng(110)
+    for b in [0, len(groups) - 2] + list(rng.integers(1, len(groups) - 2, size=3)):
+        i0, i1 = groups[b], groups[b + 1]
+        so = o[i0:i1 + 1] - o[i0]
+        want = red.reduce_groups("std", [0, i1 - i0], so, t[o[i0]:o[i1]], v[o[i0]:o[i1]])
+        assert np.array_equal(got[b][0], want[0][0]), b
+        assert np.array_equal(got[b][1], want[0][1]), b
