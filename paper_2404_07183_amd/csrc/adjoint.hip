@@ -140,36 +140,169 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
 }
 
 // ---------------------------------------------------------------------------
-// The LDS adjoint chain: the forward chain's P/Q formulation (h symmetric,
-// P the piece loaded last, Q the other one, one full-wave record read per
-// step) with each piece's value-gradient accumulator. LDS record q and its
-// two gradient slots belong together, so the slot of a piece is its record
-// index and the chain never needs to know which PCF a piece belongs to.
-// Fixed parameters (t_0, the last value) and padding slots receive terms
-// too; the flush at the end of the tile drops them.
+// The LDS adjoint chain: the forward chain's P/Q formulation and record walk
+// (h symmetric, P the piece loaded last, Q the other one, one record read
+// per step) with each piece's value-gradient accumulator.
+//
+// Gradient slots: record q (at LDS address R0 + 16q) has two FP64 slots,
+// dL/dv of its piece at V0 + 8q and dL/dt of its end time kAdjGtOffset
+// bytes further, so the slots of a piece are found from its record address
+// alone (a halving and the add of a workgroup constant, V0 - R0/2) and the
+// chain never needs to know which PCF a piece belongs to. Each step ends one piece E:
+// its value gradient so far and the time gradient of its end time y go to
+// E's slots (two LDS atomic adds at the walk's address, immediate offsets).
+// Fixed parameters (the last value, the sentinel end time of the last
+// piece) and padding slots receive terms too; the flush at the end of the
+// tile drops them.
+//
+// Time gradient at a breakpoint y where E ends and the other piece O goes
+// on: h(vE, vO) - h(vN, vO), vN the value after y. Where O breaks at y too
+// (equal times: P ends, as P wins ties), the mean of the one-sided
+// derivatives is taken for both breakpoints in that step, reading O's next
+// value; the next step, which ends O with width 0, adds no time gradient.
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef const __attribute__((address_space(3))) d2 *lds_d2;
 
 struct AdjChain {
-    d2 P, Q;               // (end time, value) of the two current pieces
-    int32_t iP, iQ;        // their record indices (= gradient slots)
-    double gP, gQ;         // value gradients of the two pieces so far
+    d2 P;                  // (end time, value) of the piece loaded last
+    uint32_t gb;           // gradient slot base V0 - R0/2 (workgroup constant)
+    double tQ, vQ;         // the other piece
+    LdsWalk<double> w;     // record addresses
+    double gQ;             // value gradient of Q so far, in units of
+                           // gunit<HK> (P's is 0: loaded by the last step)
     double x;              // start of the current cell
-    double W;              // weight of the current pair
+    double Wv, Wt;         // pair weight times the unit of dh/da; pair weight
     int32_t left;          // steps left in the current pair
-    int32_t r, c, rb, rn, cb, cn;
+    int32_t k, r, c, rb, rn, cb, cn;
 };
 
-__device__ __forceinline__ double adj_min(double a, double b)
+// dh/da(a, b) = gunit * dP(a, b); dh/da(b, a) = gunit * dQ(a, b).
+template <int HK>
+__device__ __forceinline__ double gunit(double p)
 {
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
+    if constexpr (HK == kSqr)
+        return 2.0;
+    else if constexpr (HK == kAbs || HK == kProd)
+        return 1.0;
+    else
+        return p;
 }
-__device__ __forceinline__ double adj_max(double a, double b)
+
+// h(e, o) - h(n, o)
+template <int HK>
+__device__ __forceinline__ double hdiff(double e, double n, double o, double p)
 {
-    double r;
-    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
+    if constexpr (HK == kSqr)
+        return (e - n) * ((e + n) - 2.0 * o);
+    else if constexpr (HK == kProd)
+        return (e - n) * o;
+    else
+        return hval<double, HK>(e, o, p) - hval<double, HK>(n, o, p);
+}
+
+// The step's value-gradient terms, dh/da(a, b) = gunit * dP and
+// dh/da(b, a) = gunit * dQ, and h(a, b), from the one difference d = a - b
+// (|d|^p = |d|^(p-1) |d| for general p).
+template <int HK>
+__device__ __forceinline__ void step_terms(double a, double b, double p, double &dP,
+                                           double &dQ, double &hab)
+{
+    if constexpr (HK == kProd) {
+        dP = b;
+        dQ = a;
+        hab = a * b;
+    } else {
+        const double d = a - b;
+        if constexpr (HK == kSqr) {
+            dP = d;
+            hab = d * d;
+        } else if constexpr (HK == kAbs) {
+            dP = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+            hab = fabs(d);
+        } else {
+            const double m = hval<double, HK>(d, 0.0, p - 1.0);  // |d|^(p-1)
+            dP = d > 0.0 ? m : (d < 0.0 ? -m : 0.0);
+            hab = m * fabs(d);
+        }
+        dQ = -dP;
+    }
+}
+
+// The dL/dv slot of the record at LDS address a, plus Extra bytes (the
+// dL/dt slot at Extra + kAdjGtOffset), for gb = V0 - R0/2. Extra becomes a
+// constant offset of the atomic.
+template <uint32_t Extra>
+__device__ __forceinline__ lds_f64 *grad_slot(uint32_t a, uint32_t gb)
+{
+    return (lds_f64 *)(size_t)((a >> 1) + gb + Extra);
+}
+
+__device__ __forceinline__ void lds_add(lds_f64 *p, double x)
+{
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One step: the cell [x, y) closes, E (the piece ending at y, P on equal
+// times) adds its value gradient and the time gradient of y to its slots.
+// h(vE, vO) = h(vP, vQ) by symmetry, so E's own value is needed only in the
+// tie branch (where E = P). At a tie the first step adds the mean one-sided
+// derivatives of both breakpoints and carries O's next value vON as Q's
+// value: the second, width-0 step (which ends O) then adds
+// h(vN, vON) - h(vON, vN) = 0 to O's time slot and nothing to any value
+// gradient, and O's value is not used after it. A run that begins with such
+// a second half subtracts that step's own term at its start (adj_begin).
+// Width-0 steps past the sentinel only reach dropped slots.
+template <int K, int HK>
+__device__ __forceinline__ void adj_step(AdjChain &ch, double p)
+{
+    const double S = sentinel<double>();
+    const double tP = ch.P.x, vP = ch.P.y, tQ = ch.tQ, vQ = ch.vQ;
+    const double y = min_raw(tP, tQ);
+    const double w = y - ch.x;
+    ch.x = y;
+    double dP, dQ, hPQ;
+    step_terms<HK>(vP, vQ, p, dP, dQ, hPQ);
+    const double gP = dP * w;  // P was loaded by the previous step
+    const double gQ = fma(dQ, w, ch.gQ);
+    const bool c = tP <= tQ;
+    const double vO = c ? vQ : vP;
+    const double gE = c ? gP : gQ, gO = c ? gQ : gP;
+    const uint32_t aQ = ch.w.S - ch.w.q;  // Q's record address at this step
+    const d2 N = ch.w.template advance<K>(c);
+    // E's record address is the walk's q plus K records
+    lds_add(grad_slot<K * 8>(ch.w.q, ch.gb), ch.Wv * gE);
+    double dE = hPQ - hval<double, HK>(N.y, vO, p);
+    double vOc = vO;
+    if (tP == tQ && y < S) {
+        // both break at y (E = P, O = Q): the mean of the one-sided
+        // derivatives for both
+        const double vON = ((lds_d2)(size_t)(aQ + (uint32_t)sizeof(Rec<double>)))->y;
+        dE = 0.5 * (dE + hdiff<HK>(vP, N.y, vON, p));
+        const double dO = 0.5 * (hdiff<HK>(vQ, vON, vP, p) + hdiff<HK>(vQ, vON, N.y, p));
+        lds_add(grad_slot<kAdjGtOffset>(aQ, ch.gb), ch.Wt * dO);
+        vOc = vON;
+    }
+    lds_add(grad_slot<K * 8 + kAdjGtOffset>(ch.w.q, ch.gb), ch.Wt * dE);
+    ch.P = N;
+    ch.tQ = max_raw(tP, tQ);
+    ch.vQ = vOc;
+    ch.gQ = gO;
+}
+
+template <int HK, int... Ks>
+__device__ __forceinline__ void adj_block(AdjChain &ch, double p,
+                                          std::integer_sequence<int, Ks...>)
+{
+    (adj_step<Ks, HK>(ch, p), ...);
+    ch.w.end_block();
+}
+
+// The value gradients of the two current pieces (at a block boundary, where
+// the walk's q is P's record address).
+__device__ __forceinline__ void adj_flush(const AdjChain &ch)
+{
+    lds_add(grad_slot<0>(ch.w.S - ch.w.q, ch.gb), ch.Wv * ch.gQ);  // P's is 0 (just loaded)
 }
 
 __device__ __forceinline__ int32_t adj_pair_steps(int32_t na, int32_t nb)
@@ -178,58 +311,26 @@ __device__ __forceinline__ int32_t adj_pair_steps(int32_t na, int32_t nb)
 }
 
 template <int HK>
-__device__ __forceinline__ void adj_step(AdjChain &ch, const d2 *lv, double *lgt,
-                                         double *lgv, double p)
+__device__ __forceinline__ void adj_load(AdjChain &ch, const Rec<double> *lrec, int32_t iP,
+                                         int32_t iQ, double p)
 {
-    const double tP = ch.P.x, tQ = ch.Q.x, vP = ch.P.y, vQ = ch.Q.y;
-    const double y = adj_min(tP, tQ);
-    const double w = y - ch.x;
-    ch.x = y;
-    ch.gP = fma(dhda<HK>(vP, vQ, p), w, ch.gP);
-    ch.gQ = fma(dhda<HK>(vQ, vP, p), w, ch.gQ);
-    const bool c = tP <= tQ;
-    // E: the piece that ends at y, O: the one that goes on
-    const int32_t iE = c ? ch.iP : ch.iQ, iO = c ? ch.iQ : ch.iP;
-    const double vE = c ? vP : vQ, vO = c ? vQ : vP;
-    const double gE = c ? ch.gP : ch.gQ, gO = c ? ch.gQ : ch.gP;
-    const double tO = adj_max(tP, tQ);
-    const d2 N = lv[iE + 1];
-    atomicAdd(&lgv[iE], ch.W * gE);
-    // time gradient of E's breakpoint y (slot iE + 1); a zero-width step is
-    // the second half of a tie, handled at the tie
-    if (w > 0.0) {
-        const double vN = N.y;
-        double dE;
-        if (tO == y) {
-            // O breaks at y too: mean of the one-sided derivatives, for both
-            const double vON = lv[iO + 1].y;
-            dE = 0.5 * (hval<double, HK>(vE, vON, p) - hval<double, HK>(vN, vON, p) +
-                        hval<double, HK>(vE, vO, p) - hval<double, HK>(vN, vO, p));
-            const double dO =
-                0.5 * (hval<double, HK>(vO, vN, p) - hval<double, HK>(vON, vN, p) +
-                       hval<double, HK>(vO, vE, p) - hval<double, HK>(vON, vE, p));
-            atomicAdd(&lgt[iO + 1], ch.W * dO);
-        } else {
-            dE = hval<double, HK>(vE, vO, p) - hval<double, HK>(vN, vO, p);
-        }
-        atomicAdd(&lgt[iE + 1], ch.W * dE);
-    }
-    ch.P = N;
-    ch.iP = iE + 1;
-    ch.gP = 0.0;
-    ch.Q.x = tO;
-    ch.Q.y = vO;
-    ch.iQ = iO;
-    ch.gQ = gO;
+    ch.w.set(lrec, iP, iQ);
+    ch.P = LdsWalk<double>::at(lrec, iP);
+    const d2 Q = LdsWalk<double>::at(lrec, iQ);
+    ch.tQ = Q.x;
+    ch.vQ = Q.y;
+    ch.gQ = 0.0;
 }
 
-// Starting state at step d of pair k (merge-path split), weight from sh.part.
+// Starting state at step d of pair k (merge-path split), weights from
+// sh.part.
+template <int HK>
 __device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
                                           const Rec<double> *lrec, int32_t k,
-                                          int64_t d, int32_t C)
+                                          int64_t d, int32_t C, double p)
 {
-    const d2 *lv = reinterpret_cast<const d2 *>(lrec);
     const int r = div_by_c(k, sh.cmag), c = k - r * C;
+    ch.k = k;
     ch.r = r;
     ch.c = c;
     ch.rb = sh.rb[r];
@@ -239,26 +340,35 @@ __device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
     int32_t i0, j0;
     double x;
     pair_start<double>(lrec, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
-    ch.iP = i0;
-    ch.iQ = j0;
-    ch.P = lv[i0];
-    ch.Q = lv[j0];
+    adj_load<HK>(ch, lrec, i0, j0, p);
     ch.x = x;
-    ch.gP = 0.0;
-    ch.gQ = 0.0;
-    ch.W = sh.part[k];
+    ch.Wt = sh.part[k];
+    ch.Wv = ch.Wt * gunit<HK>(p);
     ch.left = adj_pair_steps(ch.rn, ch.cn) - (int32_t)d;
+    if (x > 0.0 && x < sentinel<double>() && min_raw(ch.P.x, ch.tQ) == x) {
+        // the run starts at the width-0 second half of a tie, whose time
+        // gradients the run before added in full: this step's own term
+        // (as adj_step computes it) is subtracted in advance
+        const bool c0 = ch.P.x <= ch.tQ;
+        const uint32_t aE = c0 ? ch.w.q : ch.w.S - ch.w.q;
+        const double vO0 = c0 ? ch.vQ : ch.P.y;
+        const double vN0 = ((lds_d2)(size_t)(aE + (uint32_t)sizeof(Rec<double>)))->y;
+        double dP, dQ, hPQ;
+        step_terms<HK>(ch.P.y, ch.vQ, p, dP, dQ, hPQ);
+        const double dE = hPQ - hval<double, HK>(vN0, vO0, p);
+        lds_add(grad_slot<kAdjGtOffset>(aE, ch.gb), -(ch.Wt * dE));
+    }
 }
 
-// Next pair with steps (row-major pair order; see chain_next_pair of the
-// forward kernel).
+// Next pair with steps (row-major pair order, as the forward chain).
+template <int HK>
 __device__ __forceinline__ void adj_next_pair(AdjChain &ch, const TileShared &sh,
                                               const Rec<double> *lrec, int32_t C,
-                                              bool diag, int gram)
+                                              bool diag, int gram, double p)
 {
-    const d2 *lv = reinterpret_cast<const d2 *>(lrec);
-    int32_t r = ch.r, c = ch.c, rb = ch.rb, rn = ch.rn, cb = ch.cb, cn = ch.cn;
+    int32_t k = ch.k, r = ch.r, c = ch.c, rb = ch.rb, rn = ch.rn, cb = ch.cb, cn = ch.cn;
     do {
+        ++k;
         if (c + 1 < C) {
             cb += cn + kPad;
             ++c;
@@ -268,52 +378,45 @@ __device__ __forceinline__ void adj_next_pair(AdjChain &ch, const TileShared &sh
             ++r;
             rn = sh.rn[r];
             c = diag ? (gram ? r : r + 1) : 0;
+            k = r * C + c;
             cb = sh.cb[c];
             cn = sh.cn[c];
         }
     } while (adj_pair_steps(rn, cn) == 0);
+    ch.k = k;
     ch.r = r;
     ch.c = c;
     ch.rb = rb;
     ch.rn = rn;
     ch.cb = cb;
     ch.cn = cn;
-    ch.iP = rb;
-    ch.iQ = cb;
-    ch.P = lv[rb];
-    ch.Q = lv[cb];
+    adj_load<HK>(ch, lrec, rb, cb, p);
     ch.x = 0.0;
-    ch.gP = 0.0;
-    ch.gQ = 0.0;
-    ch.W = sh.part[r * C + c];
+    ch.Wt = sh.part[k];
+    ch.Wv = ch.Wt * gunit<HK>(p);
     ch.left = adj_pair_steps(rn, cn);
 }
 
 template <int HK>
 __device__ __forceinline__ void adj_lane_chain(const TileShared &sh,
-                                               const Rec<double> *lrec, double *lgt,
-                                               double *lgv, int64_t s, int64_t e,
-                                               int32_t k, int32_t C, bool diag,
-                                               int gram, double p)
+                                               const Rec<double> *lrec, uint32_t gb,
+                                               int64_t s, int64_t e, int32_t k, int32_t C,
+                                               bool diag, int gram, double p)
 {
-    const d2 *lv = reinterpret_cast<const d2 *>(lrec);
     AdjChain ch;
+    ch.gb = gb;
     // (an LDS tile: its step prefix is the 32-bit one)
-    adj_begin(ch, sh, lrec, k, s - sh.pw[k], C);
+    adj_begin<HK>(ch, sh, lrec, k, s - sh.pw[k], C, p);
     for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
         if (ch.left == 0) {
-            atomicAdd(&lgv[ch.iP], ch.W * ch.gP);
-            atomicAdd(&lgv[ch.iQ], ch.W * ch.gQ);
-            adj_next_pair(ch, sh, lrec, C, diag, gram);
+            adj_flush(ch);
+            adj_next_pair<HK>(ch, sh, lrec, C, diag, gram, p);
         }
-#pragma unroll
-        for (int u = 0; u < kStepBlock; ++u)
-            adj_step<HK>(ch, lv, lgt, lgv, p);
+        adj_block<HK>(ch, p, std::make_integer_sequence<int, kStepBlock>{});
         ch.left -= kStepBlock;
     }
-    // the pieces going on past this run: their gradients so far
-    atomicAdd(&lgv[ch.iP], ch.W * ch.gP);
-    atomicAdd(&lgv[ch.iQ], ch.W * ch.gQ);
+    // the piece going on past this run: its gradient so far
+    adj_flush(ch);
 }
 
 template <int HK>
@@ -327,8 +430,11 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     const WsHeader &h = hdr_of(args.ws);
     Rec<double> *lrec = reinterpret_cast<Rec<double> *>(smem);
     int64_t *pw64 = reinterpret_cast<int64_t *>(lrec);  // wide step prefix
-    // gradient slots (gt, gv) follow the record slots
-    double *lg = reinterpret_cast<double *>(lrec + h.lds_records);
+    // gradient slots follow the records: dL/dv of record q at lg[q], dL/dt
+    // of its end time at lg[kAdjLdsRecords + q] (kAdjLdsRecords records a
+    // tile)
+    double *lg = reinterpret_cast<double *>(lrec + kAdjLdsRecords);
+    const uint32_t gb = lds_address(lg) - (lds_address(lrec) >> 1);
     const Rec<double> *grec = reinterpret_cast<const Rec<double> *>(args.ws + h.off_rec);
     const int64_t *offsets = args.offsets;
     const int tid = threadIdx.x;
@@ -337,17 +443,22 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     PhaseClock pc;  // (cycle counters only in timing builds)
     TileLoop loop;
     loop.start<double, true>(sh, args.ws, offsets, lrec, grec);
+    pc.mark(-1);
     while (loop.live(sh, args.ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
-        tile_scan<double>(sh, D, args.gram, gmode ? grec : lrec, pw64, pc);
+        tile_scan<double, kWeightsAdjoint>(sh, D, args.gram, gmode ? grec : lrec, pw64, pc);
         const int32_t R = D.R, C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = pw_at(sh, pw64, npairs);
+        pc.mark(kPhaseScan);
+        pc.tile(total);
         const int64_t nslots = diag ? D.rrecs : D.rrecs + D.crecs;
         if (!gmode)
-            for (int64_t q = tid; q < 2 * nslots; q += kThreads)
+            for (int64_t q = tid; q < nslots; q += kThreads) {
                 lg[q] = 0.0;
+                lg[kAdjLdsRecords + q] = 0.0;
+            }
         // pair weights: W = (G_ij + G_ji) * chain for i != j, G_ii on the
         // diagonal; stored in the partial-sum slots (unused here)
         if (tid < npairs) {
@@ -367,13 +478,13 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         }
         sync_lds();
         loop.take_next(args.ws);
+        pc.mark(kPhaseStart);
 
         // this lane's share of the tile's steps
         int64_t s, e;
         lane_steps(sh, tid, total, s, e);
         if (s < e && !gmode) {
-            adj_lane_chain<HK>(sh, lrec, lg, lg + nslots, s, e, sh.pairof[tid], C,
-                               diag, args.gram, p);
+            adj_lane_chain<HK>(sh, lrec, gb, s, e, sh.pairof[tid], C, diag, args.gram, p);
         } else if (s < e) {
             int32_t k = sh.pairof[tid];
             int64_t d = s - pw_at(sh, pw64, k);
@@ -382,26 +493,16 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 const int64_t len = pw_at(sh, pw64, k + 1) - pw_at(sh, pw64, k);
                 const int64_t m = (len - d < e - s) ? len - d : e - s;
                 const int32_t A = sh.rb[r], B = sh.cb[c];
+                // global record index -> CSR row: row = record - i * kPad
+                const int64_t i = D.r_lo + r, j = D.c_lo + c;
                 GradSink sa, sb;
                 sa.last = A + sh.rn[r] - 1;
                 sb.last = B + sh.cn[c] - 1;
-                if (gmode) {
-                    // global record index -> CSR row: row = record - i * kPad
-                    const int64_t i = D.r_lo + r, j = D.c_lo + c;
-                    sa.gt = args.grad_t - i * kPad;
-                    sa.gv = args.grad_v - i * kPad;
-                    sb.gt = args.grad_t - j * kPad;
-                    sb.gv = args.grad_v - j * kPad;
-                    adjoint_pair<HK>(grec, A, sh.rn[r], B, sh.cn[c], d, m,
-                                     sh.part[k], p, sa, sb);
-                } else {
-                    sa.gt = lg;
-                    sa.gv = lg + nslots;
-                    sb.gt = lg;
-                    sb.gv = lg + nslots;
-                    adjoint_pair<HK>(lrec, A, sh.rn[r], B, sh.cn[c], d, m,
-                                     sh.part[k], p, sa, sb);
-                }
+                sa.gt = args.grad_t - i * kPad;
+                sa.gv = args.grad_v - i * kPad;
+                sb.gt = args.grad_t - j * kPad;
+                sb.gv = args.grad_v - j * kPad;
+                adjoint_pair<HK>(grec, A, sh.rn[r], B, sh.cn[c], d, m, sh.part[k], p, sa, sb);
                 s += m;
                 d = 0;
                 ++k;
@@ -409,48 +510,99 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                     ++k;
             }
         }
+        pc.mark(kPhaseMerge);
+        // the next tile's staging loads, issued as soon as this wave's merge
+        // work is done (into registers: the records are stored to LDS after
+        // the accumulator flush, which reads the current block metadata)
+        const bool has_next = loop.has_next(sh, args.ws);
+        StageRegs<double, false, kAdjStageUnroll> next;
+        if (has_next)
+            stage_load<double, false, kAdjStageUnroll>(next, sh.desc[loop.nxt()], grec,
+                                                      offsets, lrec);
         sync_lds();
+        pc.mark(kPhaseMergeWait);
         loop.decode_next(sh, args.ws, offsets);
+        pc.mark(kPhaseStageIssue);
 
-        // add the tile's accumulators to the outputs; slot 0 of a PCF's
-        // time gradient (t_0) and the last value stay untouched (fixed)
-        if (!gmode) {
-            for (int64_t q = tid; q < nslots; q += kThreads) {
-                const bool in_rows = q < D.rrecs;
-                const int64_t base = in_rows ? D.rrec0 : D.crec0;
-                const int64_t lq = in_rows ? q : q - D.rrecs;
-                const int64_t rec = base + lq;           // global record index
-                // PCF of this record: the block's PCF whose record range
-                // holds it
-                const int32_t nb = in_rows ? R : C;
-                const int32_t *bs = in_rows ? sh.rb : sh.cb;
-                const int32_t *ns = in_rows ? sh.rn : sh.cn;
-                const int64_t pcf0 = in_rows ? D.r_lo : D.c_lo;
-                // last PCF of the block whose records start at or before q
-                int32_t which = 0, hi = nb - 1;
-                while (which < hi) {
-                    const int32_t mid = (which + hi + 1) >> 1;
-                    if (bs[mid] <= q)
-                        which = mid;
-                    else
-                        hi = mid - 1;
-                }
-                const int64_t kk = q - bs[which];  // record within the PCF
-                if (kk >= ns[which])
-                    continue;                      // padding
-                const int64_t row = rec - (pcf0 + which) * kPad;
-                const double gtv = lg[q], gvv = lg[nslots + q];
-                if (kk >= 1 && gtv != 0.0)
-                    atomicAdd(&args.grad_t[row], gtv);
-                if (kk + 1 < ns[which] && gvv != 0.0)
-                    atomicAdd(&args.grad_v[row], gvv);
+        // the tile's accumulators, read before the next tile's block
+        // metadata is stored and added to the outputs after it (so that the
+        // staging's wait for its loads does not also wait for these atomics);
+        // t_0 and the last value of each PCF stay untouched (fixed). A slot
+        // q holds record q's value gradient and its end time's gradient.
+        static_assert(kAdjStageUnroll * kThreads >= kAdjLdsRecords, "slots per thread");
+        double fv[kAdjStageUnroll], ft[kAdjStageUnroll];
+        int64_t frow[kAdjStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kAdjStageUnroll; ++u) {
+            const int64_t q = tid + u * kThreads;
+            frow[u] = -1;
+            fv[u] = ft[u] = 0.0;
+            if (gmode || q >= nslots)
+                continue;
+            const bool in_rows = q < D.rrecs;
+            const int64_t base = in_rows ? D.rrec0 : D.crec0;
+            const int64_t lq = in_rows ? q : q - D.rrecs;
+            const int64_t rec = base + lq;  // global record index
+            // PCF of this record: the last PCF of its block whose records
+            // start at or before q
+            const int32_t nb = in_rows ? R : C;
+            const int32_t *bs = in_rows ? sh.rb : sh.cb;
+            const int32_t *ns = in_rows ? sh.rn : sh.cn;
+            const int64_t pcf0 = in_rows ? D.r_lo : D.c_lo;
+            int32_t which = 0, hi = nb - 1;
+            while (which < hi) {
+                const int32_t mid = (which + hi + 1) >> 1;
+                if (bs[mid] <= q)
+                    which = mid;
+                else
+                    hi = mid - 1;
             }
+            const int64_t kk = q - bs[which];  // record within the PCF
+            // padding, and the last record (fixed value, sentinel end time)
+            if (kk + 1 >= ns[which])
+                continue;
+            frow[u] = rec - (pcf0 + which) * kPad;
+            fv[u] = lg[q];
+            ft[u] = lg[kAdjLdsRecords + q];
         }
-        // (the accumulator flush reads the block metadata)
-        loop.stage_next<double, true>(sh, args.ws, grec, offsets, lrec, true);
+        pc.mark(kPhaseFinish);
+        if (has_next) {
+            sync_lds();  // (the slot reads above use the block metadata)
+            stage_store<double, false, kAdjStageUnroll>(sh, next, sh.desc[loop.nxt()], lrec);
+        }
+#pragma unroll
+        for (int u = 0; u < kAdjStageUnroll; ++u) {
+            if (frow[u] < 0)
+                continue;
+            if (fv[u] != 0.0)
+                atomicAdd(&args.grad_v[frow[u]], fv[u]);
+            if (ft[u] != 0.0)
+                atomicAdd(&args.grad_t[frow[u] + 1], ft[u]);  // the piece's end time
+        }
+        pc.mark(kPhaseStageStore);
         loop.advance();
+        pc.mark(kPhaseAdvance);
     }
+    pc.flush((tid & 63) == 0 ? tid >> 6 : -1);
 }
+
+#ifdef PCF_PHASE_TIMING
+// Timing builds only: the adjoint kernel's per-phase cycle sums (its own
+// copy of the counters), as pcf_debug_phase.
+extern "C" int pcf_debug_phase_adjoint(unsigned long long *host, int reset)
+{
+    if (hipMemcpyFromSymbol(host, HIP_SYMBOL(pcf::g_phase_cycles),
+                            sizeof(pcf::g_phase_cycles)) != hipSuccess)
+        return -1;
+    if (reset) {
+        static const unsigned long long zero[sizeof(pcf::g_phase_cycles) / 8] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(pcf::g_phase_cycles), zero, sizeof(zero)) !=
+            hipSuccess)
+            return -2;
+    }
+    return 0;
+}
+#endif
 
 // Zero a double array (a kernel, so that captured graphs replay it).
 __global__ void zero_doubles(double *p, int64_t n)

@@ -27,6 +27,16 @@ constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
 #define PCF_LDSREC (136 * 1024)
 #endif
 constexpr int kLdsRecordBytes = PCF_LDSREC;
+// The adjoint (FP64 records) keeps two FP64 gradient slots per record in two
+// arrays after its records, dL/dv then dL/dt (8-byte strides, so that random
+// slots spread over the LDS banks): kAdjLdsRecords records a tile, and
+// kAdjGtOffset bytes from a record's dL/dv slot to its dL/dt slot (a
+// constant offset of the LDS atomics, which holds 16 bits).
+constexpr int kAdjLdsRecords = kLdsRecordBytes / 32;
+constexpr uint32_t kAdjGtOffset = (uint32_t)kAdjLdsRecords * 8;
+static_assert(kAdjGtOffset + 8 * 8 <= 65535, "adjoint LDS layout");
+// Records per thread when the adjoint stages a tile through registers.
+constexpr int kAdjStageUnroll = (kAdjLdsRecords + kThreads - 1) / kThreads;
 
 // Rows a PCF may have (exclusive): keeps a pair's merge steps below 2^31.
 constexpr int64_t kMaxRows = (int64_t)1 << 30;

@@ -133,75 +133,6 @@ __global__ void validate_rows(const int64_t *__restrict__ offsets, int64_t n,
 // step: one full-wave LDS read, no divergent branch. The end time of the
 // piece that goes on is max(P.t, Q.t), which saves two selects.
 
-// v_min / v_max without the quieting of signalling NaNs that fmin/fmax
-// would add (the data contract excludes NaN).
-__device__ __forceinline__ double min_raw(double a, double b)
-{
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ float min_raw(float a, float b)
-{
-    float r;
-    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double max_raw(double a, double b)
-{
-    double r;
-    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ float max_raw(float a, float b)
-{
-    float r;
-    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-
-// Record addresses of a chain's two pieces. Global mode keeps both
-// pointers. LDS mode keeps one 32-bit address and a sum instead: every step
-// loads exactly one record, the successor of the piece that ends, so
-// addr(P) + addr(Q) grows by one record per step. With S that sum at the
-// start of a block of kStepBlock steps and q = addr(P) - k * rec at step k
-// of the block (rec = record bytes), addr(Q) - k * rec = |S - q| - k * rec
-// (one v_sad_u32); the ending piece's address minus k * rec is a select of
-// the two and becomes the next q, and its successor is read at that plus
-// (k + 1) * rec, a constant offset of the LDS read. Two VALU instructions
-// per step instead of three.
-template <typename T> struct LdsWalk {
-    typedef typename RecVec<T>::type V;
-    typedef const __attribute__((address_space(3))) V *ptr;
-    static constexpr uint32_t kRec = sizeof(Rec<T>);
-    uint32_t q, S;
-
-    __device__ __forceinline__ void set(const Rec<T> *base, int32_t iP, int32_t iQ)
-    {
-        q = lds_address(base + iP);
-        S = q + lds_address(base + iQ);
-    }
-    __device__ __forceinline__ static V at(const Rec<T> *base, int32_t i)
-    {
-        return *(ptr)(size_t)lds_address(base + i);
-    }
-    template <int K>
-    __device__ __forceinline__ V advance(bool p_ends)
-    {
-        uint32_t b;
-        asm("v_sad_u32 %0, %1, %2, %3"
-            : "=v"(b)
-            : "v"(S), "v"(q), "s"((uint32_t)(0u - K * kRec)));
-        const uint32_t m = p_ends ? q : b;
-        q = m;
-        return *(ptr)(size_t)(m + (uint32_t)(K + 1) * kRec);
-    }
-    __device__ __forceinline__ void end_block()
-    {
-        q += kStepBlock * kRec;
-        S += kStepBlock * kRec;
-    }
-};
 template <typename T> struct GlobalWalk {
     typedef typename RecVec<T>::type V;
     const V *pP, *pQ;
@@ -510,10 +441,12 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
 
 size_t tile_shared_bytes(int rec_bytes, bool backward)
 {
-    const int per = rec_bytes + (backward ? 16 : 0);
     // the forward kernel keeps its tile state at the start of the dynamic
-    // LDS, the adjoint in static LDS
-    return (size_t)(backward ? 0 : kSharedHead) + (size_t)(kLdsRecordBytes / per) * per;
+    // LDS, the adjoint in static LDS (with two FP64 gradient slots per
+    // record after its records)
+    if (backward)
+        return (size_t)kAdjLdsRecords * (16 + 16);
+    return (size_t)kSharedHead + (size_t)(kLdsRecordBytes / rec_bytes) * rec_bytes;
 }
 
 template <typename T>

@@ -8,9 +8,11 @@ namespace pcf {
 
 int64_t lds_record_capacity(int rec_bytes, bool backward)
 {
-    // the adjoint keeps two FP64 gradient accumulators per record slot
-    const int64_t per = rec_bytes + (backward ? 16 : 0);
-    return kLdsRecordBytes / per;
+    // the adjoint (FP64) keeps two FP64 gradient accumulators per record
+    // slot, at a fixed distance from the records
+    if (backward)
+        return kAdjLdsRecords;
+    return kLdsRecordBytes / rec_bytes;
 }
 
 int64_t block_budget(int rec_bytes, bool backward, const TileShape &shape)

@@ -444,6 +444,76 @@ template <typename T> struct RecVec;
 template <> struct RecVec<double> { typedef d2v type; };
 template <> struct RecVec<float> { typedef f2v type; };
 
+// v_min / v_max without the quieting of signalling NaNs that fmin/fmax
+// would add (the data contract excludes NaN).
+__device__ __forceinline__ double min_raw(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float min_raw(float a, float b)
+{
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double max_raw(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float max_raw(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Record addresses of a chain's two pieces. Global mode keeps both
+// pointers. LDS mode keeps one 32-bit address and a sum instead: every step
+// loads exactly one record, the successor of the piece that ends, so
+// addr(P) + addr(Q) grows by one record per step. With S that sum at the
+// start of a block of kStepBlock steps and q = addr(P) - k * rec at step k
+// of the block (rec = record bytes), addr(Q) - k * rec = |S - q| - k * rec
+// (one v_sad_u32); the ending piece's address minus k * rec is a select of
+// the two and becomes the next q, and its successor is read at that plus
+// (k + 1) * rec, a constant offset of the LDS read. Two VALU instructions
+// per step instead of three.
+template <typename T> struct LdsWalk {
+    typedef typename RecVec<T>::type V;
+    typedef const __attribute__((address_space(3))) V *ptr;
+    static constexpr uint32_t kRec = sizeof(Rec<T>);
+    uint32_t q, S;
+
+    __device__ __forceinline__ void set(const Rec<T> *base, int32_t iP, int32_t iQ)
+    {
+        q = lds_address(base + iP);
+        S = q + lds_address(base + iQ);
+    }
+    __device__ __forceinline__ static V at(const Rec<T> *base, int32_t i)
+    {
+        return *(ptr)(size_t)lds_address(base + i);
+    }
+    template <int K>
+    __device__ __forceinline__ V advance(bool p_ends)
+    {
+        uint32_t b;
+        asm("v_sad_u32 %0, %1, %2, %3"
+            : "=v"(b)
+            : "v"(S), "v"(q), "s"((uint32_t)(0u - K * kRec)));
+        const uint32_t m = p_ends ? q : b;
+        q = m;
+        return *(ptr)(size_t)(m + (uint32_t)(K + 1) * kRec);
+    }
+    __device__ __forceinline__ void end_block()
+    {
+        q += kStepBlock * kRec;
+        S += kStepBlock * kRec;
+    }
+};
+
 // Direct staging (`Direct`, FP64 records only) moves records straight from
 // global memory to LDS (global_load_lds_dwordx4: each lane's record lands at
 // the wave's LDS base plus 16 bytes per lane), with no register round trip
@@ -452,22 +522,21 @@ template <> struct RecVec<float> { typedef f2v type; };
 // LDS object), so it pays where staging is not overlapped with other LDS
 // work (the adjoint); the forward kernel stages through registers, with the
 // loads in flight while it finishes the current tile.
-template <typename T, bool Direct>
+template <typename T, bool Direct, int U = stage_unroll<T>()>
 struct StageRegs {
     static_assert(!Direct || sizeof(Rec<T>) == 16, "direct staging moves 16-byte records");
-    typename RecVec<T>::type r[Direct ? 1 : stage_unroll<T>()];
+    typename RecVec<T>::type r[Direct ? 1 : U];
     int64_t m0, m1;
 };
 
 // Loads of tile d's staging: its records (row block, then column block
 // unless diagonal; none in global mode) and the block metadata.
-template <typename T, bool Direct>
-__device__ __forceinline__ void stage_load(StageRegs<T, Direct> &g, const TileDesc &d,
+template <typename T, bool Direct, int U = stage_unroll<T>()>
+__device__ __forceinline__ void stage_load(StageRegs<T, Direct, U> &g, const TileDesc &d,
                                            const Rec<T> *grec,
                                            const int64_t *offsets, Rec<T> *lrec)
 {
     typedef typename RecVec<T>::type V;
-    constexpr int U = stage_unroll<T>();
     const int tid = threadIdx.x;
     const int64_t rrecs = d.rrecs, rrec0 = d.rrec0, crec0 = d.crec0;
     const int64_t total = d.global_mode ? 0 : (d.diag ? rrecs : rrecs + d.crecs);
@@ -516,11 +585,10 @@ __device__ __forceinline__ void stage_load(StageRegs<T, Direct> &g, const TileDe
 }
 
 // LDS stores of tile d's staging (after stage_load on the same thread).
-template <typename T, bool Direct>
-__device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T, Direct> &g,
+template <typename T, bool Direct, int U = stage_unroll<T>()>
+__device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T, Direct, U> &g,
                                             const TileDesc &d, Rec<T> *lrec)
 {
-    constexpr int U = stage_unroll<T>();
     const int tid = threadIdx.x;
     const int64_t rrecs = d.rrecs;
     const int64_t total = d.global_mode ? 0 : (d.diag ? rrecs : rrecs + d.crecs);
@@ -572,19 +640,26 @@ __device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T, D
 constexpr int kGroups = kThreads / 256;
 constexpr int kGroupLanes = 256;
 // Weights measured on MI355X (per-wave completion times of equal runs):
-// FP64 records, FP32 records.
-constexpr int64_t kGroupWeights[2][4] = {{66, 61, 53, 38}, {64, 60, 55, 45}};
+// forward FP64 records, forward FP32 records, the adjoint (FP64; its waves
+// differ more in speed, older waves winning the LDS atomics and issue).
+constexpr int kWeightsF64 = 0, kWeightsF32 = 1, kWeightsAdjoint = 2;
+constexpr int64_t kGroupWeights[3][4] = {{66, 61, 53, 38}, {64, 60, 55, 45}, {83, 62, 44, 29}};
 template <typename T>
+constexpr int forward_weights()
+{
+    return sizeof(T) == 4 ? kWeightsF32 : kWeightsF64;
+}
+template <int WS>
 __device__ __forceinline__ int64_t group_weight(int g)
 {
-    return kGroupWeights[sizeof(T) == 4][g];
+    return kGroupWeights[WS][g];
 }
-template <typename T>
+template <int WS>
 constexpr int64_t weight_sum()
 {
     int64_t w = 0;
     for (int g = 0; g < kGroups; ++g)
-        w += kGroupWeights[sizeof(T) == 4][g];
+        w += kGroupWeights[WS][g];
     return w;
 }
 
@@ -598,7 +673,7 @@ __device__ __forceinline__ int32_t quot_small(int32_t a, int32_t b)
     return j;
 }
 
-template <typename T>
+template <int WS>
 struct LaneSplit {
     int64_t per[kGroups], base[kGroups + 1];
 
@@ -606,13 +681,13 @@ struct LaneSplit {
     {
         // groups before the last: their share rounded to whole blocks; the
         // last group takes the rest (rounded up)
-        constexpr int64_t kUnit = kGroupLanes * weight_sum<T>();
+        constexpr int64_t kUnit = kGroupLanes * weight_sum<WS>();
         base[0] = 0;
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
             int64_t p;
             if (g + 1 < kGroups) {
-                p = (total * group_weight<T>(g) + kUnit * kStepBlock / 2) /
+                p = (total * group_weight<WS>(g) + kUnit * kStepBlock / 2) /
                     (kUnit * kStepBlock) * kStepBlock;
             } else {
                 const int64_t rest = total - base[g];
@@ -627,14 +702,14 @@ struct LaneSplit {
     // in FP64 (the same instructions on every lane, so the same split)
     __device__ __forceinline__ void make_small(int32_t total)
     {
-        constexpr double kInv = 1.0 / (double)(kGroupLanes * weight_sum<T>() * kStepBlock);
+        constexpr double kInv = 1.0 / (double)(kGroupLanes * weight_sum<WS>() * kStepBlock);
         int32_t b = 0;
         base[0] = 0;
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
             int32_t p;
             if (g + 1 < kGroups) {
-                p = (int32_t)rint((double)total * (double)group_weight<T>(g) * kInv) *
+                p = (int32_t)rint((double)total * (double)group_weight<WS>(g) * kInv) *
                     kStepBlock;
             } else {
                 const int32_t rest = total - b > 0 ? total - b : 0;
@@ -703,7 +778,7 @@ static_assert((int64_t)kMaxBlock * (kLdsRecordBytes / 8) + 8 * (int64_t)kMaxPair
 // of every PCF of the tile (sh.rlast, clast),
 // read from `src` (the LDS records, or the packed records in global mode).
 // Needs the staged tile; ends with a barrier.
-template <typename T>
+template <typename T, int WS = forward_weights<T>()>
 __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
                                           int gram, const Rec<T> *src, int64_t *pw64,
                                           PhaseClock &pc)
@@ -728,7 +803,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
     // 32-bit work when the tile's step total certainly stays below 2^30
     // (LDS tiles)
     int64_t total;
-    LaneSplit<T> sp;
+    LaneSplit<WS> sp;
     const int64_t bound = (int64_t)C * d.rrecs + (int64_t)d.R * d.crecs +
                           (int64_t)kStepBlock * npairs;
     if (bound < ((int64_t)1 << 30)) {
@@ -766,7 +841,7 @@ __device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
                 const int64_t lo = excl > sp.base[g] ? excl : sp.base[g];
                 const int64_t hi = excl + wp < sp.base[g + 1] ? excl + wp : sp.base[g + 1];
                 if (lo < hi) {
-                    for (int64_t j = LaneSplit<T>::quot(lo - sp.base[g] + sp.per[g] - 1,
+                    for (int64_t j = LaneSplit<WS>::quot(lo - sp.base[g] + sp.per[g] - 1,
                                                         sp.per[g]);
                          sp.base[g] + j * sp.per[g] < hi; ++j)
                         sh.pairof[g * kGroupLanes + j] = (int16_t)tid;
