@@ -23,7 +23,8 @@ from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "cdist", "cross_gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
            "integrals", "norms", "restrict", "warp", "reduce", "combine",
-           "autotune", "TILE_SHAPES", "PCF_LP", "PCF_LP_POW", "PCF_GRAM"]
+           "autotune", "TuneCache", "workload_signature", "TILE_SHAPES", "PCF_LP",
+           "PCF_LP_POW", "PCF_GRAM"]
 
 
 def _stream_handle(stream=None):
@@ -446,16 +447,115 @@ TILE_SHAPES = [(32, 2), (16, 2), (32, 3), (24, 2), (8, 2), (32, 4)]
 _TUNED = {}
 
 
-def autotune(run, key, shapes=None, reps=3):
+def _bucket(x):
+    """log2 bucket of a positive size (0 for x <= 1)."""
+    return int(math.floor(math.log2(x))) if x > 1 else 0
+
+
+def workload_signature(X, kind, p=0.0, set_offsets=None):
+    """A tuning key that groups similar workloads: dtype, kind (and for L_p
+    whether p is 1, 2 or general), and log2 buckets of the set size, of the
+    mean and of the largest row count per PCF; for a batch (``set_offsets``)
+    the number of problems and the bucket of their mean size instead of the
+    set size. Workloads in one bucket share a tuned tile shape."""
+    n = np.diff(X.offsets_host)
+    mean_rows = float(n.mean()) if len(n) else 0.0
+    pk = "gram" if kind == PCF_GRAM else ("p1" if p == 1.0 else ("p2" if p == 2.0 else "p"))
+    if kind == PCF_LP_POW:
+        pk += "pow"
+    sig = ["f64" if X.dtype == torch.float64 else "f32", pk,
+           "rows%d" % _bucket(mean_rows), "max%d" % _bucket(int(n.max()) if len(n) else 0)]
+    if set_offsets is None:
+        sig.append("n%d" % _bucket(X.n))
+    else:
+        sizes = np.diff(np.asarray(set_offsets, dtype=np.int64))
+        sig += ["b%d" % _bucket(len(sizes)), "s%d" % _bucket(float(sizes.mean()) if len(sizes) else 0)]
+    return "/".join(sig)
+
+
+class TuneCache:
+    """Tuned tile shapes kept in a JSON file across processes.
+
+    Entries are keyed by the tuning key together with the device name and a
+    digest of the loaded library, so a rebuilt library or another GPU model
+    tunes again. The default file is ``$PCF_TUNE_CACHE`` or
+    ``~/.cache/paper_2404_07183_amd/tiles.json``. An unreadable file is
+    treated as empty; writes replace the file atomically."""
+
+    def __init__(self, path=None):
+        import os
+        self.path = path or os.environ.get("PCF_TUNE_CACHE") or os.path.join(
+            os.path.expanduser("~"), ".cache", "paper_2404_07183_amd", "tiles.json")
+
+    @staticmethod
+    def context():
+        import hashlib
+        import os
+        h = hashlib.sha256()
+        with open(_lib.LIB_PATH, "rb") as f:
+            h.update(f.read())
+        dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+        return "%s|%s" % (dev, h.hexdigest()[:16])
+
+    def _load(self):
+        import json
+        try:
+            with open(self.path) as f:
+                data = json.load(f)
+            return data if isinstance(data, dict) else {}
+        except (OSError, ValueError):
+            return {}
+
+    def get(self, key, context=None):
+        e = self._load().get("%s|%s" % (context or self.context(), key))
+        if not e or "shape" not in e:
+            return None
+        shape = e["shape"]
+        return (tuple(shape) if shape is not None else None,
+                {(tuple(k) if k is not None else None): ms for k, ms in e.get("times", [])})
+
+    def put(self, key, shape, times, context=None):
+        """Stores an entry; returns False (and keeps nothing) when the file
+        cannot be written."""
+        import json
+        import os
+        data = self._load()
+        data["%s|%s" % (context or self.context(), key)] = {
+            "shape": list(shape) if shape is not None else None,
+            "times": [[list(k) if k is not None else None, v] for k, v in times.items()]}
+        tmp = "%s.tmp%d" % (self.path, os.getpid())
+        try:
+            d = os.path.dirname(self.path)
+            if d:
+                os.makedirs(d, exist_ok=True)
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+        except OSError:
+            return False
+        return True
+
+
+def autotune(run, key, shapes=None, reps=3, cache=None):
     """Pick the fastest tile shape for a workload.
 
     ``run(shape)`` must launch one call with that shape (``None`` = default)
     on the current stream. Every candidate runs once untimed (which also
     builds its plan) and ``reps`` times between HIP events; the shape with the
-    smallest mean time wins and is remembered under ``key`` for the process.
-    Returns ``(shape, {shape: ms})``."""
-    if key in _TUNED:
-        return _TUNED[key]
+    smallest mean time wins and is remembered under ``key`` for the process
+    and, with ``cache`` (a :class:`TuneCache`, or True for the default file),
+    across processes (see :func:`workload_signature` for keys that group
+    workloads by size and row-count bucket). Returns ``(shape, {shape: ms})``."""
+    if cache is True:
+        cache = TuneCache()
+    ckey = (key, cache.path if cache else None)
+    if ckey in _TUNED:
+        return _TUNED[ckey]
+    if cache:
+        hit = cache.get(str(key))
+        if hit is not None:
+            _TUNED[ckey] = hit
+            return hit
     shapes = shapes or TILE_SHAPES
     stream = torch.cuda.current_stream()
     times = {}
@@ -470,8 +570,10 @@ def autotune(run, key, shapes=None, reps=3):
         e1.synchronize()
         times[shape] = e0.elapsed_time(e1) / reps
     best = min(times, key=times.get)
-    _TUNED[key] = (best, times)
-    return _TUNED[key]
+    _TUNED[ckey] = (best, times)
+    if cache:
+        cache.put(str(key), best, times)
+    return _TUNED[ckey]
 
 
 def validate(X, stream=None):

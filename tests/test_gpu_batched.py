@@ -119,3 +119,28 @@ def test_batch_with_range_and_weight_vs_oracle():
         R, ab = oracle.entries_w(oracle.LP, 1.0, oracle.W_EXP, c, oo_, tt, vv, I.ravel(),
                                  J.ravel(), a=a, b=b, with_abs=True)
         assert np.all(np.abs(M.ravel() - R) <= 1e-12 * np.maximum(ab, 1e-300)), k
+
+
+def test_autotune_persists_across_processes(tmp_path):
+    # the first tuning runs every candidate and stores the winner for this
+    # library build and GPU; a later process (the in-process memo cleared)
+    # takes it from the file without launching anything
+    so, o, t, v = workloads.config_batched(B=16, smax=64, mean_len=40)
+    X = api.PcfSet(o, t, v, device=DEV)
+    sizes = np.diff(so)
+    out = torch.empty(int((sizes ** 2).sum()), dtype=torch.float64, device=DEV)
+    ws = api.Workspace(device=DEV)
+    calls = []
+
+    def run(shape):
+        calls.append(shape)
+        api.pairwise_batched(so, X, api.PCF_LP, 2.0, out=out, workspace=ws, shape=shape)
+    key = api.workload_signature(X, api.PCF_LP, 2.0, set_offsets=so)
+    cache = api.TuneCache(str(tmp_path / "tiles.json"))
+    shape, times = api.autotune(run, key, cache=cache, reps=2)
+    assert len(calls) == 3 * len(api.TILE_SHAPES) and shape in api.TILE_SHAPES
+    assert set(times) == set(api.TILE_SHAPES)
+    api._TUNED.clear()
+    calls.clear()
+    assert api.autotune(run, key, cache=api.TuneCache(cache.path)) == (shape, times)
+    assert calls == []
