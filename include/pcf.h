@@ -272,6 +272,33 @@ pcf_status pcf_warp_rows(const pcf_set *X, pcf_weight_kind weight, double c,
 pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
                     const int64_t *offsets_out, void *t_out, void *v_out, void *stream);
 
+/* Gradients through a range restriction and a time warp (Section 3, the
+ * remark after Algorithm "CombineIntegrate" that the integrals' parameter
+ * derivatives are analytic; Section 2.2 ranges and weights). For a loss of a
+ * matrix computed on Y = pcf_restrict(X, a, b) or Y = pcf_warp(X, weight, c),
+ * these map dL/dt and dL/dv of Y's rows (FP64 device arrays of
+ * offsets_y[n] entries each, e.g. from pcf_pairwise_backward on Y; offsets_y
+ * the device offsets that pcf_restrict_rows / pcf_warp_rows wrote) to those
+ * of X's rows (FP64 device arrays of X's row count, overwritten). With a
+ * range and a weight, apply the warp's map, then the restriction's.
+ *
+ * Restriction: a row of X kept in Y passes its two gradients on; the row
+ * holding a receives the value gradient of Y's row (a, v); the times 0, a
+ * and b, the added values, every row outside [a, b) and the last value of
+ * each PCF (a fixed parameter, as in pcf_pairwise_backward) get 0.
+ * Warp (tau = W(t)): dL/dt_k = dL/dtau_k * w(t_k) (W' = w), dL/dv_k as given;
+ * t_0 and a row dropped because its rounded tau ties the next get 0.
+ * a, b, weight and c must be those of the forward call (PCF_EINVAL as there);
+ * PCF_EINVAL for NULL pointers. Asynchronous on `stream`. */
+pcf_status pcf_restrict_backward(const pcf_set *X, double a, double b,
+                                 const int64_t *offsets_y, const void *grad_t_y,
+                                 const void *grad_v_y, void *grad_t_x, void *grad_v_x,
+                                 void *stream);
+pcf_status pcf_warp_backward(const pcf_set *X, pcf_weight_kind weight, double c,
+                             const int64_t *offsets_y, const void *grad_t_y,
+                             const void *grad_v_y, void *grad_t_x, void *grad_v_x,
+                             void *stream);
+
 /* Reductions of groups of PCFs (Section 2.1, combinations and reductions;
  * Section 4, Algorithm ReducePair and reduction trees). Group b is PCFs
  * group_offsets_host[b] .. group_offsets_host[b+1]-1 (HOST array, B+1

@@ -114,6 +114,14 @@ _SIGS = {
     "pcf_warp": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]),
+    "pcf_restrict_backward": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "pcf_warp_backward": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "pcf_single": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                   ctypes.c_void_p]),
@@ -264,6 +272,18 @@ def pcf_warp_rows(X, weight, c, offsets_out_ptr, offsets_out_host_ptr, stream):
 def pcf_warp(X, weight, c, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
     return load().pcf_warp(ctypes.byref(X), weight, c, offsets_out_ptr, t_out_ptr,
                            v_out_ptr, stream)
+
+
+def pcf_restrict_backward(X, a, b, offsets_y_ptr, gt_y_ptr, gv_y_ptr, gt_x_ptr, gv_x_ptr,
+                          stream):
+    return load().pcf_restrict_backward(ctypes.byref(X), a, b, offsets_y_ptr, gt_y_ptr,
+                                        gv_y_ptr, gt_x_ptr, gv_x_ptr, stream)
+
+
+def pcf_warp_backward(X, weight, c, offsets_y_ptr, gt_y_ptr, gv_y_ptr, gt_x_ptr, gv_x_ptr,
+                      stream):
+    return load().pcf_warp_backward(ctypes.byref(X), weight, c, offsets_y_ptr, gt_y_ptr,
+                                    gv_y_ptr, gt_x_ptr, gv_x_ptr, stream)
 
 
 def pcf_single(X, kind, p, a, b, out_ptr, stream):

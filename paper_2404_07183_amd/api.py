@@ -23,6 +23,7 @@ from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "cdist", "cross_gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
            "integrals", "norms", "restrict", "warp", "reduce", "combine",
+           "restrict_backward", "warp_backward",
            "autotune", "TuneCache", "workload_signature", "TILE_SHAPES", "PCF_LP",
            "PCF_LP_POW", "PCF_GRAM"]
 
@@ -268,6 +269,34 @@ def warp(X, weight, c, stream=None):
     new.offsets_host, new.offsets, new.n = off_h, off_d, X.n
     new.t, new.v = t, v
     return new
+
+
+def restrict_backward(X, a, b, Y, grad_t, grad_v, stream=None):
+    """dL/dt, dL/dv of ``X``'s rows (FP64) from those of ``Y = restrict(X, a,
+    b)``'s rows: kept rows pass theirs on, the row holding ``a`` receives the
+    value gradient of Y's row at ``a``, all else is 0 (see pcf.h)."""
+    gt = torch.empty(X.t.shape[0], dtype=torch.float64, device=X.t.device)
+    gv = torch.empty_like(gt)
+    grad_t = grad_t.to(torch.float64).contiguous()
+    grad_v = grad_v.to(torch.float64).contiguous()
+    check(_lib.pcf_restrict_backward(X.c_struct(), float(a), float(b), Y.offsets.data_ptr(),
+                                     grad_t.data_ptr(), grad_v.data_ptr(), gt.data_ptr(),
+                                     gv.data_ptr(), _stream_handle(stream)))
+    return gt, gv
+
+
+def warp_backward(X, weight, c, Y, grad_t, grad_v, stream=None):
+    """dL/dt, dL/dv of ``X``'s rows (FP64) from those of ``Y = warp(X,
+    weight, c)``'s rows: dL/dt_k = dL/dtau_k * w(t_k) (see pcf.h)."""
+    wk = _WEIGHTS.get(weight, weight)
+    gt = torch.empty(X.t.shape[0], dtype=torch.float64, device=X.t.device)
+    gv = torch.empty_like(gt)
+    grad_t = grad_t.to(torch.float64).contiguous()
+    grad_v = grad_v.to(torch.float64).contiguous()
+    check(_lib.pcf_warp_backward(X.c_struct(), int(wk), float(c), Y.offsets.data_ptr(),
+                                 grad_t.data_ptr(), grad_v.data_ptr(), gt.data_ptr(),
+                                 gv.data_ptr(), _stream_handle(stream)))
+    return gt, gv
 
 
 _REDUCE_OPS = {"sum": PCF_REDUCE_SUM, "mean": PCF_REDUCE_MEAN, "max": PCF_REDUCE_MAX,
@@ -583,16 +612,24 @@ def validate(X, stream=None):
 
 
 class PairwiseMatrix(torch.autograd.Function):
-    """F(C) as a differentiable function of the breakpoint times and values.
+    """F(C) as a differentiable function of the breakpoint times and values,
+    optionally over a range [a, b) and with a time weight.
 
-    Forward runs the pairwise kernel; backward runs the adjoint kernel, which
-    recomputes every pair's merge (nothing is stored between the two)."""
+    Forward restricts and warps the set (when asked) and runs the pairwise
+    kernel; backward runs the adjoint kernel on the transformed set, which
+    recomputes every pair's merge (nothing is stored between the two), then
+    maps the gradients back through the warp and the restriction."""
 
     @staticmethod
-    def forward(ctx, t, v, X, kind, p):
+    def forward(ctx, t, v, X, kind, p, bounds, weight):
         Xv = X.with_values(t.detach(), v.detach())
-        out = _forward(Xv, kind, p, None, None, False, False, None, None)
-        ctx.X, ctx.kind, ctx.p = Xv, kind, p
+        sets = [Xv]
+        if bounds is not None:
+            sets.append(restrict(sets[-1], bounds[0], bounds[1]))
+        if weight is not None:
+            sets.append(warp(sets[-1], weight[0], weight[1]))
+        out = _forward(sets[-1], kind, p, None, None, False, False, None, None)
+        ctx.sets, ctx.kind, ctx.p, ctx.bounds, ctx.weight = sets, kind, p, bounds, weight
         ctx.save_for_backward(out)
         return out
 
@@ -600,12 +637,21 @@ class PairwiseMatrix(torch.autograd.Function):
     def backward(ctx, grad_out):
         (out,) = ctx.saved_tensors
         need_fwd = ctx.kind == PCF_LP and ctx.p != 1.0
-        gt, gv = pairwise_backward(ctx.X, ctx.kind, ctx.p, grad_out,
+        sets = ctx.sets
+        gt, gv = pairwise_backward(sets[-1], ctx.kind, ctx.p, grad_out,
                                    out.to(torch.float64) if need_fwd else None)
-        return gt, gv, None, None, None
+        k = len(sets) - 1
+        if ctx.weight is not None:
+            gt, gv = warp_backward(sets[k - 1], ctx.weight[0], ctx.weight[1], sets[k], gt, gv)
+            k -= 1
+        if ctx.bounds is not None:
+            gt, gv = restrict_backward(sets[k - 1], ctx.bounds[0], ctx.bounds[1], sets[k],
+                                       gt, gv)
+        return gt, gv, None, None, None, None, None
 
 
-def pairwise_matrix(X, t, v, kind=PCF_LP, p=1.0):
+def pairwise_matrix(X, t, v, kind=PCF_LP, p=1.0, bounds=None, weight=None):
     """Differentiable F(C) over ``X``'s offsets with times ``t`` and values
-    ``v`` (tensors that may require grad)."""
-    return PairwiseMatrix.apply(t, v, X, kind, p)
+    ``v`` (tensors that may require grad); ``bounds=(a, b)`` integrates over
+    [a, b), ``weight=("exp"|"pow", c)`` with the time weight (as ``pdist``)."""
+    return PairwiseMatrix.apply(t, v, X, kind, p, bounds, weight)

@@ -1122,6 +1122,52 @@ pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
     return PCF_OK;
 }
 
+pcf_status pcf_restrict_backward(const pcf_set *X, double a, double b,
+                                 const int64_t *offsets_y, const void *grad_t_y,
+                                 const void *grad_v_y, void *grad_t_x, void *grad_v_x,
+                                 void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st == PCF_OK)
+        st = check_range(X, a, b);
+    if (st != PCF_OK)
+        return st;
+    if (X->n == 0)
+        return PCF_OK;
+    if (!offsets_y || !grad_t_y || !grad_v_y || !grad_t_x || !grad_v_x)
+        return fail(PCF_EINVAL, "a gradient or offsets pointer is NULL");
+    hipError_t e = launch_restrict_backward(
+        X->dtype == PCF_F64, X->offsets, X->n, X->t, a, b, offsets_y,
+        (const double *)grad_t_y, (const double *)grad_v_y, (double *)grad_t_x,
+        (double *)grad_v_x, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "restriction gradient launch");
+    return PCF_OK;
+}
+
+pcf_status pcf_warp_backward(const pcf_set *X, pcf_weight_kind weight, double c,
+                             const int64_t *offsets_y, const void *grad_t_y,
+                             const void *grad_v_y, void *grad_t_x, void *grad_v_x,
+                             void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st == PCF_OK)
+        st = check_weight(weight, c);
+    if (st != PCF_OK)
+        return st;
+    if (X->n == 0)
+        return PCF_OK;
+    if (!offsets_y || !grad_t_y || !grad_v_y || !grad_t_x || !grad_v_x)
+        return fail(PCF_EINVAL, "a gradient or offsets pointer is NULL");
+    hipError_t e = launch_warp_backward(
+        X->dtype == PCF_F64, X->offsets, X->n, X->t, (int)weight, c, offsets_y,
+        (const double *)grad_t_y, (const double *)grad_v_y, (double *)grad_t_x,
+        (double *)grad_v_x, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "warp gradient launch");
+    return PCF_OK;
+}
+
 pcf_status pcf_reduce_workspace_bytes(const pcf_set *X, int32_t B,
                                       const int64_t *group_offsets_host, pcf_reduce_op op,
                                       size_t *bytes)

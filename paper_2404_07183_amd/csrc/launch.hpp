@@ -74,6 +74,15 @@ hipError_t launch_warp_count(bool f64, const int64_t *offsets, int64_t n, const 
 hipError_t launch_warp_fill(bool f64, const int64_t *offsets, int64_t n, const void *t,
                             const void *v, int wk, double c, const int64_t *out_off,
                             void *t_out, void *v_out, hipStream_t s);
+// gradients through a restriction / a warp: dL/dt, dL/dv (FP64) of the
+// transformed set Y (offsets y_off) to those of X's rows
+hipError_t launch_restrict_backward(bool f64, const int64_t *offsets, int64_t n,
+                                    const void *t, double a, double b, const int64_t *y_off,
+                                    const double *gt_y, const double *gv_y, double *gt_x,
+                                    double *gv_x, hipStream_t s);
+hipError_t launch_warp_backward(bool f64, const int64_t *offsets, int64_t n, const void *t,
+                                int wk, double c, const int64_t *y_off, const double *gt_y,
+                                const double *gv_y, double *gt_x, double *gv_x, hipStream_t s);
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);

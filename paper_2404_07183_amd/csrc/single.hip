@@ -235,6 +235,48 @@ __global__ void restrict_fill(const int64_t *__restrict__ offsets, int64_t n,
     }
 }
 
+// Gradients through a restriction. Y = X 1_[a,b) holds, per PCF, a head row
+// (a, v_ka) (after (0, 0) when a > 0; (0, v_0) when a = 0), X's rows
+// ka+1 .. kb-1, and (b, 0) when b is finite. Given dL/dt, dL/dv of Y's rows
+// (FP64), X's rows get: a kept row, its own; row ka, the head row's value
+// gradient; every other row 0 (the times 0, a, b and the added values are
+// constants, and rows outside the range do not reach Y). The last value is a
+// fixed parameter, as in the adjoint. One wave per PCF.
+template <typename T>
+__global__ void restrict_backward(const int64_t *__restrict__ offsets, int64_t n,
+                                  const T *__restrict__ t, double a, double b,
+                                  const int64_t *__restrict__ y_off,
+                                  const double *__restrict__ gt_y,
+                                  const double *__restrict__ gv_y, double *__restrict__ gt_x,
+                                  double *__restrict__ gv_x)
+{
+    const T ta = (T)a, tb = (T)b;
+    const bool bf = !(b == INFINITY);
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves) {
+        const int64_t o = offsets[i], ni = offsets[i + 1] - o;
+        int64_t ka, kb;
+        kept_rows(t + o, ni, ta, tb, bf, ka, kb);
+        const int head = ta > T(0) ? 2 : 1;
+        const int64_t w = y_off[i] + head;  // Y's row of X's row ka + 1
+        for (int64_t k = lane; k < ni; k += 64) {
+            double gt = 0.0, gv = 0.0;
+            if (k > ka && k < kb) {
+                gt = gt_y[w + (k - ka - 1)];
+                gv = gv_y[w + (k - ka - 1)];
+            }
+            if (k == ka)
+                gv = gv_y[w - 1];  // the head row (a, v_ka)
+            if (k == ni - 1)
+                gv = 0.0;  // the last value is fixed (0 by the data contract)
+            gt_x[o + k] = gt;
+            gv_x[o + k] = gv;
+        }
+    }
+}
+
 hipError_t launch_restrict_count(bool f64, const int64_t *offsets, int64_t n,
                                  const void *t, double a, double b, int64_t *counts,
                                  hipStream_t s)
@@ -250,6 +292,25 @@ hipError_t launch_restrict_count(bool f64, const int64_t *offsets, int64_t n,
     else
         hipLaunchKernelGGL(restrict_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                            offsets, n, (const float *)t, a, b, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_backward(bool f64, const int64_t *offsets, int64_t n,
+                                    const void *t, double a, double b, const int64_t *y_off,
+                                    const double *gt_y, const double *gv_y, double *gt_x,
+                                    double *gv_x, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (f64)
+        hipLaunchKernelGGL(restrict_backward<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const double *)t, a, b, y_off, gt_y, gv_y, gt_x, gv_x);
+    else
+        hipLaunchKernelGGL(restrict_backward<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const float *)t, a, b, y_off, gt_y, gv_y, gt_x, gv_x);
     return hipGetLastError();
 }
 
@@ -343,6 +404,51 @@ __global__ void warp_count(const int64_t *__restrict__ offsets, int64_t n,
     }
 }
 
+// Gradients through a time warp: Y's kept rows are (W(t_k), v_k), so X's
+// row k gets dL/dt = dL/dtau w(t_k) (W' = w; t_0 = 0 is fixed) and dL/dv as
+// given; a row dropped because its rounded tau ties the next one's (a piece
+// of zero width in Y) gets 0. One wave per PCF, the rows decided as in
+// warp_fill.
+template <typename T>
+__global__ void warp_backward(const int64_t *__restrict__ offsets, int64_t n,
+                              const T *__restrict__ t, int wk, double c,
+                              const int64_t *__restrict__ y_off,
+                              const double *__restrict__ gt_y,
+                              const double *__restrict__ gv_y, double *__restrict__ gt_x,
+                              double *__restrict__ gv_x)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n;
+         i += nwaves) {
+        const int64_t o = offsets[i], ni = offsets[i + 1] - o;
+        int64_t w = y_off[i];
+        const int64_t end = y_off[i + 1];
+        for (int64_t base = 0; base < ni; base += 64) {
+            T tau;
+            bool keep, bad;
+            warp_chunk(t + o, ni, base, lane, wk, c, tau, keep, bad);
+            const uint64_t m = __ballot(keep);
+            const int64_t pos = w + __popcll(m & below);
+            const int64_t k = base + lane;
+            if (k < ni) {
+                double gt = 0.0, gv = 0.0;
+                if (keep && pos < end) {
+                    gv = gv_y[pos];
+                    if (k > 0) {
+                        const double x = (double)t[o + k];
+                        gt = gt_y[pos] * (wk == WK_EXP ? exp(-c * x) : pow(x, c));
+                    }
+                }
+                gt_x[o + k] = gt;
+                gv_x[o + k] = gv;
+            }
+            w += __popcll(m);
+        }
+    }
+}
+
 template <typename T>
 __global__ void warp_fill(const int64_t *__restrict__ offsets, int64_t n,
                           const T *__restrict__ t, const T *__restrict__ v, int wk,
@@ -406,6 +512,25 @@ hipError_t launch_warp_fill(bool f64, const int64_t *offsets, int64_t n, const v
         hipLaunchKernelGGL(warp_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                            offsets, n, (const float *)t, (const float *)v, wk, c,
                            out_off, (float *)t_out, (float *)v_out);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_warp_backward(bool f64, const int64_t *offsets, int64_t n, const void *t,
+                                int wk, double c, const int64_t *y_off, const double *gt_y,
+                                const double *gv_y, double *gt_x, double *gv_x, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (f64)
+        hipLaunchKernelGGL(warp_backward<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const double *)t, wk, c, y_off, gt_y, gv_y, gt_x, gv_x);
+    else
+        hipLaunchKernelGGL(warp_backward<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           offsets, n, (const float *)t, wk, c, y_off, gt_y, gv_y, gt_x, gv_x);
     return hipGetLastError();
 }
 

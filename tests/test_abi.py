@@ -64,6 +64,22 @@ def test_argument_errors_need_no_device():
         assert lib.pcf_warp(ctypes.byref(X), wk, c, None, None, None, None) == _lib.PCF_EINVAL
     assert lib.pcf_warp(ctypes.byref(X), _lib.PCF_WEIGHT_EXP, 1.0, None, None, None,
                         None) == _lib.PCF_OK
+    # the gradient maps through a restriction and a warp check the same
+    # arguments as the forward calls, and NULL pointers, before device work
+    for a, b in ((2.0, 2.0), (-1.0, 3.0), (3.0, 1.0)):
+        assert lib.pcf_restrict_backward(ctypes.byref(X), a, b, None, None, None, None, None,
+                                         None) == _lib.PCF_EINVAL
+    for wk, c in bad_weights:
+        assert lib.pcf_warp_backward(ctypes.byref(X), wk, c, None, None, None, None, None,
+                                     None) == _lib.PCF_EINVAL
+    X1 = _lib.pcf_set(1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                      _lib.PCF_F64, None)  # (never dereferenced: refused first)
+    assert lib.pcf_restrict_backward(ctypes.byref(X1), 0.5, 2.0, None, None, None, None,
+                                     None, None) == _lib.PCF_EINVAL
+    assert lib.pcf_warp_backward(ctypes.byref(X1), _lib.PCF_WEIGHT_EXP, 1.0, None, None,
+                                 None, None, None, None) == _lib.PCF_EINVAL
+    assert lib.pcf_restrict_backward(ctypes.byref(X), 0.5, 2.0, None, None, None, None,
+                                     None, None) == _lib.PCF_OK  # empty set: no-op
 
 
 def _inspect(offsets, dtype=_lib.PCF_F64, window=None, backward=False):

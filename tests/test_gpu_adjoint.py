@@ -167,3 +167,73 @@ def test_grad_config_full_size_properties():
         a, b = o[i], o[i + 1]
         assert _close(gt[a:b], (rt1 + rt2)[a:b], 1e-10)
         assert _close(gv[a:b], (rv1 + rv2)[a:b], 1e-10)
+
+
+@pytest.mark.parametrize("bounds,weight", [((0.7, 3.1), None), ((0.0, 2.4), None),
+                                           (None, ("exp", 0.3)), (None, ("pow", 0.5)),
+                                           ((0.5, np.inf), ("pow", -0.4)),
+                                           ((0.6, 4.0), ("exp", 0.2))])
+def test_gradients_through_range_and_weight(bounds, weight):
+    # L = sum W_ij d_2(f_i,f_j)^2 + sum U_ij <f_i,f_j>, both integrals over
+    # [a, b) with the time weight: the GPU gradients (adjoint on the
+    # transformed set, mapped back through the warp and the restriction)
+    # against central differences of the oracle's weighted, bounded loss
+    o, t, v = _set(11, 10, 2, 14)
+    N = len(o) - 1
+    rng = np.random.default_rng(12)
+    W = rng.uniform(0, 1, size=(N, N))
+    W = np.triu(W) + np.triu(W, 1).T
+    U = rng.uniform(0, 1, size=(N, N))
+    U = np.triu(U) + np.triu(U, 1).T
+    a, b = bounds if bounds is not None else (0.0, np.inf)
+    wk, c = weight if weight is not None else (None, 0.0)
+    I, J = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+
+    def oracle_loss(tt, vv):
+        if weight is None:
+            m1 = oracle.entries_ab(oracle.LP_POW, 2.0, a, b, o, tt, vv, I, J)
+            m2 = oracle.entries_ab(oracle.GRAM, 0.0, a, b, o, tt, vv, I, J)
+        else:
+            code = oracle.W_EXP if wk == "exp" else oracle.W_POW
+            m1 = oracle.entries_w(oracle.LP_POW, 2.0, code, c, o, tt, vv, I, J, a, b)
+            m2 = oracle.entries_w(oracle.GRAM, 0.0, code, c, o, tt, vv, I, J, a, b)
+        return float((W.ravel() * m1).sum() + (U.ravel() * m2).sum())
+
+    X = api.PcfSet(o, t, v, device=DEV)
+    Wt, Ut = torch.as_tensor(W, device=DEV), torch.as_tensor(U, device=DEV)
+    tt = torch.as_tensor(t, device=DEV).clone().requires_grad_(True)
+    vv = torch.as_tensor(v, device=DEV).clone().requires_grad_(True)
+    M1 = api.pairwise_matrix(X, tt, vv, api.PCF_LP_POW, 2.0, bounds=bounds, weight=weight)
+    M2 = api.pairwise_matrix(X, tt, vv, api.PCF_GRAM, bounds=bounds, weight=weight)
+    L = (Wt * M1).sum() + (Ut * M2).sum()
+    assert abs(L.item() - oracle_loss(t, v)) <= 1e-10 * max(1.0, abs(L.item()))
+    L.backward()
+    gt, gv = tt.grad.cpu().numpy(), vv.grad.cpu().numpy()
+    h = 1e-6
+    checked = 0
+    for k in range(len(t)):
+        # rows within h of a bound would cross it under the perturbation
+        if np.isfinite(b) and abs(t[k] - b) < 1e-4 or a > 0 and abs(t[k] - a) < 1e-4:
+            continue
+        for arr, g in ((t, gt), (v, gv)):
+            x = arr.copy()
+            x[k] += h
+            lp = oracle_loss(x, v) if arr is t else oracle_loss(t, x)
+            x[k] -= 2 * h
+            lm = oracle_loss(x, v) if arr is t else oracle_loss(t, x)
+            fd = (lp - lm) / (2 * h)
+            fixed = (arr is t and k in set(o[:-1].tolist())) or \
+                    (arr is v and k in set((o[1:] - 1).tolist()))
+            if fixed:
+                assert g[k] == 0.0, (k, g[k])
+            else:
+                assert abs(g[k] - fd) <= 2e-6 * max(1.0, abs(fd)), (k, arr is t, g[k], fd)
+                checked += 1
+    assert checked > 60
+    # rows entirely outside the range receive no gradient
+    if bounds is not None:
+        for i in range(N):
+            for k in range(o[i], o[i + 1]):
+                if t[k] >= b or (k + 1 < o[i + 1] and t[k + 1] <= a):
+                    assert gt[k] == 0.0 and gv[k] == 0.0, k
