@@ -272,6 +272,34 @@ pcf_status pcf_warp_rows(const pcf_set *X, pcf_weight_kind weight, double c,
 pcf_status pcf_warp(const pcf_set *X, pcf_weight_kind weight, double c,
                     const int64_t *offsets_out, void *t_out, void *v_out, void *stream);
 
+/* Time-dependent combinations given by a sum of separable terms (Section 3:
+ * a time-dependent h whose antiderivative H in t is known adds, per
+ * rectangle [l, r) with values (a, b), H(a, b, r) - H(a, b, l)). Here
+ *   h(a, b, t) = sum_m coef_m h0_m(a, b) w_m(t),  H = sum_m coef_m h0_m W_m,
+ * with h0_m = |a - b|^p (PCF_LP_POW) or a b (PCF_GRAM) and w_m = 1 (weight
+ * 0), e^{-ct} or t^c (pcf_weight_kind, as pcf_warp): not separable in
+ * general. The result is F_ij = r(sum_m coef_m I_m(f_i, f_j)), r(x) = x^(1/q)
+ * (q >= 1; q = 0: no root), each I_m on the set warped by w_m. Output and
+ * window as pcf_pairwise_lp; PCF_UPPER_ONLY honoured; PCF_REUSE_PLAN and
+ * PCF_RECORDS_PACKED refused (PCF_EINVAL: every term plans and packs its own
+ * set). A root of a negative sum is NaN. Workspace: pcf_terms_workspace_bytes
+ * (the forward's, plus one warped copy of the set). Synchronises the stream
+ * once per weighted term (to read the warped row counts). PCF_EINVAL for an
+ * empty term list, a bad kind, p, weight or root, or a non-finite
+ * coefficient. */
+typedef struct {
+    pcf_kind kind;           /* PCF_LP_POW or PCF_GRAM */
+    double p;                /* the exponent of PCF_LP_POW */
+    int weight;              /* 0 (w = 1), PCF_WEIGHT_EXP or PCF_WEIGHT_POW */
+    double c;                /* the weight's parameter */
+    double coef;             /* the term's coefficient */
+} pcf_term;
+pcf_status pcf_terms_workspace_bytes(const pcf_set *X, const pcf_window *w, uint32_t flags,
+                                     size_t *bytes);
+pcf_status pcf_pairwise_terms(const pcf_set *X, int32_t nterms, const pcf_term *terms,
+                              double q, void *out, int64_t ldo, const pcf_window *w,
+                              void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
 /* Gradients through a range restriction and a time warp (Section 3, the
  * remark after Algorithm "CombineIntegrate" that the integrals' parameter
  * derivatives are analytic; Section 2.2 ranges and weights). For a loss of a

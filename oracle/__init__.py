@@ -173,6 +173,24 @@ def entries_w(kind, p, weight, c, offsets, t, v, I, J, a=0.0, b=np.inf, with_abs
     return (out, ab) if with_abs else out
 
 
+def entries_terms(terms, q, offsets, t, v, I, J):
+    """F(f_I[k], f_J[k]) = r(sum_m coef_m I_m) for the time-dependent
+    combination h(a, b, t) = sum_m coef_m h0_m(a, b) w_m(t) (Section 3:
+    H(a, b, r) - H(a, b, l) per rectangle, H = sum_m coef_m h0_m W_m), by the
+    definition: each term's integral (``entries`` / ``entries_w``), the
+    coefficients, the sum, then r(x) = x^(1/q) (q = 0: none). ``terms``:
+    ``(kind, p, weight, c, coef)`` with kind LP_POW or GRAM, weight 0 (w = 1),
+    W_EXP or W_POW."""
+    total = np.zeros(len(I), dtype=np.float64)
+    for kind, p, weight, c, coef in terms:
+        if weight:
+            m = entries_w(kind, p, weight, c, offsets, t, v, I, J)
+        else:
+            m = entries(kind, p, offsets, t, v, I, J)
+        total = total + coef * m
+    return total ** (1.0 / q) if q else total
+
+
 def matrix(kind, p, offsets, t, v):
     """The full M x M matrix, every entry computed on its own."""
     lib = _load()

@@ -36,6 +36,11 @@ class pcf_set(ctypes.Structure):
                 ("offsets_host", ctypes.c_void_p)]
 
 
+class pcf_term(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double), ("weight", ctypes.c_int),
+                ("c", ctypes.c_double), ("coef", ctypes.c_double)]
+
+
 class pcf_window(ctypes.Structure):
     _fields_ = [("row0", ctypes.c_int64), ("row1", ctypes.c_int64),
                 ("col0", ctypes.c_int64), ("col1", ctypes.c_int64)]
@@ -114,6 +119,14 @@ _SIGS = {
     "pcf_warp": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int, ctypes.c_double,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]),
+    "pcf_terms_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(pcf_set),
+                                                 ctypes.POINTER(pcf_window), ctypes.c_uint32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "pcf_pairwise_terms": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_int32,
+                                          ctypes.POINTER(pcf_term), ctypes.c_double,
+                                          ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.POINTER(pcf_window), ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p]),
     "pcf_restrict_backward": (ctypes.c_int, [ctypes.POINTER(pcf_set), ctypes.c_double,
                                              ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -272,6 +285,21 @@ def pcf_warp_rows(X, weight, c, offsets_out_ptr, offsets_out_host_ptr, stream):
 def pcf_warp(X, weight, c, offsets_out_ptr, t_out_ptr, v_out_ptr, stream):
     return load().pcf_warp(ctypes.byref(X), weight, c, offsets_out_ptr, t_out_ptr,
                            v_out_ptr, stream)
+
+
+def pcf_terms_workspace_bytes(X, window, flags):
+    out = ctypes.c_size_t(0)
+    check(load().pcf_terms_workspace_bytes(ctypes.byref(X),
+                                           ctypes.byref(window) if window else None, flags,
+                                           ctypes.byref(out)))
+    return out.value
+
+
+def pcf_pairwise_terms(X, terms, q, out_ptr, ldo, window, ws_ptr, ws_bytes, flags, stream):
+    arr = (pcf_term * len(terms))(*terms)
+    return load().pcf_pairwise_terms(ctypes.byref(X), len(terms), arr, q, out_ptr, ldo,
+                                     ctypes.byref(window) if window else None, ws_ptr,
+                                     ws_bytes, flags, stream)
 
 
 def pcf_restrict_backward(X, a, b, offsets_y_ptr, gt_y_ptr, gv_y_ptr, gt_x_ptr, gv_x_ptr,

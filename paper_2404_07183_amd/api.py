@@ -23,7 +23,7 @@ from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
 __all__ = ["PcfSet", "Workspace", "pdist", "gram", "cdist", "cross_gram", "pairwise_backward",
            "pairwise_batched", "validate", "pairwise_matrix", "PairwiseMatrix",
            "integrals", "norms", "restrict", "warp", "reduce", "combine",
-           "restrict_backward", "warp_backward",
+           "restrict_backward", "warp_backward", "pairwise_terms",
            "autotune", "TuneCache", "workload_signature", "TILE_SHAPES", "PCF_LP",
            "PCF_LP_POW", "PCF_GRAM"]
 
@@ -185,6 +185,38 @@ def gram(X, *, window=None, out=None, upper_only=False, validate=False,
     X = _transform(X, bounds, weight, stream)
     return _forward(X, PCF_GRAM, 0.0, window, out, upper_only, validate, workspace,
                     stream, packed, shape)
+
+
+def pairwise_terms(X, terms, root=None, *, window=None, out=None, upper_only=False,
+                   workspace=None, stream=None):
+    """The matrix r(sum_m coef_m I_m(f_i, f_j)) of a time-dependent combination
+    h(a, b, t) = sum_m coef_m h0_m(a, b) w_m(t) (Section 3: H(a, b, r) -
+    H(a, b, l) per rectangle with H = sum_m coef_m h0_m W_m). ``terms``: a list
+    of ``(h0, p, weight, coef)`` with h0 ``"lp"`` (|a - b|^p) or ``"gram"``
+    (a b, p ignored) and weight None, ``("exp", c)`` or ``("pow", c)``.
+    ``root``: q for r(x) = x^(1/q), or None. Synchronises once per weighted
+    term."""
+    Xc = X.c_struct()
+    win = _window(window)
+    oshape = (X.n, X.n) if window is None else (window[1] - window[0], window[3] - window[2])
+    if out is None:
+        out = torch.zeros(oshape, dtype=X.dtype, device=X.t.device)
+    _check_out(out, X, oshape)
+    ldo = out.stride(0) if out.shape[0] > 1 else max(out.shape[1], 1)
+    ct = []
+    for h0, p, weight, coef in terms:
+        kind = {"lp": PCF_LP_POW, "gram": PCF_GRAM}[h0]
+        wk, c = (0, 0.0) if weight is None else (_WEIGHTS.get(weight[0], weight[0]), weight[1])
+        ct.append(_lib.pcf_term(int(kind), float(p) if kind == PCF_LP_POW else 0.0, int(wk),
+                                float(c), float(coef)))
+    flags = PCF_UPPER_ONLY if upper_only else 0
+    ws = workspace if workspace is not None else Workspace(device=X.t.device)
+    ws.ensure(_lib.pcf_terms_workspace_bytes(Xc, win, flags))
+    ws.planned = None
+    ws.packed_data = None
+    check(_lib.pcf_pairwise_terms(Xc, ct, float(root) if root else 0.0, out.data_ptr(), ldo,
+                                  win, ws.ptr, ws.nbytes, flags, _stream_handle(stream)))
+    return out
 
 
 def _cross(X, Y, kind, p, out, validate, workspace, stream, shape=None):

@@ -305,7 +305,8 @@ int tile_grid(const Plan *plan, bool reuse)
 
 pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
                           int64_t ldo, const pcf_window *w, void *ws,
-                          size_t ws_bytes, uint32_t flags, void *stream)
+                          size_t ws_bytes, uint32_t flags, void *stream,
+                          int accumulate = 0, double coef = 1.0)
 {
     pcf_status st = check_set(X);
     if (st != PCF_OK)
@@ -356,6 +357,8 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
     a.p = p;
     a.inv_p = 1.0 / p;
     a.gram = kind == PCF_GRAM ? 1 : 0;
+    a.accumulate = accumulate;
+    a.coef = coef;
     int hk;
     if (kind == PCF_GRAM) {
         hk = HK_PROD;
@@ -364,6 +367,8 @@ pcf_status forward_common(const pcf_set *X, pcf_kind kind, double p, void *out,
         hk = lp_hkind(p, X->dtype == PCF_F64);
         a.root = (kind == PCF_LP_POW || p == 1.0) ? 0 : (p == 2.0 ? 1 : 2);
     }
+    if (accumulate && a.root != 0)
+        return fail(PCF_EINVAL, "a term of a sum takes no root");
     hipError_t e = launch_forward(X->dtype == PCF_F64, hk, a,
                                   tile_grid(reuse ? nullptr : &plan, reuse), s);
     if (e != hipSuccess)
@@ -607,9 +612,138 @@ pcf_status noalloc_plan_bytes(const pcf_set *X, const pcf_window *w, int64_t ldo
     return PCF_OK;
 }
 
+// Workspace of a sum of terms: the forward's (planned on X; a warped set has
+// no more rows), then the warped set's offsets, times and values.
+struct TermsLayout {
+    size_t fwd = 0, off = 0, t = 0, v = 0, bytes = 0;
+};
+
+pcf_status terms_layout(const pcf_set *X, const pcf_window *w, uint32_t flags,
+                        TermsLayout &L)
+{
+    int64_t fb = 0;
+    const int64_t ldo = w ? (w->col1 - w->col0) : X->n;
+    pcf_status st = noalloc_plan_bytes(X, w, ldo, flags & ~(uint32_t)PCF_UPPER_ONLY, &fb);
+    if (st != PCF_OK)
+        return st;
+    std::vector<int64_t> obuf;
+    const int64_t *ho = nullptr;
+    st = host_offsets(X, obuf, ho, nullptr);
+    if (st != PCF_OK)
+        return st;
+    const size_t rows = X->n > 0 ? (size_t)ho[X->n] : 0;
+    const size_t esz = X->dtype == PCF_F64 ? 8 : 4;
+    L.fwd = align256((size_t)fb);
+    L.off = L.fwd;
+    L.t = L.off + align256((size_t)(X->n + 1) * sizeof(int64_t));
+    L.v = L.t + align256((rows > 0 ? rows : 1) * esz);
+    L.bytes = L.v + align256((rows > 0 ? rows : 1) * esz);
+    return PCF_OK;
+}
+
+pcf_status check_terms(int32_t nterms, const pcf_term *terms, double q)
+{
+    if (nterms < 1 || !terms)
+        return fail(PCF_EINVAL, "at least one term is needed");
+    for (int32_t m = 0; m < nterms; ++m) {
+        const pcf_term &T = terms[m];
+        const std::string who = "term " + std::to_string(m) + ": ";
+        if (T.kind != PCF_LP_POW && T.kind != PCF_GRAM)
+            return fail(PCF_EINVAL, who + "kind must be PCF_LP_POW or PCF_GRAM");
+        if (T.kind == PCF_LP_POW && (!(T.p >= 1.0) || !isfinite(T.p)))
+            return fail(PCF_EINVAL, who + "p must be finite and >= 1");
+        if (T.weight != 0 && check_weight(T.weight, T.c) != PCF_OK)
+            return fail(PCF_EINVAL, who + "bad weight");
+        if (!isfinite(T.coef))
+            return fail(PCF_EINVAL, who + "the coefficient is not finite");
+    }
+    if (!(q == 0.0 || (q >= 1.0 && isfinite(q))))
+        return fail(PCF_EINVAL, "the root q must be 0 (none) or finite and >= 1");
+    return PCF_OK;
+}
+
 }  // namespace pcf
 
 extern "C" {
+
+pcf_status pcf_terms_workspace_bytes(const pcf_set *X, const pcf_window *w, uint32_t flags,
+                                     size_t *bytes)
+{
+    if (!bytes)
+        return fail(PCF_EINVAL, "bytes is NULL");
+    TermsLayout L;
+    pcf_status st = terms_layout(X, w, flags, L);
+    if (st != PCF_OK)
+        return st;
+    *bytes = L.bytes;
+    return PCF_OK;
+}
+
+pcf_status pcf_pairwise_terms(const pcf_set *X, int32_t nterms, const pcf_term *terms,
+                              double q, void *out, int64_t ldo, const pcf_window *w,
+                              void *ws, size_t ws_bytes, uint32_t flags, void *stream)
+{
+    pcf_status st = check_set(X);
+    if (st == PCF_OK)
+        st = check_terms(nterms, terms, q);
+    if (st != PCF_OK)
+        return st;
+    if (flags & (PCF_REUSE_PLAN | PCF_RECORDS_PACKED))
+        return fail(PCF_EINVAL, "every term plans and packs its own set: no plan reuse");
+    if (X->n == 0)
+        return PCF_OK;
+    if (!out || !ws)
+        return fail(PCF_EINVAL, "out or ws is NULL");
+    TermsLayout L;
+    st = terms_layout(X, w, flags, L);
+    if (st != PCF_OK)
+        return st;
+    if (ws_bytes < L.bytes)
+        return fail(PCF_ENOMEM, "workspace too small: need " + std::to_string(L.bytes) +
+                                    " bytes (pcf_terms_workspace_bytes)");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *wb = (unsigned char *)ws;
+    std::vector<int64_t> zoff((size_t)X->n + 1);
+    for (int32_t m = 0; m < nterms; ++m) {
+        const pcf_term &T = terms[m];
+        pcf_set Z = *X;
+        if (T.weight != 0) {
+            // the set warped by this term's weight, in the workspace
+            int64_t *off = (int64_t *)(wb + L.off);
+            hipError_t e = launch_warp_count(X->dtype == PCF_F64, X->offsets, X->n, X->t,
+                                             (int)T.weight, T.c, off, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "warp count launch");
+            st = counts_to_offsets(X->n, off, zoff.data(), s, "warped");
+            if (st != PCF_OK)
+                return st;
+            e = launch_warp_fill(X->dtype == PCF_F64, X->offsets, X->n, X->t, X->v,
+                                 (int)T.weight, T.c, off, wb + L.t, wb + L.v, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "warp kernel launch");
+            Z.offsets = off;
+            Z.t = wb + L.t;
+            Z.v = wb + L.v;
+            Z.offsets_host = zoff.data();
+        }
+        st = forward_common(&Z, T.kind, T.kind == PCF_GRAM ? 0.0 : T.p, out, ldo, w, ws,
+                            L.fwd, flags & ~(uint32_t)PCF_DETERMINISTIC, stream,
+                            m == 0 ? 2 : 1, T.coef);
+        if (st != PCF_OK)
+            return st;
+        // (the next term's warp rewrites the area after this term's kernels
+        // on the same stream)
+    }
+    if (q > 1.0) {
+        const int64_t rows = w ? w->row1 - w->row0 : X->n, cols = w ? w->col1 - w->col0 : X->n;
+        hipError_t e = launch_apply_root(X->dtype == PCF_F64, out, rows, cols, ldo, q,
+                                         (flags & PCF_UPPER_ONLY) != 0, w ? w->row0 : 0,
+                                         w ? w->col0 : 0, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "root launch");
+    }
+    return PCF_OK;
+}
 
 const char *pcf_last_error(void) { return g_err.c_str(); }
 

@@ -412,6 +412,8 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
                 else if constexpr (RT == kRootPow)
                     val = pow(val, args.inv_p);
                 const int64_t i = D.r_lo + r, j = D.c_lo + c;
+                if (args.accumulate != 0)  // a term of a sum (no root: checked on the host)
+                    val *= args.coef;
                 res = (T)val;
                 wr = true;
                 at0 = D.obase + (i - D.row0) * D.ldo + (j - D.col0);
@@ -426,9 +428,17 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
         // (i, j) and, mirrored, (j, i); nothing waits for these stores until
         // the next tile's staging
         if (wr) {
-            out[at0] = res;
-            if (wr_mirror)
-                out[at1] = res;
+            if (args.accumulate == 1) {
+                // each entry has one writer per launch; the terms' launches
+                // are ordered on the stream
+                out[at0] += res;
+                if (wr_mirror)
+                    out[at1] += res;
+            } else {
+                out[at0] = res;
+                if (wr_mirror)
+                    out[at1] = res;
+            }
         }
         loop.advance();
         pc.mark(kPhaseAdvance);

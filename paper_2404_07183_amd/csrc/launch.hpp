@@ -25,6 +25,8 @@ struct FwdArgs {
     double inv_p;            // for kRootPow
     int root;                // Root
     int gram;                // 1: diagonal pairs carry work (Gram)
+    int accumulate = 0;      // 1: out += coef * value, 2: out = coef * value
+    double coef = 1.0;       // (the terms of a sum; no root)
 };
 
 struct BwdArgs {
@@ -83,6 +85,11 @@ hipError_t launch_restrict_backward(bool f64, const int64_t *offsets, int64_t n,
 hipError_t launch_warp_backward(bool f64, const int64_t *offsets, int64_t n, const void *t,
                                 int wk, double c, const int64_t *y_off, const double *gt_y,
                                 const double *gv_y, double *gt_x, double *gv_x, hipStream_t s);
+// x -> x^(1/q) over a rows x cols region of out (leading dimension ldo); with
+// upper, only the entries whose global row i0 + r is at most their global
+// column j0 + c
+hipError_t launch_apply_root(bool f64, void *out, int64_t rows, int64_t cols, int64_t ldo,
+                             double q, bool upper, int64_t i0, int64_t j0, hipStream_t s);
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);

@@ -534,4 +534,38 @@ hipError_t launch_warp_backward(bool f64, const int64_t *offsets, int64_t n, con
     return hipGetLastError();
 }
 
+
+// The root of a sum of terms (pcf_pairwise_terms): x -> x^(1/q) (sqrt for
+// q = 2) over a region of the output, one thread per entry.
+template <typename T>
+__global__ void apply_root(T *__restrict__ out, int64_t rows, int64_t cols, int64_t ldo,
+                          double q, int upper, int64_t i0, int64_t j0)
+{
+    const int64_t total = rows * cols;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = k / cols, c = k - r * cols;
+        if (upper && i0 + r > j0 + c)
+            continue;
+        T *x = out + r * ldo + c;
+        *x = q == 2.0 ? (T)sqrt((double)*x) : (T)pow((double)*x, 1.0 / q);
+    }
+}
+
+hipError_t launch_apply_root(bool f64, void *out, int64_t rows, int64_t cols, int64_t ldo,
+                             double q, bool upper, int64_t i0, int64_t j0, hipStream_t s)
+{
+    if (rows <= 0 || cols <= 0)
+        return hipSuccess;
+    int64_t blocks = (rows * cols + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    if (f64)
+        hipLaunchKernelGGL(apply_root<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (double *)out, rows, cols, ldo, q, upper ? 1 : 0, i0, j0);
+    else
+        hipLaunchKernelGGL(apply_root<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (float *)out, rows, cols, ldo, q, upper ? 1 : 0, i0, j0);
+    return hipGetLastError();
+}
 }  // namespace pcf
