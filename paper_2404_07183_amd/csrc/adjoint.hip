@@ -162,6 +162,7 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
 // value; the next step, which ends O with width 0, adds no time gradient.
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) long long lds_i64;
 typedef const __attribute__((address_space(3))) d2 *lds_d2;
 
 struct AdjChain {
@@ -173,6 +174,8 @@ struct AdjChain {
                            // gunit<HK> (P's is 0: loaded by the last step)
     double x;              // start of the current cell
     double Wv, Wt;         // pair weight times the unit of dh/da; pair weight
+                           // (times the tile's value and time slot scales)
+    double sv, st;         // the tile's slot scales (slot_scales)
     int32_t left;          // steps left in the current pair
     int32_t k, r, c, rb, rn, cb, cn;
 };
@@ -238,9 +241,74 @@ __device__ __forceinline__ lds_f64 *grad_slot(uint32_t a, uint32_t gb)
     return (lds_f64 *)(size_t)((a >> 1) + gb + Extra);
 }
 
-__device__ __forceinline__ void lds_add(lds_f64 *p, double x)
+// The slots hold fixed-point sums: the add of a gradient term w g (w a pair
+// weight already multiplied by the tile's scale 2^s for the slot's kind)
+// adds floor(y), y = w g + 1/2, as a 64-bit integer: its high word
+// floor(y / 2^32), its low word the remainder y - 2^32 floor(y / 2^32),
+// in [0, 2^32) (exact but for its own rounding below one unit). So each add
+// is w g within one unit 2^-s, or within the FP64 rounding of w g where that
+// is coarser (|y| < 2^57 here). Integer LDS atomics are faster than FP64 ones; the
+// adds are exact modulo 2^64, so a tile's sums no longer depend on their
+// order.
+__device__ __forceinline__ void lds_add(lds_f64 *p, double w, double g)
 {
-    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const double y = fma(w, g, 0.5);
+    const double hi = floor(y * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, y);
+    const unsigned long long n =
+        ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+    __hip_atomic_fetch_add((lds_i64 *)p, (long long)n, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// 2^s with B 2^s < 2^57 and Wm 2^s <= 2^1000 (B > 0; a power of two above
+// DBL_MAX where B overflowed)
+__device__ __forceinline__ double scale_below(double B, double Wm)
+{
+    if (!(B > 0.0))
+        return 1.0;
+    int e = 1024, ew;
+    if (isfinite(B))
+        frexp(B, &e);  // B < 2^e
+    frexp(Wm, &ew);
+    int sh = 57 - e;
+    sh = sh > 1000 - ew ? 1000 - ew : sh;
+    return ldexp(1.0, sh < -1000 ? -1000 : sh);
+}
+
+// The tile's slot scales, one for the value slots and one for the time
+// slots (their gradients may differ by any factor). A kept slot sums, over
+// at most 32 partners of its PCF (33 terms: a diagonal Gram pair adds
+// twice), one pair's gradient each: a value gradient over one piece, at most
+// |W| max|dh/da| times the piece's length, or a time gradient, at most
+// 2 |W| max|h| (a jump of h, or the mean of two at a tie); every single add
+// is a part of one such term and at most twice its bound. With Wm, vm and Lm
+// the tile's largest |W|, |v| and piece length, Bv = Wm max|dh/da| Lm and
+// Bt = 4 Wm max|h| bound both kinds, and each scale puts its bound below
+// 2^57: a slot's final sum stays below 33 * 2^57 < 2^63 (partial sums may
+// wrap). (|a - b| <= 2 vm.) Slots of the fixed last value and of padding
+// may take larger adds; they are dropped.
+template <int HK>
+__device__ __forceinline__ void slot_scales(double Wm, double vm, double Lm, double p,
+                                            double &sv, double &st)
+{
+    const double a = 2.0 * vm;
+    double dh, hm;
+    if constexpr (HK == kAbs) {
+        dh = 1.0;
+        hm = a;
+    } else if constexpr (HK == kSqr) {
+        dh = 2.0 * a;
+        hm = a * a;
+    } else if constexpr (HK == kProd) {
+        dh = vm;
+        hm = vm * vm;
+    } else {
+        dh = p * pow(a, p - 1.0);
+        hm = pow(a, p);
+    }
+    sv = scale_below(Wm * dh * Lm, Wm);
+    st = scale_below(4.0 * Wm * hm, Wm);
 }
 
 // One step: the cell [x, y) closes, E (the piece ending at y, P on equal
@@ -271,7 +339,7 @@ __device__ __forceinline__ void adj_step(AdjChain &ch, double p)
     const uint32_t aQ = ch.w.S - ch.w.q;  // Q's record address at this step
     const d2 N = ch.w.template advance<K>(c);
     // E's record address is the walk's q plus K records
-    lds_add(grad_slot<K * 8>(ch.w.q, ch.gb), ch.Wv * gE);
+    lds_add(grad_slot<K * 8>(ch.w.q, ch.gb), ch.Wv, gE);
     double dE = hPQ - hval<double, HK>(N.y, vO, p);
     double vOc = vO;
     if (tP == tQ && y < S) {
@@ -280,10 +348,10 @@ __device__ __forceinline__ void adj_step(AdjChain &ch, double p)
         const double vON = ((lds_d2)(size_t)(aQ + (uint32_t)sizeof(Rec<double>)))->y;
         dE = 0.5 * (dE + hdiff<HK>(vP, N.y, vON, p));
         const double dO = 0.5 * (hdiff<HK>(vQ, vON, vP, p) + hdiff<HK>(vQ, vON, N.y, p));
-        lds_add(grad_slot<kAdjGtOffset>(aQ, ch.gb), ch.Wt * dO);
+        lds_add(grad_slot<kAdjGtOffset>(aQ, ch.gb), ch.Wt, dO);
         vOc = vON;
     }
-    lds_add(grad_slot<K * 8 + kAdjGtOffset>(ch.w.q, ch.gb), ch.Wt * dE);
+    lds_add(grad_slot<K * 8 + kAdjGtOffset>(ch.w.q, ch.gb), ch.Wt, dE);
     ch.P = N;
     ch.tQ = max_raw(tP, tQ);
     ch.vQ = vOc;
@@ -302,7 +370,7 @@ __device__ __forceinline__ void adj_block(AdjChain &ch, double p,
 // the walk's q is P's record address).
 __device__ __forceinline__ void adj_flush(const AdjChain &ch)
 {
-    lds_add(grad_slot<0>(ch.w.S - ch.w.q, ch.gb), ch.Wv * ch.gQ);  // P's is 0 (just loaded)
+    lds_add(grad_slot<0>(ch.w.S - ch.w.q, ch.gb), ch.Wv, ch.gQ);  // P's is 0 (just loaded)
 }
 
 __device__ __forceinline__ int32_t adj_pair_steps(int32_t na, int32_t nb)
@@ -342,8 +410,8 @@ __device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
     pair_start<double>(lrec, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
     adj_load<HK>(ch, lrec, i0, j0, p);
     ch.x = x;
-    ch.Wt = sh.part[k];
-    ch.Wv = ch.Wt * gunit<HK>(p);
+    ch.Wt = sh.part[k] * ch.st;
+    ch.Wv = sh.part[k] * gunit<HK>(p) * ch.sv;
     ch.left = adj_pair_steps(ch.rn, ch.cn) - (int32_t)d;
     if (x > 0.0 && x < sentinel<double>() && min_raw(ch.P.x, ch.tQ) == x) {
         // the run starts at the width-0 second half of a tie, whose time
@@ -356,7 +424,7 @@ __device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
         double dP, dQ, hPQ;
         step_terms<HK>(ch.P.y, ch.vQ, p, dP, dQ, hPQ);
         const double dE = hPQ - hval<double, HK>(vN0, vO0, p);
-        lds_add(grad_slot<kAdjGtOffset>(aE, ch.gb), -(ch.Wt * dE));
+        lds_add(grad_slot<kAdjGtOffset>(aE, ch.gb), -ch.Wt, dE);
     }
 }
 
@@ -392,19 +460,22 @@ __device__ __forceinline__ void adj_next_pair(AdjChain &ch, const TileShared &sh
     ch.cn = cn;
     adj_load<HK>(ch, lrec, rb, cb, p);
     ch.x = 0.0;
-    ch.Wt = sh.part[k];
-    ch.Wv = ch.Wt * gunit<HK>(p);
+    ch.Wt = sh.part[k] * ch.st;
+    ch.Wv = sh.part[k] * gunit<HK>(p) * ch.sv;
     ch.left = adj_pair_steps(rn, cn);
 }
 
 template <int HK>
 __device__ __forceinline__ void adj_lane_chain(const TileShared &sh,
                                                const Rec<double> *lrec, uint32_t gb,
-                                               int64_t s, int64_t e, int32_t k, int32_t C,
-                                               bool diag, int gram, double p)
+                                               double sv, double st, int64_t s, int64_t e,
+                                               int32_t k,
+                                               int32_t C, bool diag, int gram, double p)
 {
     AdjChain ch;
     ch.gb = gb;
+    ch.sv = sv;
+    ch.st = st;
     // (an LDS tile: its step prefix is the 32-bit one)
     adj_begin<HK>(ch, sh, lrec, k, s - sh.pw[k], C, p);
     for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
@@ -432,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     int64_t *pw64 = reinterpret_cast<int64_t *>(lrec);  // wide step prefix
     // gradient slots follow the records: dL/dv of record q at lg[q], dL/dt
     // of its end time at lg[kAdjLdsRecords + q] (kAdjLdsRecords records a
-    // tile)
+    // tile), as 64-bit fixed-point sums at the tile's scales (lds_add)
     double *lg = reinterpret_cast<double *>(lrec + kAdjLdsRecords);
     const uint32_t gb = lds_address(lg) - (lds_address(lrec) >> 1);
     const Rec<double> *grec = reinterpret_cast<const Rec<double> *>(args.ws + h.off_rec);
@@ -461,6 +532,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             }
         // pair weights: W = (G_ij + G_ji) * chain for i != j, G_ii on the
         // diagonal; stored in the partial-sum slots (unused here)
+        double mw = 0.0, mv = 0.0, ml = 0.0;  // this thread's largest |W|, |v|, piece
         if (tid < npairs) {
             const int r = div_by_c(tid, sh.cmag), c = tid - r * C;
             const int64_t i = D.r_lo + r, j = D.c_lo + c;
@@ -475,16 +547,55 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 }
             }
             sh.part[tid] = W;
+            mw = fabs(W);
+        }
+        if (!gmode) {
+            const double S = sentinel<double>();
+            for (int64_t q = tid; q < nslots; q += kThreads) {
+                const Rec<double> rq = lrec[q];
+                mv = fmax(mv, fabs(rq.v));
+                // a piece starts at the previous record's end time, or at 0
+                // where that record is a sentinel (a PCF's first piece: the
+                // record before it ends the previous PCF, or pads, or q
+                // starts a block)
+                const double t0 = (q == 0 || q == D.rrecs) ? 0.0 : lrec[q - 1].t;
+                if (rq.t < S)
+                    ml = fmax(ml, rq.t - (t0 < S ? t0 : 0.0));
+            }
+            // the tile's maxima through the wave's lanes, then one slot per
+            // wave (the tail-rule values of the scan, unused by the adjoint)
+            for (int h = 32; h >= 1; h >>= 1) {
+                mw = fmax(mw, __shfl_xor(mw, h, 64));
+                mv = fmax(mv, __shfl_xor(mv, h, 64));
+                ml = fmax(ml, __shfl_xor(ml, h, 64));
+            }
+            if ((tid & 63) == 0) {
+                sh.rlast[tid >> 6] = mw;
+                sh.rlast[16 + (tid >> 6)] = mv;
+                sh.clast[tid >> 6] = ml;
+            }
         }
         sync_lds();
         loop.take_next(args.ws);
+        double sv = 1.0, st = 1.0;  // slot scales (powers of two: exact inverses)
+        if (!gmode) {
+            double Wm = 0.0, vm = 0.0, Lm = 0.0;
+            for (int w = 0; w < kThreads / 64; ++w) {
+                Wm = fmax(Wm, sh.rlast[w]);
+                vm = fmax(vm, sh.rlast[16 + w]);
+                Lm = fmax(Lm, sh.clast[w]);
+            }
+            slot_scales<HK>(Wm, vm, Lm, p, sv, st);
+        }
+        const double isv = 1.0 / sv, ist = 1.0 / st;
         pc.mark(kPhaseStart);
 
         // this lane's share of the tile's steps
         int64_t s, e;
         lane_steps(sh, tid, total, s, e);
         if (s < e && !gmode) {
-            adj_lane_chain<HK>(sh, lrec, gb, s, e, sh.pairof[tid], C, diag, args.gram, p);
+            adj_lane_chain<HK>(sh, lrec, gb, sv, st, s, e, sh.pairof[tid], C, diag, args.gram,
+                               p);
         } else if (s < e) {
             int32_t k = sh.pairof[tid];
             int64_t d = s - pw_at(sh, pw64, k);
@@ -562,8 +673,9 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             if (kk + 1 >= ns[which])
                 continue;
             frow[u] = rec - (pcf0 + which) * kPad;
-            fv[u] = lg[q];
-            ft[u] = lg[kAdjLdsRecords + q];
+            const long long *li = reinterpret_cast<const long long *>(lg);
+            fv[u] = (double)li[q] * isv;
+            ft[u] = (double)li[kAdjLdsRecords + q] * ist;
         }
         pc.mark(kPhaseFinish);
         if (has_next) {

@@ -82,6 +82,24 @@ def test_adjoint_ties_dyadic():
         assert _close(gt, rt) and _close(gv, rv), name
 
 
+@pytest.mark.parametrize("vscale,tscale", [(1e80, 1e-60), (1e-70, 1e90), (1.0, 1.0)])
+def test_adjoint_extreme_magnitudes_and_weights(vscale, tscale):
+    # LDS tiles accumulate their gradient slots in 64-bit fixed point at a
+    # power-of-two scale taken from the tile's own weights, values and piece
+    # lengths: magnitudes far from 1, and pair weights spread over twelve
+    # decades within one tile, stay at the FP64 bar
+    o, t, v = _set(11, 60, 2, 40)
+    t, v = t * tscale, v * vscale
+    rng = np.random.default_rng(12)
+    G = rng.choice([-1.0, 1.0], size=(60, 60)) * 10.0 ** rng.uniform(-6, 6, size=(60, 60))
+    for name, kind, p, okind in CASES:
+        gt, gv = _gpu_grad(o, t, v, kind, p, G)
+        rt, rv = oracle.backward(okind, p, o, t, v, G)
+        assert np.all(np.isfinite(gt)) and np.all(np.isfinite(gv)), name
+        assert _close(gt, rt), (name, np.max(np.abs(gt - rt)), np.max(np.abs(rt)))
+        assert _close(gv, rv), (name, np.max(np.abs(gv - rv)), np.max(np.abs(rv)))
+
+
 def test_adjoint_long_pcfs_global_path():
     rng = np.random.default_rng(4)
     counts = np.array([20, 6000, 15, 5000, 30])
