@@ -98,11 +98,11 @@ typedef struct {
 enum {
     PCF_UPPER_ONLY = 1u,    /* write only (i,j) with i <= j of symmetric parts */
     PCF_VALIDATE = 2u,      /* check the data contract first (synchronises)   */
-    PCF_DETERMINISTIC = 4u, /* bit-identical results run to run: always true
-                                of the matrix calls (fixed-order partial sums
-                                for a given plan); refused by
-                                pcf_pairwise_backward (PCF_EUNSUPPORTED),
-                                whose gradient sums use atomics            */
+    PCF_DETERMINISTIC = 4u, /* bit-identical results run to run for a given
+                                plan: always true of the matrix calls
+                                (fixed-order partial sums); for
+                                pcf_pairwise_backward, integer gradient sums
+                                (see there)                                 */
     PCF_REUSE_PLAN = 8u,    /* reuse the plan already in ws (see above)       */
     PCF_RECORDS_PACKED = 16u /* with PCF_REUSE_PLAN: ws also still holds the
                                 packed records of these very t and v (e.g. an
@@ -177,9 +177,19 @@ pcf_status pcf_pairwise_lp_noalloc(const pcf_set *X, pcf_kind kind, double p,
  * entries are 0. At an exact tie of two PCFs' breakpoint times the mean of
  * the one-sided time derivatives is used. Each pair's merge is recomputed;
  * nothing is stored between forward and backward. FP64 only
- * (PCF_EUNSUPPORTED for FP32). Gradient sums use atomics: the summation
- * order, and the last bits, may vary between runs, so PCF_DETERMINISTIC is
- * refused (PCF_EUNSUPPORTED, before any device work). */
+ * (PCF_EUNSUPPORTED for FP32). A tile sums its gradient terms in 64-bit fixed
+ * point at power-of-two scales bounded from its own weights, values and
+ * piece lengths (order-independent), and adds the sums to grad_t, grad_v with
+ * FP64 atomics, whose order, and so the last bits, may vary between runs.
+ * With PCF_DETERMINISTIC the sums in HBM are 64-bit fixed point too, at
+ * scales bounded from the whole set (largest |w_ij|, |v| and piece length,
+ * found by two extra passes over grad_out, fwd_out and the records): grad_t
+ * and grad_v hold the integer sums until a last pass converts them in place,
+ * and the result is bit-identical run to run for a given plan and tile
+ * shape. Each term is then rounded to a unit of about 2^-61 (n + 1) times
+ * the set's largest possible term, so gradients far below that lose
+ * relative precision. PCF_EUNSUPPORTED for more than 2,097,120 PCFs with
+ * PCF_DETERMINISTIC. */
 pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
                                  const void *grad_out, int64_t ldg,
                                  const void *fwd_out, int64_t ldf,

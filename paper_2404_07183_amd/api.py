@@ -16,7 +16,7 @@ import torch
 
 from . import _lib
 from ._lib import (PCF_F32, PCF_F64, PCF_GRAM, PCF_LP, PCF_LP_POW,
-                   PCF_RECORDS_PACKED, PCF_REUSE_PLAN, PCF_UPPER_ONLY,
+                   PCF_DETERMINISTIC, PCF_RECORDS_PACKED, PCF_REUSE_PLAN, PCF_UPPER_ONLY,
                    PCF_VALIDATE, PCF_WEIGHT_EXP, PCF_WEIGHT_POW, PCF_REDUCE_SUM,
                    PCF_REDUCE_MEAN, PCF_REDUCE_MAX, PCF_REDUCE_MIN, PCF_REDUCE_STD, check)
 
@@ -425,10 +425,12 @@ def norms(X, p=2.0, a=0.0, b=math.inf, *, power=False, out=None, stream=None):
 
 
 def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None,
-                      packed=False):
+                      packed=False, deterministic=False):
     """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, FP64).
     A ``workspace`` that served the previous backward call on the same set
-    keeps its plan; ``packed=True`` as in ``pdist``."""
+    keeps its plan; ``packed=True`` as in ``pdist``. ``deterministic=True``
+    sums the gradients in 64-bit fixed point at the set's scales: the same
+    bits on every run (PCF_DETERMINISTIC)."""
     Xc = X.c_struct()
     grad_out = grad_out.to(torch.float64).contiguous()
     if grad_out.shape != (X.n, X.n) or grad_out.device != X.t.device:
@@ -446,6 +448,8 @@ def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream
             raise ValueError("packed=True needs an earlier call on the same set, "
                              "data and workspace")
         flags |= PCF_RECORDS_PACKED
+    if deterministic:
+        flags |= PCF_DETERMINISTIC
     fptr, ldf = (fwd_out.data_ptr(), fwd_out.stride(0)) if fwd_out is not None else (None, 0)
     st = _lib.pcf_pairwise_backward(Xc, kind, float(p), grad_out.data_ptr(),
                                     grad_out.stride(0), fptr, ldf, gt.data_ptr(),
@@ -653,7 +657,7 @@ class PairwiseMatrix(torch.autograd.Function):
     maps the gradients back through the warp and the restriction."""
 
     @staticmethod
-    def forward(ctx, t, v, X, kind, p, bounds, weight):
+    def forward(ctx, t, v, X, kind, p, bounds, weight, deterministic=False):
         Xv = X.with_values(t.detach(), v.detach())
         sets = [Xv]
         if bounds is not None:
@@ -662,6 +666,7 @@ class PairwiseMatrix(torch.autograd.Function):
             sets.append(warp(sets[-1], weight[0], weight[1]))
         out = _forward(sets[-1], kind, p, None, None, False, False, None, None)
         ctx.sets, ctx.kind, ctx.p, ctx.bounds, ctx.weight = sets, kind, p, bounds, weight
+        ctx.deterministic = deterministic
         ctx.save_for_backward(out)
         return out
 
@@ -671,7 +676,8 @@ class PairwiseMatrix(torch.autograd.Function):
         need_fwd = ctx.kind == PCF_LP and ctx.p != 1.0
         sets = ctx.sets
         gt, gv = pairwise_backward(sets[-1], ctx.kind, ctx.p, grad_out,
-                                   out.to(torch.float64) if need_fwd else None)
+                                   out.to(torch.float64) if need_fwd else None,
+                                   deterministic=ctx.deterministic)
         k = len(sets) - 1
         if ctx.weight is not None:
             gt, gv = warp_backward(sets[k - 1], ctx.weight[0], ctx.weight[1], sets[k], gt, gv)
@@ -679,11 +685,13 @@ class PairwiseMatrix(torch.autograd.Function):
         if ctx.bounds is not None:
             gt, gv = restrict_backward(sets[k - 1], ctx.bounds[0], ctx.bounds[1], sets[k],
                                        gt, gv)
-        return gt, gv, None, None, None, None, None
+        return gt, gv, None, None, None, None, None, None
 
 
-def pairwise_matrix(X, t, v, kind=PCF_LP, p=1.0, bounds=None, weight=None):
+def pairwise_matrix(X, t, v, kind=PCF_LP, p=1.0, bounds=None, weight=None,
+                    deterministic=False):
     """Differentiable F(C) over ``X``'s offsets with times ``t`` and values
     ``v`` (tensors that may require grad); ``bounds=(a, b)`` integrates over
-    [a, b), ``weight=("exp"|"pow", c)`` with the time weight (as ``pdist``)."""
-    return PairwiseMatrix.apply(t, v, X, kind, p, bounds, weight)
+    [a, b), ``weight=("exp"|"pow", c)`` with the time weight (as ``pdist``);
+    ``deterministic=True``: bit-identical gradients run to run."""
+    return PairwiseMatrix.apply(t, v, X, kind, p, bounds, weight, deterministic)

@@ -965,12 +965,12 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
         return fail(PCF_EINVAL, "p must be finite and >= 1");
     if (X->dtype != PCF_F64)
         return fail(PCF_EUNSUPPORTED, "the adjoint is implemented for FP64 only");
-    if (flags & PCF_DETERMINISTIC)
-        return fail(PCF_EUNSUPPORTED, "the adjoint accumulates gradients with atomics: "
-                                      "PCF_DETERMINISTIC is not available for it");
     if (X->n == 0)
         return PCF_OK;
     const bool chain = kind == PCF_LP && p != 1.0;
+    const bool fixed = (flags & PCF_DETERMINISTIC) != 0;
+    if (fixed && (X->n + 31) / 32 > 65535)
+        return fail(PCF_EUNSUPPORTED, "PCF_DETERMINISTIC takes at most 2,097,120 PCFs");
     if (!grad_out || !grad_t || !grad_v || !ws)
         return fail(PCF_EINVAL, "grad_out, grad_t, grad_v or ws is NULL");
     if (chain && !fwd_out)
@@ -1016,11 +1016,23 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
     a.p = p;
     a.chain = chain ? 1 : 0;
     a.gram = kind == PCF_GRAM ? 1 : 0;
+    a.n = X->n;
+    a.fixed = fixed ? 1 : 0;
     const int hk = kind == PCF_GRAM ? HK_PROD
                                     : (p == 1.0 ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW));
+    if (fixed) {
+        e = launch_adj_bounds(a, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "adjoint bounds launch");
+    }
     e = launch_backward(hk, a, tile_grid(reuse ? nullptr : &plan, reuse), s);
     if (e != hipSuccess)
         return hip_fail(e, "adjoint kernel launch");
+    if (fixed) {
+        e = launch_adj_finish(hk, a, P, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "adjoint finish launch");
+    }
     return PCF_OK;
 }
 

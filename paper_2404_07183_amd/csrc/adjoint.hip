@@ -51,6 +51,100 @@ __device__ __forceinline__ double dhda(double a, double b, double p)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-point gradient sums. A gradient term w g (w a pair weight already
+// multiplied by a power-of-two scale 2^s) is added as the 64-bit integer
+// floor(y), y = w g + 1/2: its high word floor(y / 2^32), its low word the
+// remainder y - 2^32 floor(y / 2^32), which lies in [0, 2^32) (exact but for
+// its own rounding below one unit). So each add is w g within one unit 2^-s,
+// or within the FP64 rounding of w g where that is coarser (|y| < 2^62).
+// Integer sums are exact modulo 2^64 and do not depend on the order of the
+// adds; the scales are chosen from bounds on the terms so that no final sum
+// leaves the 64-bit range (partial sums may wrap).
+__device__ __forceinline__ long long fixed_of(double w, double g)
+{
+    const double y = fma(w, g, 0.5);
+    const double hi = floor(y * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, y);
+    return (long long)(((unsigned long long)(unsigned)(int)hi << 32) |
+                       (unsigned long long)(unsigned)lo);
+}
+
+// The exponent s with B 2^s < 2^target and Wm 2^s <= 2^1000, at least
+// -1000 (B > 0; taken as 2^1024 where it overflowed; 0 where B is 0 or NaN,
+// whose terms are all 0).
+__device__ __forceinline__ int scale_exp(double B, double Wm, int target)
+{
+    if (!(B > 0.0))
+        return 0;
+    int e = 1024, ew = 0;
+    if (isfinite(B))
+        frexp(B, &e);  // B < 2^e
+    if (Wm > 0.0)
+        frexp(Wm, &ew);
+    int sh = target - e;
+    sh = sh > 1000 - ew ? 1000 - ew : sh;
+    return sh < -1000 ? -1000 : sh;
+}
+
+// Bounds on one pair's gradient terms, from the largest |W|, |v| and piece
+// length Wm, vm, Lm of the pairs and pieces concerned: a value gradient over
+// one piece is at most |W| max|dh/da| times the piece's length (Bv); a time
+// gradient is at most 2 |W| max|h| (a jump of h, or the mean of two at a
+// tie), and any single add of one is a part of such a term at most twice
+// that (Bt = 4 Wm max|h|). (|a - b| <= 2 vm.)
+template <int HK>
+__device__ __forceinline__ void pair_bounds(double Wm, double vm, double Lm, double p,
+                                            double &Bv, double &Bt)
+{
+    const double a = 2.0 * vm;
+    double dh, hm;
+    if constexpr (HK == kAbs) {
+        dh = 1.0;
+        hm = a;
+    } else if constexpr (HK == kSqr) {
+        dh = 2.0 * a;
+        hm = a * a;
+    } else if constexpr (HK == kProd) {
+        dh = vm;
+        hm = vm * vm;
+    } else {
+        dh = p * pow(a, p - 1.0);
+        hm = pow(a, p);
+    }
+    Bv = Wm * dh * Lm;
+    Bt = 4.0 * Wm * hm;
+}
+
+// The set's scale exponents of the deterministic adjoint's sums in HBM: a
+// breakpoint's gradient sums one term per partner, at most n + 1 of them (a
+// diagonal Gram pair adds twice), so (n + 1) B below 2^61 keeps every final
+// sum, and the rounding of its adds, inside 64 bits.
+template <int HK>
+__device__ __forceinline__ void set_exps(const WsHeader &h, int64_t n, double p, int &ev,
+                                         int &et)
+{
+    const double Wm = __longlong_as_double((long long)h.adj_max[0]);
+    const double vm = __longlong_as_double((long long)h.adj_max[1]);
+    const double Lm = __longlong_as_double((long long)h.adj_max[2]);
+    double Bv, Bt;
+    pair_bounds<HK>(Wm, vm, Lm, p, Bv, Bt);
+    const double m = (double)(n + 1);
+    ev = scale_exp(m * Bv, Wm, 61);
+    et = scale_exp(m * Bt, Wm, 61);
+}
+
+// v 2^-k rounded half up, for a sum v in units 2^-s1 brought to units
+// 2^-(s1 - k). (The bounds keep a left shift's result inside 64 bits.)
+__device__ __forceinline__ long long fixed_rescale(long long v, int k)
+{
+    if (k <= 0)
+        return k <= -63 ? 0 : (long long)((unsigned long long)v << -k);
+    if (k >= 64)
+        return 0;
+    return (v >> k) + ((v >> (k - 1)) & 1);
+}
+
 // Gradient accumulators of one side of a pair: slot q holds (dL/dt, dL/dv)
 // of record q -- record q is (t_{k+1}, v_k) of the PCF, so the value
 // gradient of piece k goes to slot k and the time gradient of breakpoint
@@ -61,15 +155,26 @@ struct GradSink {
     double *gt;  // indexed by record index
     double *gv;
     int32_t last;  // record index of the PCF's last row (fixed value)
+    int fixed;     // 1: the arrays hold fixed-point sums at scales st, sv
+    double st, sv;
 };
 
 __device__ __forceinline__ void sink_add_t(const GradSink &s, int32_t q, double x)
 {
-    atomicAdd(&s.gt[q], x);
+    if (s.fixed)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&s.gt[q]),
+                  (unsigned long long)fixed_of(x, s.st));
+    else
+        atomicAdd(&s.gt[q], x);
 }
 __device__ __forceinline__ void sink_add_v(const GradSink &s, int32_t q, double x)
 {
-    if (q < s.last)
+    if (q >= s.last)
+        return;
+    if (s.fixed)
+        atomicAdd(reinterpret_cast<unsigned long long *>(&s.gv[q]),
+                  (unsigned long long)fixed_of(x, s.sv));
+    else
         atomicAdd(&s.gv[q], x);
 }
 
@@ -175,7 +280,7 @@ struct AdjChain {
     double x;              // start of the current cell
     double Wv, Wt;         // pair weight times the unit of dh/da; pair weight
                            // (times the tile's value and time slot scales)
-    double sv, st;         // the tile's slot scales (slot_scales)
+    double sv, st;         // the tile's slot scales (tile_exps)
     int32_t left;          // steps left in the current pair
     int32_t k, r, c, rb, rn, cb, cn;
 };
@@ -241,74 +346,13 @@ __device__ __forceinline__ lds_f64 *grad_slot(uint32_t a, uint32_t gb)
     return (lds_f64 *)(size_t)((a >> 1) + gb + Extra);
 }
 
-// The slots hold fixed-point sums: the add of a gradient term w g (w a pair
-// weight already multiplied by the tile's scale 2^s for the slot's kind)
-// adds floor(y), y = w g + 1/2, as a 64-bit integer: its high word
-// floor(y / 2^32), its low word the remainder y - 2^32 floor(y / 2^32),
-// in [0, 2^32) (exact but for its own rounding below one unit). So each add
-// is w g within one unit 2^-s, or within the FP64 rounding of w g where that
-// is coarser (|y| < 2^57 here). Integer LDS atomics are faster than FP64 ones; the
-// adds are exact modulo 2^64, so a tile's sums no longer depend on their
-// order.
+// LDS slot add: w g to the nearest unit of the tile's fixed point (w carries
+// the tile's scale). Integer LDS atomics are faster than FP64 ones; the adds
+// are exact modulo 2^64, so a tile's sums do not depend on their order.
 __device__ __forceinline__ void lds_add(lds_f64 *p, double w, double g)
 {
-    const double y = fma(w, g, 0.5);
-    const double hi = floor(y * 0x1p-32);
-    const double lo = fma(hi, -0x1p32, y);
-    const unsigned long long n =
-        ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
-    __hip_atomic_fetch_add((lds_i64 *)p, (long long)n, __ATOMIC_RELAXED,
+    __hip_atomic_fetch_add((lds_i64 *)p, fixed_of(w, g), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// 2^s with B 2^s < 2^57 and Wm 2^s <= 2^1000 (B > 0; a power of two above
-// DBL_MAX where B overflowed)
-__device__ __forceinline__ double scale_below(double B, double Wm)
-{
-    if (!(B > 0.0))
-        return 1.0;
-    int e = 1024, ew;
-    if (isfinite(B))
-        frexp(B, &e);  // B < 2^e
-    frexp(Wm, &ew);
-    int sh = 57 - e;
-    sh = sh > 1000 - ew ? 1000 - ew : sh;
-    return ldexp(1.0, sh < -1000 ? -1000 : sh);
-}
-
-// The tile's slot scales, one for the value slots and one for the time
-// slots (their gradients may differ by any factor). A kept slot sums, over
-// at most 32 partners of its PCF (33 terms: a diagonal Gram pair adds
-// twice), one pair's gradient each: a value gradient over one piece, at most
-// |W| max|dh/da| times the piece's length, or a time gradient, at most
-// 2 |W| max|h| (a jump of h, or the mean of two at a tie); every single add
-// is a part of one such term and at most twice its bound. With Wm, vm and Lm
-// the tile's largest |W|, |v| and piece length, Bv = Wm max|dh/da| Lm and
-// Bt = 4 Wm max|h| bound both kinds, and each scale puts its bound below
-// 2^57: a slot's final sum stays below 33 * 2^57 < 2^63 (partial sums may
-// wrap). (|a - b| <= 2 vm.) Slots of the fixed last value and of padding
-// may take larger adds; they are dropped.
-template <int HK>
-__device__ __forceinline__ void slot_scales(double Wm, double vm, double Lm, double p,
-                                            double &sv, double &st)
-{
-    const double a = 2.0 * vm;
-    double dh, hm;
-    if constexpr (HK == kAbs) {
-        dh = 1.0;
-        hm = a;
-    } else if constexpr (HK == kSqr) {
-        dh = 2.0 * a;
-        hm = a * a;
-    } else if constexpr (HK == kProd) {
-        dh = vm;
-        hm = vm * vm;
-    } else {
-        dh = p * pow(a, p - 1.0);
-        hm = pow(a, p);
-    }
-    sv = scale_below(Wm * dh * Lm, Wm);
-    st = scale_below(4.0 * Wm * hm, Wm);
 }
 
 // One step: the cell [x, y) closes, E (the piece ending at y, P on equal
@@ -510,6 +554,11 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     const int64_t *offsets = args.offsets;
     const int tid = threadIdx.x;
     const double p = args.p;
+    // deterministic mode: the set's scales of the sums in HBM
+    int gev = 0, get = 0;
+    if (args.fixed)
+        set_exps<HK>(h, args.n, p, gev, get);
+    const double gsv = ldexp(1.0, gev), gst = ldexp(1.0, get);
 
     PhaseClock pc;  // (cycle counters only in timing builds)
     TileLoop loop;
@@ -577,7 +626,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         }
         sync_lds();
         loop.take_next(args.ws);
-        double sv = 1.0, st = 1.0;  // slot scales (powers of two: exact inverses)
+        // the tile's slot scales 2^ev, 2^et. A kept slot sums, over at most
+        // 32 partners of its PCF (33 terms: a diagonal Gram pair adds
+        // twice), one pair's gradient each, within the pair bounds of the
+        // tile's largest |W|, |v| and piece length; each bound below 2^57
+        // keeps the slot's final sum below 33 * 2^57 < 2^63. Slots of the
+        // fixed last value and of padding may take larger adds; they are
+        // dropped.
+        int ev = 0, et = 0;
         if (!gmode) {
             double Wm = 0.0, vm = 0.0, Lm = 0.0;
             for (int w = 0; w < kThreads / 64; ++w) {
@@ -585,9 +641,13 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 vm = fmax(vm, sh.rlast[16 + w]);
                 Lm = fmax(Lm, sh.clast[w]);
             }
-            slot_scales<HK>(Wm, vm, Lm, p, sv, st);
+            double Bv, Bt;
+            pair_bounds<HK>(Wm, vm, Lm, p, Bv, Bt);
+            ev = scale_exp(Bv, Wm, 57);
+            et = scale_exp(Bt, Wm, 57);
         }
-        const double isv = 1.0 / sv, ist = 1.0 / st;
+        const double sv = ldexp(1.0, ev), st = ldexp(1.0, et);
+        const double isv = ldexp(1.0, -ev), ist = ldexp(1.0, -et);
         pc.mark(kPhaseStart);
 
         // this lane's share of the tile's steps
@@ -613,6 +673,9 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 sa.gv = args.grad_v - i * kPad;
                 sb.gt = args.grad_t - j * kPad;
                 sb.gv = args.grad_v - j * kPad;
+                sa.fixed = sb.fixed = args.fixed;
+                sa.st = sb.st = gst;
+                sa.sv = sb.sv = gsv;
                 adjoint_pair<HK>(grec, A, sh.rn[r], B, sh.cn[c], d, m, sh.part[k], p, sa, sb);
                 s += m;
                 d = 0;
@@ -674,8 +737,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 continue;
             frow[u] = rec - (pcf0 + which) * kPad;
             const long long *li = reinterpret_cast<const long long *>(lg);
-            fv[u] = (double)li[q] * isv;
-            ft[u] = (double)li[kAdjLdsRecords + q] * ist;
+            if (args.fixed) {
+                // the sums in the set's units (bit patterns in fv, ft)
+                fv[u] = __longlong_as_double(fixed_rescale(li[q], ev - gev));
+                ft[u] = __longlong_as_double(fixed_rescale(li[kAdjLdsRecords + q], et - get));
+            } else {
+                fv[u] = (double)li[q] * isv;
+                ft[u] = (double)li[kAdjLdsRecords + q] * ist;
+            }
         }
         pc.mark(kPhaseFinish);
         if (has_next) {
@@ -686,6 +755,16 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         for (int u = 0; u < kAdjStageUnroll; ++u) {
             if (frow[u] < 0)
                 continue;
+            if (args.fixed) {
+                const unsigned long long bv = (unsigned long long)__double_as_longlong(fv[u]);
+                const unsigned long long bt = (unsigned long long)__double_as_longlong(ft[u]);
+                if (bv != 0)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&args.grad_v[frow[u]]), bv);
+                if (bt != 0)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&args.grad_t[frow[u] + 1]),
+                              bt);
+                continue;
+            }
             if (fv[u] != 0.0)
                 atomicAdd(&args.grad_v[frow[u]], fv[u]);
             if (ft[u] != 0.0)
@@ -732,6 +811,142 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
     if (blocks > 4096)
         blocks = 4096;
     hipLaunchKernelGGL(zero_doubles, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic adjoint: the set's bounds, then the conversion of its sums.
+
+// Largest value over the block into *dst (bit patterns of non-negative
+// doubles order like the doubles).
+__device__ __forceinline__ void block_max_to(double m, unsigned long long *dst, double *red)
+{
+    for (int hop = 32; hop >= 1; hop >>= 1)
+        m = fmax(m, __shfl_xor(m, hop, 64));
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        red[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < nw; ++k)
+            m = fmax(m, red[k]);
+        if (m > 0.0)
+            atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// The largest |W| of the pairs (i, j), i <= j, of a 32 x 32 block of the
+// matrix above the diagonal (W as the adjoint kernel forms it; the chain
+// factor taken from F_ij and F_ji alike, whichever the tile reads). G_ji
+// comes through an LDS transpose so that both reads are coalesced.
+__global__ __launch_bounds__(256) void adj_bounds_pairs(BwdArgs a)
+{
+    __shared__ double gT[32][33], fT[32][33];
+    __shared__ double red[4];
+    const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+    if (i0 > j0)
+        return;  // (the whole block)
+    WsHeader *h = reinterpret_cast<WsHeader *>(a.ws);
+    const int64_t n = a.n;
+    const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+    for (int r = r0; r < 32; r += 8) {
+        const int64_t j = j0 + r, i = i0 + c;
+        const bool in = i < n && j < n;
+        gT[r][c] = in ? a.grad_out[j * a.ldg + i] : 0.0;
+        fT[r][c] = (in && a.chain) ? a.fwd_out[j * a.ldf + i] : 0.0;
+    }
+    __syncthreads();
+    double m = 0.0;
+    for (int r = r0; r < 32; r += 8) {
+        const int64_t i = i0 + r, j = j0 + c;
+        if (i >= n || j >= n || i > j || (i == j && !a.gram))
+            continue;
+        double W = a.grad_out[i * a.ldg + j];
+        if (i != j)
+            W += gT[c][r];
+        if (a.chain) {
+            const double F1 = a.fwd_out[i * a.ldf + j], F2 = fT[c][r];
+            const double W1 = F1 > 0.0 ? W * (1.0 / a.p) * pow(F1, 1.0 - a.p) : 0.0;
+            const double W2 = F2 > 0.0 ? W * (1.0 / a.p) * pow(F2, 1.0 - a.p) : 0.0;
+            W = fmax(fabs(W1), fabs(W2));
+        }
+        m = fmax(m, fabs(W));
+    }
+    block_max_to(m, &h->adj_max[0], red);
+}
+
+// The largest |v| and piece length of the packed records (a piece starts
+// at the previous record's end time, or at 0 after a sentinel).
+__global__ __launch_bounds__(256) void adj_bounds_records(BwdArgs a)
+{
+    __shared__ double red[4];
+    WsHeader *h = reinterpret_cast<WsHeader *>(a.ws);
+    const Rec<double> *rec = reinterpret_cast<const Rec<double> *>(a.ws + h->off_rec);
+    const int64_t count = h->rec_count;
+    const double S = sentinel<double>();
+    double mv = 0.0, ml = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const Rec<double> r = rec[q];
+        mv = fmax(mv, fabs(r.v));
+        if (r.t < S) {
+            const double t0 = q > 0 ? rec[q - 1].t : 0.0;
+            ml = fmax(ml, r.t - (t0 < S ? t0 : 0.0));
+        }
+    }
+    block_max_to(mv, &h->adj_max[1], red);
+    __syncthreads();  // (red is reused)
+    block_max_to(ml, &h->adj_max[2], red);
+}
+
+hipError_t launch_adj_bounds(const BwdArgs &a, hipStream_t s)
+{
+    hipError_t e = launch_zero(reinterpret_cast<double *>(
+                                   a.ws + offsetof(WsHeader, adj_max)),
+                               3, s);
+    if (e != hipSuccess)
+        return e;
+    const int64_t nb = (a.n + 31) / 32;
+    if (nb > 65535)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(adj_bounds_pairs, dim3((unsigned)nb, (unsigned)nb), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(adj_bounds_records, dim3(1024), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// The fixed-point sums in grad_t, grad_v (P entries each) to FP64, in place.
+template <int HK>
+__global__ __launch_bounds__(256) void adj_finish(BwdArgs a, int64_t P)
+{
+    int ev, et;
+    set_exps<HK>(*reinterpret_cast<const WsHeader *>(a.ws), a.n, a.p, ev, et);
+    const double iv = ldexp(1.0, -ev), it = ldexp(1.0, -et);
+    long long *gt = reinterpret_cast<long long *>(a.grad_t);
+    long long *gv = reinterpret_cast<long long *>(a.grad_v);
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < P;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        a.grad_t[k] = (double)gt[k] * it;
+        a.grad_v[k] = (double)gv[k] * iv;
+    }
+}
+
+hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s)
+{
+    if (P <= 0)
+        return hipSuccess;
+    int64_t blocks = (P + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    const dim3 g((unsigned)blocks), b(256);
+    switch (hk) {
+    case kAbs: hipLaunchKernelGGL(adj_finish<kAbs>, g, b, 0, s, a, P); break;
+    case kSqr: hipLaunchKernelGGL(adj_finish<kSqr>, g, b, 0, s, a, P); break;
+    case kProd: hipLaunchKernelGGL(adj_finish<kProd>, g, b, 0, s, a, P); break;
+    default: hipLaunchKernelGGL(adj_finish<kPow>, g, b, 0, s, a, P); break;
+    }
     return hipGetLastError();
 }
 

@@ -74,7 +74,10 @@ struct WsHeader {
     int64_t rec_bytes;    // bytes per record (8 FP32, 16 FP64)
     int64_t first_bad;    // validation result (PCF index or -1)
     int64_t lds_records;  // records a tile may hold in LDS
-    int64_t reserved[5];
+    // deterministic adjoint: the largest |W|, |v| and piece length, as bit
+    // patterns (non-negative doubles order like their patterns)
+    unsigned long long adj_max[3];
+    int64_t reserved[2];
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 

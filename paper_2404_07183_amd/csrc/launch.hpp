@@ -41,6 +41,10 @@ struct BwdArgs {
     double p;
     int chain;               // 1: scale by dF/dI = (1/p) I^(1/p - 1)
     int gram;                // 1: diagonal pairs carry work (Gram)
+    int64_t n;               // PCFs in the set
+    int fixed;               // 1: deterministic: grad_t, grad_v hold 64-bit
+                             // fixed-point sums at the set's scales until
+                             // launch_adj_finish (needs launch_adj_bounds first)
 };
 
 template <typename T>
@@ -94,6 +98,11 @@ hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);
 hipError_t launch_backward(int hk, const BwdArgs &a, int grid, hipStream_t s);
+// Deterministic adjoint: the set's largest pair weight, |v| and piece length
+// into the workspace header (before launch_backward with a.fixed), and the
+// fixed-point sums converted to FP64 in place (after it).
+hipError_t launch_adj_bounds(const BwdArgs &a, hipStream_t s);
+hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // Raises a kernel's dynamic-LDS limit to `bytes` once per device (thread
 // safe: concurrent first calls from several host threads all wait for it).

@@ -269,14 +269,16 @@ def test_noalloc_refuses_oversized_sets_before_device_work():
     assert "#define PCF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in src
 
 
-def test_backward_refuses_deterministic_flag():
-    """The adjoint's atomic gradient sums are not bit-reproducible, so the
-    backward call refuses PCF_DETERMINISTIC before touching a device."""
+def test_backward_deterministic_size_limit():
+    """PCF_DETERMINISTIC on the adjoint bounds its pair weights over a grid of
+    32 x 32 blocks (at most 65,535 a side): larger sets are refused before
+    any device work."""
     lib = _lib.load()
-    off = np.array([0, 2, 4], dtype=np.int64)
+    n = 65535 * 32 + 1
+    off = np.arange(n + 1, dtype=np.int64) * 2
     fake = ctypes.c_void_p(0x1000)
-    X = _lib.pcf_set(2, fake, fake, fake, _lib.PCF_F64, off.ctypes.data)
-    st = lib.pcf_pairwise_backward(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, 2, None, 0, fake,
+    X = _lib.pcf_set(n, fake, fake, fake, _lib.PCF_F64, off.ctypes.data)
+    st = lib.pcf_pairwise_backward(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, n, None, 0, fake,
                                    fake, fake, 1 << 20, _lib.PCF_DETERMINISTIC, None)
     assert st == _lib.PCF_EUNSUPPORTED
     assert "DETERMINISTIC" in _lib.last_error()

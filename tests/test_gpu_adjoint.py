@@ -100,6 +100,86 @@ def test_adjoint_extreme_magnitudes_and_weights(vscale, tscale):
         assert _close(gv, rv), (name, np.max(np.abs(gv - rv)), np.max(np.abs(rv)))
 
 
+def _gpu_grad_det(o, t, v, kind, p, G):
+    X = api.PcfSet(o, t, v, device=DEV)
+    fwd = api.pdist(X, p) if (kind == api.PCF_LP and p != 1.0) else None
+    Gt = torch.as_tensor(G, device=DEV)
+    gt, gv = api.pairwise_backward(X, kind, p, Gt, fwd, deterministic=True)
+    return gt.cpu().numpy(), gv.cpu().numpy()
+
+
+@pytest.mark.parametrize("seed,N,nmin,nmax", [(2, 40, 2, 60), (7, 300, 1, 120)])
+def test_deterministic_adjoint_bitwise_and_oracle(seed, N, nmin, nmax):
+    # PCF_DETERMINISTIC: integer sums in HBM at the set's scales; two runs
+    # (fresh workspaces) give the same bits, and both meet the FP64 bar
+    o, t, v = _set(seed, N, nmin, nmax)
+    rng = np.random.default_rng(seed + 200)
+    G = rng.uniform(-1, 1, size=(N, N))
+    for name, kind, p, okind in CASES:
+        gt1, gv1 = _gpu_grad_det(o, t, v, kind, p, G)
+        gt2, gv2 = _gpu_grad_det(o, t, v, kind, p, G)
+        assert np.array_equal(gt1.view(np.int64), gt2.view(np.int64)), name
+        assert np.array_equal(gv1.view(np.int64), gv2.view(np.int64)), name
+        rt, rv = oracle.backward(okind, p, o, t, v, G)
+        assert _close(gt1, rt), (name, np.max(np.abs(gt1 - rt)), np.max(np.abs(rt)))
+        assert _close(gv1, rv), (name, np.max(np.abs(gv1 - rv)), np.max(np.abs(rv)))
+        assert np.all(gt1[o[:-1]] == 0) and np.all(gv1[o[1:] - 1] == 0)
+
+
+def test_deterministic_adjoint_global_path_and_ties():
+    # long PCFs (tiles whose records stay in HBM add each term to the
+    # fixed-point sums directly) and exact ties on a dyadic grid
+    rng = np.random.default_rng(4)
+    counts = np.array([20, 6000, 15, 5000, 30])
+    o = np.concatenate([[0], np.cumsum(counts)])
+    t = np.empty(o[-1])
+    v = rng.standard_normal(o[-1])
+    for i in range(len(counts)):
+        a, b = o[i], o[i + 1]
+        t[a:b] = np.concatenate([[0.0], np.cumsum(rng.exponential(0.01, b - a - 1))])
+        v[b - 1] = 0.0
+    G = rng.uniform(0, 1, size=(5, 5))
+    for name, kind, p, okind in (CASES[0], CASES[2], CASES[3]):
+        gt1, gv1 = _gpu_grad_det(o, t, v, kind, p, G)
+        gt2, gv2 = _gpu_grad_det(o, t, v, kind, p, G)
+        assert np.array_equal(gt1.view(np.int64), gt2.view(np.int64)), name
+        assert np.array_equal(gv1.view(np.int64), gv2.view(np.int64)), name
+        rt, rv = oracle.backward(okind, p, o, t, v, G)
+        assert _close(gt1, rt, 1e-10) and _close(gv1, rv, 1e-10), name
+    pcfs = []
+    for _ in range(30):
+        n = int(rng.integers(1, 12))
+        ticks = np.sort(rng.choice(np.arange(1, 20), size=n - 1, replace=False)) / 2.0
+        vv = rng.integers(-4, 5, size=n) / 2.0
+        vv[-1] = 0.0
+        pcfs.append((np.concatenate([[0.0], ticks]), vv))
+    o = np.concatenate([[0], np.cumsum([len(a) for a, _ in pcfs])])
+    t = np.concatenate([a for a, _ in pcfs])
+    v = np.concatenate([b for _, b in pcfs])
+    G = rng.integers(-3, 4, size=(30, 30)).astype(float)
+    for name, kind, p, okind in CASES[:4]:
+        gt, gv = _gpu_grad_det(o, t, v, kind, p, G)
+        rt, rv = oracle.backward(okind, p, o, t, v, G)
+        assert _close(gt, rt) and _close(gv, rv), name
+
+
+def test_deterministic_through_autograd():
+    o, t, v = _set(8, 50, 2, 40)
+    X = api.PcfSet(o, t, v, device=DEV)
+    W = torch.as_tensor(np.random.default_rng(9).uniform(0, 1, size=(50, 50)), device=DEV)
+    grads = []
+    for _ in range(2):
+        tt = torch.as_tensor(t, device=DEV).clone().requires_grad_(True)
+        vv = torch.as_tensor(v, device=DEV).clone().requires_grad_(True)
+        L = (W * api.pairwise_matrix(X, tt, vv, api.PCF_LP, 2.0, deterministic=True)).sum()
+        L.backward()
+        grads.append((tt.grad.cpu().numpy(), vv.grad.cpu().numpy()))
+    assert np.array_equal(grads[0][0].view(np.int64), grads[1][0].view(np.int64))
+    assert np.array_equal(grads[0][1].view(np.int64), grads[1][1].view(np.int64))
+    gt, gv = _gpu_grad(o, t, v, api.PCF_LP, 2.0, W.cpu().numpy())
+    assert _close(grads[0][0], gt) and _close(grads[0][1], gv)
+
+
 def test_adjoint_long_pcfs_global_path():
     rng = np.random.default_rng(4)
     counts = np.array([20, 6000, 15, 5000, 30])
