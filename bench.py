@@ -598,8 +598,14 @@ def run_grad(steps, warmup, plain_steps_per_s=None):
         api.pairwise_backward(X, kind, p, G, workspace=ws)
         k_ms = _events_ms(lambda: api.pairwise_backward(X, kind, p, G, workspace=ws,
                                                         packed=True), steps, stream)
+        # the same call with PCF_DETERMINISTIC (the two bound passes, integer
+        # sums in HBM, the conversion pass)
+        d_ms = _events_ms(lambda: api.pairwise_backward(X, kind, p, G, workspace=ws,
+                                                        packed=True, deterministic=True),
+                          steps, stream)
         ops = (one_steps + extra) * k_ops
         adj[name] = {"kernel": "pairwise_adjoint_tiles<%s>" % name, "kernel_ms": k_ms,
+                     "call_ms_deterministic": d_ms,
                      "merge_steps": one_steps + extra, "ops_per_step": k_ops,
                      "achieved": ops / (k_ms * 1e-3) / 1e12,
                      "frac": ops / (k_ms * 1e-3) / PEAK_FP64_LANE_OPS}
