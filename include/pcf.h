@@ -176,12 +176,15 @@ pcf_status pcf_pairwise_lp_noalloc(const pcf_set *X, pcf_kind kind, double p,
  * diagonal. The first time and the last value of every PCF are fixed: their
  * entries are 0. At an exact tie of two PCFs' breakpoint times the mean of
  * the one-sided time derivatives is used. Each pair's merge is recomputed;
- * nothing is stored between forward and backward. FP64 only
- * (PCF_EUNSUPPORTED for FP32). A tile sums its gradient terms in 64-bit fixed
- * point at power-of-two scales bounded from its own weights, values and
- * piece lengths (order-independent), and adds the sums to grad_t, grad_v with
- * FP64 atomics, whose order, and so the last bits, may vary between runs.
- * With PCF_DETERMINISTIC the sums in HBM are 64-bit fixed point too, at
+ * nothing is stored between forward and backward. grad_out and fwd_out are
+ * FP64 for either dtype; an FP32 set merges and forms its gradient terms in
+ * FP32. A tile sums its gradient terms in 64-bit fixed point at power-of-two
+ * scales bounded from its own weights, values and piece lengths
+ * (order-independent), and adds the sums to grad_t, grad_v with atomics of
+ * the set's dtype, whose order, and so the last bits, may vary between runs.
+ * With PCF_DETERMINISTIC (FP64 sets only: PCF_EUNSUPPORTED for FP32, whose
+ * gradient arrays cannot hold the 64-bit sums) the sums in HBM are 64-bit
+ * fixed point too, at
  * scales bounded from the whole set (largest |w_ij|, |v| and piece length,
  * found by two extra passes over grad_out, fwd_out and the records): grad_t
  * and grad_v hold the integer sums until a last pass converts them in place,

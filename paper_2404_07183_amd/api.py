@@ -426,7 +426,9 @@ def norms(X, p=2.0, a=0.0, b=math.inf, *, power=False, out=None, stream=None):
 
 def pairwise_backward(X, kind, p, grad_out, fwd_out=None, workspace=None, stream=None,
                       packed=False, deterministic=False):
-    """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, FP64).
+    """(dL/dt, dL/dv) for a loss with dL/dF = grad_out (n x n, taken in
+    FP64), in the set's dtype (FP32 or FP64; FP32 sets merge in FP32 with the
+    gradient sums in 64-bit fixed point, then FP32 atomics into the result).
     A ``workspace`` that served the previous backward call on the same set
     keeps its plan; ``packed=True`` as in ``pdist``. ``deterministic=True``
     sums the gradients in 64-bit fixed point at the set's scales: the same
@@ -685,7 +687,9 @@ class PairwiseMatrix(torch.autograd.Function):
         if ctx.bounds is not None:
             gt, gv = restrict_backward(sets[k - 1], ctx.bounds[0], ctx.bounds[1], sets[k],
                                        gt, gv)
-        return gt, gv, None, None, None, None, None, None
+        # (the range and warp maps return FP64; the inputs' dtype comes back)
+        dt = sets[0].t.dtype
+        return gt.to(dt), gv.to(dt), None, None, None, None, None, None
 
 
 def pairwise_matrix(X, t, v, kind=PCF_LP, p=1.0, bounds=None, weight=None,

@@ -963,12 +963,14 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
         return fail(PCF_EINVAL, "unknown kind");
     if (kind != PCF_GRAM && (!(p >= 1.0) || !isfinite(p)))
         return fail(PCF_EINVAL, "p must be finite and >= 1");
-    if (X->dtype != PCF_F64)
-        return fail(PCF_EUNSUPPORTED, "the adjoint is implemented for FP64 only");
+    const bool f64 = X->dtype == PCF_F64;
+    const bool fixed = (flags & PCF_DETERMINISTIC) != 0;
+    if (fixed && !f64)
+        return fail(PCF_EUNSUPPORTED, "PCF_DETERMINISTIC: the adjoint's integer sums in HBM "
+                                      "need FP64 gradient arrays");
     if (X->n == 0)
         return PCF_OK;
     const bool chain = kind == PCF_LP && p != 1.0;
-    const bool fixed = (flags & PCF_DETERMINISTIC) != 0;
     if (fixed && (X->n + 31) / 32 > 65535)
         return fail(PCF_EUNSUPPORTED, "PCF_DETERMINISTIC takes at most 2,097,120 PCFs");
     if (!grad_out || !grad_t || !grad_v || !ws)
@@ -999,9 +1001,10 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
     const int64_t P = ho ? ho[X->n] : -1;
     if (P < 0)
         return fail(PCF_EINVAL, "the adjoint needs host offsets");
-    hipError_t e = launch_zero((double *)grad_t, P, s);
+    hipError_t e = f64 ? launch_zero((double *)grad_t, P, s)
+                       : launch_zero_f32((float *)grad_t, P, s);
     if (e == hipSuccess)
-        e = launch_zero((double *)grad_v, P, s);
+        e = f64 ? launch_zero((double *)grad_v, P, s) : launch_zero_f32((float *)grad_v, P, s);
     if (e != hipSuccess)
         return hip_fail(e, "clearing the gradients");
     BwdArgs a;
@@ -1011,8 +1014,8 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
     a.ldg = ldg;
     a.fwd_out = (const double *)fwd_out;
     a.ldf = ldf;
-    a.grad_t = (double *)grad_t;
-    a.grad_v = (double *)grad_v;
+    a.grad_t = grad_t;
+    a.grad_v = grad_v;
     a.p = p;
     a.chain = chain ? 1 : 0;
     a.gram = kind == PCF_GRAM ? 1 : 0;
@@ -1025,7 +1028,7 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
         if (e != hipSuccess)
             return hip_fail(e, "adjoint bounds launch");
     }
-    e = launch_backward(hk, a, tile_grid(reuse ? nullptr : &plan, reuse), s);
+    e = launch_backward(hk, f64, a, tile_grid(reuse ? nullptr : &plan, reuse), s);
     if (e != hipSuccess)
         return hip_fail(e, "adjoint kernel launch");
     if (fixed) {

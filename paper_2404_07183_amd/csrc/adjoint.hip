@@ -151,47 +151,68 @@ __device__ __forceinline__ long long fixed_rescale(long long v, int k)
 // t_{k+1} goes to slot k + 1. In LDS mode the slots are in LDS next to the
 // records; in global mode they are the output arrays themselves, reached
 // through the PCF's row base.
-struct GradSink {
-    double *gt;  // indexed by record index
-    double *gv;
+template <typename T> struct GradSink {
+    T *gt;  // indexed by record index
+    T *gv;
     int32_t last;  // record index of the PCF's last row (fixed value)
-    int fixed;     // 1: the arrays hold fixed-point sums at scales st, sv
+    int fixed;     // 1: the arrays hold fixed-point sums at scales st, sv (FP64)
     double st, sv;
 };
 
-__device__ __forceinline__ void sink_add_t(const GradSink &s, int32_t q, double x)
+template <typename T>
+__device__ __forceinline__ void sink_add_t(const GradSink<T> &s, int32_t q, double x)
 {
-    if (s.fixed)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&s.gt[q]),
-                  (unsigned long long)fixed_of(x, s.st));
-    else
-        atomicAdd(&s.gt[q], x);
+    if constexpr (sizeof(T) == 8) {
+        if (s.fixed) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s.gt[q]),
+                      (unsigned long long)fixed_of(x, s.st));
+            return;
+        }
+    }
+    atomicAdd(&s.gt[q], (T)x);
 }
-__device__ __forceinline__ void sink_add_v(const GradSink &s, int32_t q, double x)
+template <typename T>
+__device__ __forceinline__ void sink_add_v(const GradSink<T> &s, int32_t q, double x)
 {
     if (q >= s.last)
         return;
-    if (s.fixed)
-        atomicAdd(reinterpret_cast<unsigned long long *>(&s.gv[q]),
-                  (unsigned long long)fixed_of(x, s.sv));
-    else
-        atomicAdd(&s.gv[q], x);
+    if constexpr (sizeof(T) == 8) {
+        if (s.fixed) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&s.gv[q]),
+                      (unsigned long long)fixed_of(x, s.sv));
+            return;
+        }
+    }
+    atomicAdd(&s.gv[q], (T)x);
 }
 
-// Steps [d, d + m) of pair (A, B) with weight W; records from `src` (LDS or
-// global), gradients to the two sinks. m is a multiple of kStepBlock.
-template <int HK, typename Src>
-__device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
+// The record at src[i] in FP64 (the sentinel time becomes DBL_MAX).
+template <typename T>
+__device__ __forceinline__ Rec<double> rec64(const Rec<T> *src, int64_t i)
+{
+    const Rec<T> r = src[i];
+    Rec<double> o;
+    o.t = r.t < sentinel<T>() ? (double)r.t : sentinel<double>();
+    o.v = (double)r.v;
+    return o;
+}
+
+// Steps [d, d + m) of pair (A, B) with weight W; records from global
+// memory, taken in FP64; gradients to the two sinks. m is a multiple of
+// kStepBlock.
+template <int HK, typename T>
+__device__ __forceinline__ void adjoint_pair(const Rec<T> *src, int32_t A, int32_t na,
                                              int32_t B, int32_t nb, int64_t d,
                                              int64_t m, double W, double p,
-                                             const GradSink &sa,
-                                             const GradSink &sb)
+                                             const GradSink<T> &sa,
+                                             const GradSink<T> &sb)
 {
     const double S = sentinel<double>();
     int32_t ia, ib;
-    double x;
-    pair_start<double>(src, A, na, B, nb, d, ia, ib, x);
-    Rec<double> ra = src[ia], rb = src[ib];
+    T x0;
+    pair_start<T>(src, A, na, B, nb, d, ia, ib, x0);
+    double x = x0 < sentinel<T>() ? (double)x0 : S;
+    Rec<double> ra = rec64(src, ia), rb = rec64(src, ib);
     double gva = 0.0, gvb = 0.0;  // value gradients of the current pieces
     for (int64_t q = 0; q < m; ++q) {
         const double y = ra.t <= rb.t ? ra.t : rb.t;
@@ -200,14 +221,14 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
         gvb += dhda<HK>(rb.v, ra.v, p) * w;
         if (ra.t <= rb.t) {
             // the row side's breakpoint at y
-            const Rec<double> na_ = src[ia + 1];
+            const Rec<double> na_ = rec64(src, ia + 1);
             if (y < S) {
                 double dta;
                 if (rb.t == y) {
                     // the column side breaks at y too: mean of the one-sided
                     // derivatives, for both breakpoints (the column side's
                     // own step at y, next, has width 0 and adds nothing)
-                    const double bn = src[ib + 1].v;
+                    const double bn = (double)src[ib + 1].v;
                     dta = 0.5 * (hval<double, HK>(ra.v, bn, p) - hval<double, HK>(na_.v, bn, p) +
                                  hval<double, HK>(ra.v, rb.v, p) - hval<double, HK>(na_.v, rb.v, p));
                     const double dtb =
@@ -227,7 +248,7 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
             // the column side's breakpoint at y (strictly before the row
             // side's next one); a width-0 step is the second half of a tie
             // already handled above
-            const Rec<double> nb_ = src[ib + 1];
+            const Rec<double> nb_ = rec64(src, ib + 1);
             if (y < S && y > x) {
                 const double dtb =
                     hval<double, HK>(ra.v, rb.v, p) - hval<double, HK>(ra.v, nb_.v, p);
@@ -247,18 +268,20 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
 // ---------------------------------------------------------------------------
 // The LDS adjoint chain: the forward chain's P/Q formulation and record walk
 // (h symmetric, P the piece loaded last, Q the other one, one record read
-// per step) with each piece's value-gradient accumulator.
+// per step) with each piece's value-gradient accumulator, in the set's
+// precision T; the gradient sums are fixed point (lds_add).
 //
-// Gradient slots: record q (at LDS address R0 + 16q) has two FP64 slots,
-// dL/dv of its piece at V0 + 8q and dL/dt of its end time kAdjGtOffset
-// bytes further, so the slots of a piece are found from its record address
-// alone (a halving and the add of a workgroup constant, V0 - R0/2) and the
-// chain never needs to know which PCF a piece belongs to. Each step ends one piece E:
-// its value gradient so far and the time gradient of its end time y go to
-// E's slots (two LDS atomic adds at the walk's address, immediate offsets).
-// Fixed parameters (the last value, the sentinel end time of the last
-// piece) and padding slots receive terms too; the flush at the end of the
-// tile drops them.
+// Gradient slots: record q (at LDS address R0 + Rq, R = 16 bytes for FP64
+// records, 8 for FP32) has two 64-bit slots, dL/dv of its piece at V0 + 8q
+// and dL/dt of its end time AdjLayout<T>::kGt bytes further, so the slots of
+// a piece are found from its record address alone (a shift by
+// log2(R / 8) and the add of a workgroup constant, V0 - R0 8 / R) and the
+// chain never needs to know which PCF a piece belongs to. Each step ends one
+// piece E: its value gradient so far and the time gradient of its end time y
+// go to E's slots (two LDS atomic adds at the walk's address, immediate
+// offsets). Fixed parameters (the last value, the sentinel end time of the
+// last piece) and padding slots receive terms too; the flush at the end of
+// the tile drops them.
 //
 // Time gradient at a breakpoint y where E ends and the other piece O goes
 // on: h(vE, vO) - h(vN, vO), vN the value after y. Where O breaks at y too
@@ -268,19 +291,29 @@ __device__ __forceinline__ void adjoint_pair(Src src, int32_t A, int32_t na,
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) long long lds_i64;
-typedef const __attribute__((address_space(3))) d2 *lds_d2;
 
-struct AdjChain {
-    d2 P;                  // (end time, value) of the piece loaded last
-    uint32_t gb;           // gradient slot base V0 - R0/2 (workgroup constant)
-    double tQ, vQ;         // the other piece
-    LdsWalk<double> w;     // record addresses
-    double gQ;             // value gradient of Q so far, in units of
+// The adjoint's LDS layout for records of type T.
+template <typename T> struct AdjLayout {
+    static constexpr int kRecBytes = (int)sizeof(Rec<T>);
+    static constexpr int kRecords = adj_lds_records(kRecBytes);  // records a tile
+    static constexpr uint32_t kGt = adj_gt_offset(kRecBytes);    // dL/dv -> dL/dt slot
+    static constexpr int kUnroll = adj_stage_unroll(kRecBytes);  // staging, per thread
+    static constexpr int kShift = kRecBytes == 16 ? 1 : 0;       // record -> slot address
+    static_assert(kRecBytes == 16 || kRecBytes == 8, "record size");
+};
+
+template <typename T> struct AdjChain {
+    typedef typename RecVec<T>::type V;
+    V P;                   // (end time, value) of the piece loaded last
+    uint32_t gb;           // gradient slot base (workgroup constant)
+    T tQ, vQ;              // the other piece
+    LdsWalk<T> w;          // record addresses
+    T gQ;                  // value gradient of Q so far, in units of
                            // gunit<HK> (P's is 0: loaded by the last step)
-    double x;              // start of the current cell
+    T x;                   // start of the current cell
     double Wv, Wt;         // pair weight times the unit of dh/da; pair weight
                            // (times the tile's value and time slot scales)
-    double sv, st;         // the tile's slot scales (tile_exps)
+    double sv, st;         // the tile's slot scales
     int32_t left;          // steps left in the current pair
     int32_t k, r, c, rb, rn, cb, cn;
 };
@@ -298,39 +331,38 @@ __device__ __forceinline__ double gunit(double p)
 }
 
 // h(e, o) - h(n, o)
-template <int HK>
-__device__ __forceinline__ double hdiff(double e, double n, double o, double p)
+template <typename T, int HK>
+__device__ __forceinline__ T hdiff(T e, T n, T o, T p)
 {
     if constexpr (HK == kSqr)
-        return (e - n) * ((e + n) - 2.0 * o);
+        return (e - n) * ((e + n) - T(2) * o);
     else if constexpr (HK == kProd)
         return (e - n) * o;
     else
-        return hval<double, HK>(e, o, p) - hval<double, HK>(n, o, p);
+        return hval<T, HK>(e, o, p) - hval<T, HK>(n, o, p);
 }
 
 // The step's value-gradient terms, dh/da(a, b) = gunit * dP and
 // dh/da(b, a) = gunit * dQ, and h(a, b), from the one difference d = a - b
 // (|d|^p = |d|^(p-1) |d| for general p).
-template <int HK>
-__device__ __forceinline__ void step_terms(double a, double b, double p, double &dP,
-                                           double &dQ, double &hab)
+template <typename T, int HK>
+__device__ __forceinline__ void step_terms(T a, T b, T p, T &dP, T &dQ, T &hab)
 {
     if constexpr (HK == kProd) {
         dP = b;
         dQ = a;
         hab = a * b;
     } else {
-        const double d = a - b;
+        const T d = a - b;
         if constexpr (HK == kSqr) {
             dP = d;
             hab = d * d;
         } else if constexpr (HK == kAbs) {
-            dP = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+            dP = d > T(0) ? T(1) : (d < T(0) ? T(-1) : T(0));
             hab = fabs(d);
         } else {
-            const double m = hval<double, HK>(d, 0.0, p - 1.0);  // |d|^(p-1)
-            dP = d > 0.0 ? m : (d < 0.0 ? -m : 0.0);
+            const T m = hval<T, HK>(d, T(0), p - T(1));  // |d|^(p-1)
+            dP = d > T(0) ? m : (d < T(0) ? -m : T(0));
             hab = m * fabs(d);
         }
         dQ = -dP;
@@ -338,12 +370,11 @@ __device__ __forceinline__ void step_terms(double a, double b, double p, double 
 }
 
 // The dL/dv slot of the record at LDS address a, plus Extra bytes (the
-// dL/dt slot at Extra + kAdjGtOffset), for gb = V0 - R0/2. Extra becomes a
-// constant offset of the atomic.
-template <uint32_t Extra>
+// dL/dt slot at Extra + kGt). Extra becomes a constant offset of the atomic.
+template <typename T, uint32_t Extra>
 __device__ __forceinline__ lds_f64 *grad_slot(uint32_t a, uint32_t gb)
 {
-    return (lds_f64 *)(size_t)((a >> 1) + gb + Extra);
+    return (lds_f64 *)(size_t)((a >> AdjLayout<T>::kShift) + gb + Extra);
 }
 
 // LDS slot add: w g to the nearest unit of the tile's fixed point (w carries
@@ -365,56 +396,61 @@ __device__ __forceinline__ void lds_add(lds_f64 *p, double w, double g)
 // gradient, and O's value is not used after it. A run that begins with such
 // a second half subtracts that step's own term at its start (adj_begin).
 // Width-0 steps past the sentinel only reach dropped slots.
-template <int K, int HK>
-__device__ __forceinline__ void adj_step(AdjChain &ch, double p)
+template <typename T, int K, int HK>
+__device__ __forceinline__ void adj_step(AdjChain<T> &ch, T p)
 {
-    const double S = sentinel<double>();
-    const double tP = ch.P.x, vP = ch.P.y, tQ = ch.tQ, vQ = ch.vQ;
-    const double y = min_raw(tP, tQ);
-    const double w = y - ch.x;
+    typedef typename RecVec<T>::type V;
+    typedef const __attribute__((address_space(3))) V *lds_v;
+    constexpr uint32_t kGt = AdjLayout<T>::kGt;
+    const T S = sentinel<T>();
+    const T tP = ch.P.x, vP = ch.P.y, tQ = ch.tQ, vQ = ch.vQ;
+    const T y = min_raw(tP, tQ);
+    const T w = y - ch.x;
     ch.x = y;
-    double dP, dQ, hPQ;
-    step_terms<HK>(vP, vQ, p, dP, dQ, hPQ);
-    const double gP = dP * w;  // P was loaded by the previous step
-    const double gQ = fma(dQ, w, ch.gQ);
+    T dP, dQ, hPQ;
+    step_terms<T, HK>(vP, vQ, p, dP, dQ, hPQ);
+    const T gP = dP * w;  // P was loaded by the previous step
+    const T gQ = fma(dQ, w, ch.gQ);
     const bool c = tP <= tQ;
-    const double vO = c ? vQ : vP;
-    const double gE = c ? gP : gQ, gO = c ? gQ : gP;
+    const T vO = c ? vQ : vP;
+    const T gE = c ? gP : gQ, gO = c ? gQ : gP;
     const uint32_t aQ = ch.w.S - ch.w.q;  // Q's record address at this step
-    const d2 N = ch.w.template advance<K>(c);
+    const V N = ch.w.template advance<K>(c);
     // E's record address is the walk's q plus K records
-    lds_add(grad_slot<K * 8>(ch.w.q, ch.gb), ch.Wv, gE);
-    double dE = hPQ - hval<double, HK>(N.y, vO, p);
-    double vOc = vO;
+    lds_add(grad_slot<T, K * 8>(ch.w.q, ch.gb), ch.Wv, (double)gE);
+    T dE = hPQ - hval<T, HK>(N.y, vO, p);
+    T vOc = vO;
     if (tP == tQ && y < S) {
         // both break at y (E = P, O = Q): the mean of the one-sided
         // derivatives for both
-        const double vON = ((lds_d2)(size_t)(aQ + (uint32_t)sizeof(Rec<double>)))->y;
-        dE = 0.5 * (dE + hdiff<HK>(vP, N.y, vON, p));
-        const double dO = 0.5 * (hdiff<HK>(vQ, vON, vP, p) + hdiff<HK>(vQ, vON, N.y, p));
-        lds_add(grad_slot<kAdjGtOffset>(aQ, ch.gb), ch.Wt, dO);
+        const T vON = ((lds_v)(size_t)(aQ + (uint32_t)sizeof(Rec<T>)))->y;
+        dE = T(0.5) * (dE + hdiff<T, HK>(vP, N.y, vON, p));
+        const T dO = T(0.5) * (hdiff<T, HK>(vQ, vON, vP, p) + hdiff<T, HK>(vQ, vON, N.y, p));
+        lds_add(grad_slot<T, kGt>(aQ, ch.gb), ch.Wt, (double)dO);
         vOc = vON;
     }
-    lds_add(grad_slot<K * 8 + kAdjGtOffset>(ch.w.q, ch.gb), ch.Wt, dE);
+    lds_add(grad_slot<T, K * 8 + kGt>(ch.w.q, ch.gb), ch.Wt, (double)dE);
     ch.P = N;
     ch.tQ = max_raw(tP, tQ);
     ch.vQ = vOc;
     ch.gQ = gO;
 }
 
-template <int HK, int... Ks>
-__device__ __forceinline__ void adj_block(AdjChain &ch, double p,
+template <typename T, int HK, int... Ks>
+__device__ __forceinline__ void adj_block(AdjChain<T> &ch, T p,
                                           std::integer_sequence<int, Ks...>)
 {
-    (adj_step<Ks, HK>(ch, p), ...);
+    (adj_step<T, Ks, HK>(ch, p), ...);
     ch.w.end_block();
 }
 
 // The value gradients of the two current pieces (at a block boundary, where
 // the walk's q is P's record address).
-__device__ __forceinline__ void adj_flush(const AdjChain &ch)
+template <typename T>
+__device__ __forceinline__ void adj_flush(const AdjChain<T> &ch)
 {
-    lds_add(grad_slot<0>(ch.w.S - ch.w.q, ch.gb), ch.Wv, ch.gQ);  // P's is 0 (just loaded)
+    // P's is 0 (just loaded)
+    lds_add(grad_slot<T, 0>(ch.w.S - ch.w.q, ch.gb), ch.Wv, (double)ch.gQ);
 }
 
 __device__ __forceinline__ int32_t adj_pair_steps(int32_t na, int32_t nb)
@@ -422,25 +458,27 @@ __device__ __forceinline__ int32_t adj_pair_steps(int32_t na, int32_t nb)
     return (na + nb - 2 + kStepBlock - 1) & ~(kStepBlock - 1);
 }
 
-template <int HK>
-__device__ __forceinline__ void adj_load(AdjChain &ch, const Rec<double> *lrec, int32_t iP,
-                                         int32_t iQ, double p)
+template <typename T>
+__device__ __forceinline__ void adj_load(AdjChain<T> &ch, const Rec<T> *lrec, int32_t iP,
+                                         int32_t iQ)
 {
     ch.w.set(lrec, iP, iQ);
-    ch.P = LdsWalk<double>::at(lrec, iP);
-    const d2 Q = LdsWalk<double>::at(lrec, iQ);
+    ch.P = LdsWalk<T>::at(lrec, iP);
+    const typename RecVec<T>::type Q = LdsWalk<T>::at(lrec, iQ);
     ch.tQ = Q.x;
     ch.vQ = Q.y;
-    ch.gQ = 0.0;
+    ch.gQ = T(0);
 }
 
 // Starting state at step d of pair k (merge-path split), weights from
 // sh.part.
-template <int HK>
-__device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
-                                          const Rec<double> *lrec, int32_t k,
-                                          int64_t d, int32_t C, double p)
+template <typename T, int HK>
+__device__ __forceinline__ void adj_begin(AdjChain<T> &ch, const TileShared &sh,
+                                          const Rec<T> *lrec, int32_t k, int64_t d,
+                                          int32_t C, T p)
 {
+    typedef typename RecVec<T>::type V;
+    typedef const __attribute__((address_space(3))) V *lds_v;
     const int r = div_by_c(k, sh.cmag), c = k - r * C;
     ch.k = k;
     ch.r = r;
@@ -450,33 +488,33 @@ __device__ __forceinline__ void adj_begin(AdjChain &ch, const TileShared &sh,
     ch.cb = sh.cb[c];
     ch.cn = sh.cn[c];
     int32_t i0, j0;
-    double x;
-    pair_start<double>(lrec, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
-    adj_load<HK>(ch, lrec, i0, j0, p);
+    T x;
+    pair_start<T>(lrec, ch.rb, ch.rn, ch.cb, ch.cn, d, i0, j0, x);
+    adj_load<T>(ch, lrec, i0, j0);
     ch.x = x;
     ch.Wt = sh.part[k] * ch.st;
-    ch.Wv = sh.part[k] * gunit<HK>(p) * ch.sv;
+    ch.Wv = sh.part[k] * gunit<HK>((double)p) * ch.sv;
     ch.left = adj_pair_steps(ch.rn, ch.cn) - (int32_t)d;
-    if (x > 0.0 && x < sentinel<double>() && min_raw(ch.P.x, ch.tQ) == x) {
+    if (x > T(0) && x < sentinel<T>() && min_raw(ch.P.x, ch.tQ) == x) {
         // the run starts at the width-0 second half of a tie, whose time
         // gradients the run before added in full: this step's own term
         // (as adj_step computes it) is subtracted in advance
         const bool c0 = ch.P.x <= ch.tQ;
         const uint32_t aE = c0 ? ch.w.q : ch.w.S - ch.w.q;
-        const double vO0 = c0 ? ch.vQ : ch.P.y;
-        const double vN0 = ((lds_d2)(size_t)(aE + (uint32_t)sizeof(Rec<double>)))->y;
-        double dP, dQ, hPQ;
-        step_terms<HK>(ch.P.y, ch.vQ, p, dP, dQ, hPQ);
-        const double dE = hPQ - hval<double, HK>(vN0, vO0, p);
-        lds_add(grad_slot<kAdjGtOffset>(aE, ch.gb), -ch.Wt, dE);
+        const T vO0 = c0 ? ch.vQ : ch.P.y;
+        const T vN0 = ((lds_v)(size_t)(aE + (uint32_t)sizeof(Rec<T>)))->y;
+        T dP, dQ, hPQ;
+        step_terms<T, HK>(ch.P.y, ch.vQ, p, dP, dQ, hPQ);
+        const T dE = hPQ - hval<T, HK>(vN0, vO0, p);
+        lds_add(grad_slot<T, AdjLayout<T>::kGt>(aE, ch.gb), -ch.Wt, (double)dE);
     }
 }
 
 // Next pair with steps (row-major pair order, as the forward chain).
-template <int HK>
-__device__ __forceinline__ void adj_next_pair(AdjChain &ch, const TileShared &sh,
-                                              const Rec<double> *lrec, int32_t C,
-                                              bool diag, int gram, double p)
+template <typename T, int HK>
+__device__ __forceinline__ void adj_next_pair(AdjChain<T> &ch, const TileShared &sh,
+                                              const Rec<T> *lrec, int32_t C, bool diag,
+                                              int gram, T p)
 {
     int32_t k = ch.k, r = ch.r, c = ch.c, rb = ch.rb, rn = ch.rn, cb = ch.cb, cn = ch.cn;
     do {
@@ -502,58 +540,60 @@ __device__ __forceinline__ void adj_next_pair(AdjChain &ch, const TileShared &sh
     ch.rn = rn;
     ch.cb = cb;
     ch.cn = cn;
-    adj_load<HK>(ch, lrec, rb, cb, p);
-    ch.x = 0.0;
+    adj_load<T>(ch, lrec, rb, cb);
+    ch.x = T(0);
     ch.Wt = sh.part[k] * ch.st;
-    ch.Wv = sh.part[k] * gunit<HK>(p) * ch.sv;
+    ch.Wv = sh.part[k] * gunit<HK>((double)p) * ch.sv;
     ch.left = adj_pair_steps(rn, cn);
 }
 
-template <int HK>
-__device__ __forceinline__ void adj_lane_chain(const TileShared &sh,
-                                               const Rec<double> *lrec, uint32_t gb,
-                                               double sv, double st, int64_t s, int64_t e,
-                                               int32_t k,
-                                               int32_t C, bool diag, int gram, double p)
+template <typename T, int HK>
+__device__ __forceinline__ void adj_lane_chain(const TileShared &sh, const Rec<T> *lrec,
+                                               uint32_t gb, double sv, double st, int64_t s,
+                                               int64_t e, int32_t k, int32_t C, bool diag,
+                                               int gram, T p)
 {
-    AdjChain ch;
+    AdjChain<T> ch;
     ch.gb = gb;
     ch.sv = sv;
     ch.st = st;
     // (an LDS tile: its step prefix is the 32-bit one)
-    adj_begin<HK>(ch, sh, lrec, k, s - sh.pw[k], C, p);
+    adj_begin<T, HK>(ch, sh, lrec, k, s - sh.pw[k], C, p);
     for (int32_t blk = (int32_t)((e - s) / kStepBlock); blk > 0; --blk) {
         if (ch.left == 0) {
             adj_flush(ch);
-            adj_next_pair<HK>(ch, sh, lrec, C, diag, gram, p);
+            adj_next_pair<T, HK>(ch, sh, lrec, C, diag, gram, p);
         }
-        adj_block<HK>(ch, p, std::make_integer_sequence<int, kStepBlock>{});
+        adj_block<T, HK>(ch, p, std::make_integer_sequence<int, kStepBlock>{});
         ch.left -= kStepBlock;
     }
     // the piece going on past this run: its gradient so far
     adj_flush(ch);
 }
 
-template <int HK>
+template <typename T, int HK>
 __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
 {
+    typedef AdjLayout<T> L;
     // tile state in static LDS, records (and the adjoint's accumulators)
     // in the dynamic part: distinct objects, so the compiler knows that the
     // direct record loads into the latter never touch the former
     __shared__ TileShared sh;
     extern __shared__ __align__(16) unsigned char smem[];
     const WsHeader &h = hdr_of(args.ws);
-    Rec<double> *lrec = reinterpret_cast<Rec<double> *>(smem);
+    Rec<T> *lrec = reinterpret_cast<Rec<T> *>(smem);
     int64_t *pw64 = reinterpret_cast<int64_t *>(lrec);  // wide step prefix
     // gradient slots follow the records: dL/dv of record q at lg[q], dL/dt
-    // of its end time at lg[kAdjLdsRecords + q] (kAdjLdsRecords records a
-    // tile), as 64-bit fixed-point sums at the tile's scales (lds_add)
-    double *lg = reinterpret_cast<double *>(lrec + kAdjLdsRecords);
-    const uint32_t gb = lds_address(lg) - (lds_address(lrec) >> 1);
-    const Rec<double> *grec = reinterpret_cast<const Rec<double> *>(args.ws + h.off_rec);
+    // of its end time at lg[L::kRecords + q] (L::kRecords records a tile),
+    // as 64-bit fixed-point sums at the tile's scales (lds_add)
+    double *lg = reinterpret_cast<double *>(lrec + L::kRecords);
+    const uint32_t gb = lds_address(lg) - (lds_address(lrec) >> L::kShift);
+    const Rec<T> *grec = reinterpret_cast<const Rec<T> *>(args.ws + h.off_rec);
     const int64_t *offsets = args.offsets;
     const int tid = threadIdx.x;
     const double p = args.p;
+    T *const grad_t = reinterpret_cast<T *>(args.grad_t);
+    T *const grad_v = reinterpret_cast<T *>(args.grad_v);
     // deterministic mode: the set's scales of the sums in HBM
     int gev = 0, get = 0;
     if (args.fixed)
@@ -562,12 +602,13 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
 
     PhaseClock pc;  // (cycle counters only in timing builds)
     TileLoop loop;
-    loop.start<double, true>(sh, args.ws, offsets, lrec, grec);
+    // (direct staging moves 16-byte records)
+    loop.start<T, sizeof(Rec<T>) == 16>(sh, args.ws, offsets, lrec, grec);
     pc.mark(-1);
     while (loop.live(sh, args.ws)) {
         const TileDesc &D = sh.desc[loop.cur];
         const bool gmode = D.global_mode != 0;
-        tile_scan<double, kWeightsAdjoint>(sh, D, args.gram, gmode ? grec : lrec, pw64, pc);
+        tile_scan<T, kWeightsAdjoint>(sh, D, args.gram, gmode ? grec : lrec, pw64, pc);
         const int32_t R = D.R, C = D.C, npairs = sh.npairs;
         const bool diag = D.diag != 0;
         const int64_t total = pw_at(sh, pw64, npairs);
@@ -577,7 +618,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         if (!gmode)
             for (int64_t q = tid; q < nslots; q += kThreads) {
                 lg[q] = 0.0;
-                lg[kAdjLdsRecords + q] = 0.0;
+                lg[L::kRecords + q] = 0.0;
             }
         // pair weights: W = (G_ij + G_ji) * chain for i != j, G_ii on the
         // diagonal; stored in the partial-sum slots (unused here)
@@ -599,17 +640,17 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             mw = fabs(W);
         }
         if (!gmode) {
-            const double S = sentinel<double>();
+            const T S = sentinel<T>();
             for (int64_t q = tid; q < nslots; q += kThreads) {
-                const Rec<double> rq = lrec[q];
-                mv = fmax(mv, fabs(rq.v));
+                const Rec<T> rq = lrec[q];
+                mv = fmax(mv, fabs((double)rq.v));
                 // a piece starts at the previous record's end time, or at 0
                 // where that record is a sentinel (a PCF's first piece: the
                 // record before it ends the previous PCF, or pads, or q
                 // starts a block)
-                const double t0 = (q == 0 || q == D.rrecs) ? 0.0 : lrec[q - 1].t;
+                const T t0 = (q == 0 || q == D.rrecs) ? T(0) : lrec[q - 1].t;
                 if (rq.t < S)
-                    ml = fmax(ml, rq.t - (t0 < S ? t0 : 0.0));
+                    ml = fmax(ml, (double)rq.t - (t0 < S ? (double)t0 : 0.0));
             }
             // the tile's maxima through the wave's lanes, then one slot per
             // wave (the tail-rule values of the scan, unused by the adjoint)
@@ -654,8 +695,8 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         int64_t s, e;
         lane_steps(sh, tid, total, s, e);
         if (s < e && !gmode) {
-            adj_lane_chain<HK>(sh, lrec, gb, sv, st, s, e, sh.pairof[tid], C, diag, args.gram,
-                               p);
+            adj_lane_chain<T, HK>(sh, lrec, gb, sv, st, s, e, sh.pairof[tid], C, diag,
+                                  args.gram, (T)p);
         } else if (s < e) {
             int32_t k = sh.pairof[tid];
             int64_t d = s - pw_at(sh, pw64, k);
@@ -666,17 +707,17 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 const int32_t A = sh.rb[r], B = sh.cb[c];
                 // global record index -> CSR row: row = record - i * kPad
                 const int64_t i = D.r_lo + r, j = D.c_lo + c;
-                GradSink sa, sb;
+                GradSink<T> sa, sb;
                 sa.last = A + sh.rn[r] - 1;
                 sb.last = B + sh.cn[c] - 1;
-                sa.gt = args.grad_t - i * kPad;
-                sa.gv = args.grad_v - i * kPad;
-                sb.gt = args.grad_t - j * kPad;
-                sb.gv = args.grad_v - j * kPad;
+                sa.gt = grad_t - i * kPad;
+                sa.gv = grad_v - i * kPad;
+                sb.gt = grad_t - j * kPad;
+                sb.gv = grad_v - j * kPad;
                 sa.fixed = sb.fixed = args.fixed;
                 sa.st = sb.st = gst;
                 sa.sv = sb.sv = gsv;
-                adjoint_pair<HK>(grec, A, sh.rn[r], B, sh.cn[c], d, m, sh.part[k], p, sa, sb);
+                adjoint_pair<HK, T>(grec, A, sh.rn[r], B, sh.cn[c], d, m, sh.part[k], p, sa, sb);
                 s += m;
                 d = 0;
                 ++k;
@@ -689,10 +730,9 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         // work is done (into registers: the records are stored to LDS after
         // the accumulator flush, which reads the current block metadata)
         const bool has_next = loop.has_next(sh, args.ws);
-        StageRegs<double, false, kAdjStageUnroll> next;
+        StageRegs<T, false, L::kUnroll> next;
         if (has_next)
-            stage_load<double, false, kAdjStageUnroll>(next, sh.desc[loop.nxt()], grec,
-                                                      offsets, lrec);
+            stage_load<T, false, L::kUnroll>(next, sh.desc[loop.nxt()], grec, offsets, lrec);
         sync_lds();
         pc.mark(kPhaseMergeWait);
         loop.decode_next(sh, args.ws, offsets);
@@ -703,11 +743,11 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         // staging's wait for its loads does not also wait for these atomics);
         // t_0 and the last value of each PCF stay untouched (fixed). A slot
         // q holds record q's value gradient and its end time's gradient.
-        static_assert(kAdjStageUnroll * kThreads >= kAdjLdsRecords, "slots per thread");
-        double fv[kAdjStageUnroll], ft[kAdjStageUnroll];
-        int64_t frow[kAdjStageUnroll];
+        static_assert(L::kUnroll * kThreads >= L::kRecords, "slots per thread");
+        double fv[L::kUnroll], ft[L::kUnroll];
+        int64_t frow[L::kUnroll];
 #pragma unroll
-        for (int u = 0; u < kAdjStageUnroll; ++u) {
+        for (int u = 0; u < L::kUnroll; ++u) {
             const int64_t q = tid + u * kThreads;
             frow[u] = -1;
             fv[u] = ft[u] = 0.0;
@@ -740,35 +780,39 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             if (args.fixed) {
                 // the sums in the set's units (bit patterns in fv, ft)
                 fv[u] = __longlong_as_double(fixed_rescale(li[q], ev - gev));
-                ft[u] = __longlong_as_double(fixed_rescale(li[kAdjLdsRecords + q], et - get));
+                ft[u] = __longlong_as_double(fixed_rescale(li[L::kRecords + q], et - get));
             } else {
                 fv[u] = (double)li[q] * isv;
-                ft[u] = (double)li[kAdjLdsRecords + q] * ist;
+                ft[u] = (double)li[L::kRecords + q] * ist;
             }
         }
         pc.mark(kPhaseFinish);
         if (has_next) {
             sync_lds();  // (the slot reads above use the block metadata)
-            stage_store<double, false, kAdjStageUnroll>(sh, next, sh.desc[loop.nxt()], lrec);
+            stage_store<T, false, L::kUnroll>(sh, next, sh.desc[loop.nxt()], lrec);
         }
 #pragma unroll
-        for (int u = 0; u < kAdjStageUnroll; ++u) {
+        for (int u = 0; u < L::kUnroll; ++u) {
             if (frow[u] < 0)
                 continue;
-            if (args.fixed) {
-                const unsigned long long bv = (unsigned long long)__double_as_longlong(fv[u]);
-                const unsigned long long bt = (unsigned long long)__double_as_longlong(ft[u]);
-                if (bv != 0)
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&args.grad_v[frow[u]]), bv);
-                if (bt != 0)
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&args.grad_t[frow[u] + 1]),
-                              bt);
-                continue;
+            if constexpr (sizeof(T) == 8) {
+                if (args.fixed) {
+                    const unsigned long long bv =
+                        (unsigned long long)__double_as_longlong(fv[u]);
+                    const unsigned long long bt =
+                        (unsigned long long)__double_as_longlong(ft[u]);
+                    if (bv != 0)
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&grad_v[frow[u]]), bv);
+                    if (bt != 0)
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&grad_t[frow[u] + 1]),
+                                  bt);
+                    continue;
+                }
             }
             if (fv[u] != 0.0)
-                atomicAdd(&args.grad_v[frow[u]], fv[u]);
+                atomicAdd(&grad_v[frow[u]], (T)fv[u]);
             if (ft[u] != 0.0)
-                atomicAdd(&args.grad_t[frow[u] + 1], ft[u]);  // the piece's end time
+                atomicAdd(&grad_t[frow[u] + 1], (T)ft[u]);  // the piece's end time
         }
         pc.mark(kPhaseStageStore);
         loop.advance();
@@ -795,24 +839,27 @@ extern "C" int pcf_debug_phase_adjoint(unsigned long long *host, int reset)
 }
 #endif
 
-// Zero a double array (a kernel, so that captured graphs replay it).
-__global__ void zero_doubles(double *p, int64_t n)
+// Zero an array (a kernel, so that captured graphs replay it).
+template <typename U> __global__ void zero_array(U *p, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+        p[i] = U(0);
 }
 
-hipError_t launch_zero(double *p, int64_t n, hipStream_t s)
+template <typename U> static hipError_t launch_zero_t(U *p, int64_t n, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096)
         blocks = 4096;
-    hipLaunchKernelGGL(zero_doubles, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(zero_array<U>, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s) { return launch_zero_t(p, n, s); }
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s) { return launch_zero_t(p, n, s); }
 
 // ---------------------------------------------------------------------------
 // Deterministic adjoint: the set's bounds, then the conversion of its sums.
@@ -926,10 +973,12 @@ __global__ __launch_bounds__(256) void adj_finish(BwdArgs a, int64_t P)
     const double iv = ldexp(1.0, -ev), it = ldexp(1.0, -et);
     long long *gt = reinterpret_cast<long long *>(a.grad_t);
     long long *gv = reinterpret_cast<long long *>(a.grad_v);
+    double *ot = reinterpret_cast<double *>(a.grad_t);
+    double *ov = reinterpret_cast<double *>(a.grad_v);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < P;
          k += (int64_t)gridDim.x * blockDim.x) {
-        a.grad_t[k] = (double)gt[k] * it;
-        a.grad_v[k] = (double)gv[k] * iv;
+        ot[k] = (double)gt[k] * it;
+        ov[k] = (double)gv[k] * iv;
     }
 }
 
@@ -950,27 +999,32 @@ hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int HK>
+template <typename T, int HK>
 static hipError_t launch_bwd_t(const BwdArgs &a, int grid, hipStream_t s)
 {
-    const size_t shm = tile_shared_bytes(16, true);
+    const size_t shm = tile_shared_bytes((int)sizeof(Rec<T>), true);
     const hipError_t e = ensure_dynamic_lds(
-        reinterpret_cast<const void *>(&pairwise_adjoint_tiles<HK>), (int)shm);
+        reinterpret_cast<const void *>(&pairwise_adjoint_tiles<T, HK>), (int)shm);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL((pairwise_adjoint_tiles<HK>), dim3(grid), dim3(kThreads),
-                       shm, s, a);
+    hipLaunchKernelGGL((pairwise_adjoint_tiles<T, HK>), dim3(grid), dim3(kThreads), shm, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_backward(int hk, const BwdArgs &a, int grid, hipStream_t s)
+template <typename T>
+static hipError_t launch_bwd_k(int hk, const BwdArgs &a, int grid, hipStream_t s)
 {
     switch (hk) {
-    case kAbs: return launch_bwd_t<kAbs>(a, grid, s);
-    case kSqr: return launch_bwd_t<kSqr>(a, grid, s);
-    case kProd: return launch_bwd_t<kProd>(a, grid, s);
-    default: return launch_bwd_t<kPow>(a, grid, s);
+    case kAbs: return launch_bwd_t<T, kAbs>(a, grid, s);
+    case kSqr: return launch_bwd_t<T, kSqr>(a, grid, s);
+    case kProd: return launch_bwd_t<T, kProd>(a, grid, s);
+    default: return launch_bwd_t<T, kPow>(a, grid, s);
     }
+}
+
+hipError_t launch_backward(int hk, bool f64, const BwdArgs &a, int grid, hipStream_t s)
+{
+    return f64 ? launch_bwd_k<double>(hk, a, grid, s) : launch_bwd_k<float>(hk, a, grid, s);
 }
 
 }  // namespace pcf

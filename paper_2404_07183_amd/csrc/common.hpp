@@ -27,16 +27,29 @@ constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
 #define PCF_LDSREC (136 * 1024)
 #endif
 constexpr int kLdsRecordBytes = PCF_LDSREC;
-// The adjoint (FP64 records) keeps two FP64 gradient slots per record in two
-// arrays after its records, dL/dv then dL/dt (8-byte strides, so that random
-// slots spread over the LDS banks): kAdjLdsRecords records a tile, and
-// kAdjGtOffset bytes from a record's dL/dv slot to its dL/dt slot (a
-// constant offset of the LDS atomics, which holds 16 bits).
-constexpr int kAdjLdsRecords = kLdsRecordBytes / 32;
-constexpr uint32_t kAdjGtOffset = (uint32_t)kAdjLdsRecords * 8;
-static_assert(kAdjGtOffset + 8 * 8 <= 65535, "adjoint LDS layout");
+// The adjoint keeps two 64-bit gradient slots per record in two arrays after
+// its records, dL/dv then dL/dt (8-byte strides, so that random slots spread
+// over the LDS banks): adj_lds_records(rec_bytes) records a tile (a multiple
+// of 64), and adj_gt_offset(rec_bytes) bytes from a record's dL/dv slot to
+// its dL/dt slot (a constant offset of the LDS atomics, which holds 16 bits).
+constexpr int adj_lds_records(int rec_bytes)
+{
+    return kLdsRecordBytes / (rec_bytes + 16) / 64 * 64;
+}
+constexpr uint32_t adj_gt_offset(int rec_bytes)
+{
+    return (uint32_t)adj_lds_records(rec_bytes) * 8;
+}
 // Records per thread when the adjoint stages a tile through registers.
-constexpr int kAdjStageUnroll = (kAdjLdsRecords + kThreads - 1) / kThreads;
+constexpr int adj_stage_unroll(int rec_bytes)
+{
+    return (adj_lds_records(rec_bytes) + kThreads - 1) / kThreads;
+}
+static_assert(adj_gt_offset(16) + 8 * 8 <= 65535 && adj_gt_offset(8) + 8 * 8 <= 65535,
+              "adjoint LDS layout");
+static_assert(adj_lds_records(16) * (16 + 16) <= kLdsRecordBytes &&
+                  adj_lds_records(8) * (8 + 16) <= kLdsRecordBytes,
+              "adjoint LDS capacity");
 
 // Rows a PCF may have (exclusive): keeps a pair's merge steps below 2^31.
 constexpr int64_t kMaxRows = (int64_t)1 << 30;

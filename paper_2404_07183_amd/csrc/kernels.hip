@@ -452,10 +452,10 @@ __global__ __launch_bounds__(kThreads) void pairwise_tiles(FwdArgs args)
 size_t tile_shared_bytes(int rec_bytes, bool backward)
 {
     // the forward kernel keeps its tile state at the start of the dynamic
-    // LDS, the adjoint in static LDS (with two FP64 gradient slots per
+    // LDS, the adjoint in static LDS (with two 64-bit gradient slots per
     // record after its records)
     if (backward)
-        return (size_t)kAdjLdsRecords * (16 + 16);
+        return (size_t)adj_lds_records(rec_bytes) * (rec_bytes + 16);
     return (size_t)kSharedHead + (size_t)(kLdsRecordBytes / rec_bytes) * rec_bytes;
 }
 

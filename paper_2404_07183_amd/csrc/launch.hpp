@@ -36,8 +36,8 @@ struct BwdArgs {
     int64_t ldg;
     const double *fwd_out;   // forward result (for the root's chain factor)
     int64_t ldf;
-    double *grad_t;          // dL/dt, CSR layout (accumulated)
-    double *grad_v;          // dL/dv, CSR layout (accumulated)
+    void *grad_t;            // dL/dt, CSR layout, the set's dtype (accumulated)
+    void *grad_v;            // dL/dv, CSR layout, the set's dtype (accumulated)
     double p;
     int chain;               // 1: scale by dF/dI = (1/p) I^(1/p - 1)
     int gram;                // 1: diagonal pairs carry work (Gram)
@@ -97,13 +97,14 @@ hipError_t launch_apply_root(bool f64, void *out, int64_t rows, int64_t cols, in
 hipError_t launch_reset(unsigned char *ws, hipStream_t s);
 hipError_t launch_forward(bool f64, int hk, const FwdArgs &a, int grid,
                           hipStream_t s);
-hipError_t launch_backward(int hk, const BwdArgs &a, int grid, hipStream_t s);
+hipError_t launch_backward(int hk, bool f64, const BwdArgs &a, int grid, hipStream_t s);
 // Deterministic adjoint: the set's largest pair weight, |v| and piece length
 // into the workspace header (before launch_backward with a.fixed), and the
 // fixed-point sums converted to FP64 in place (after it).
 hipError_t launch_adj_bounds(const BwdArgs &a, hipStream_t s);
 hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
 // Raises a kernel's dynamic-LDS limit to `bytes` once per device (thread
 // safe: concurrent first calls from several host threads all wait for it).
 hipError_t ensure_dynamic_lds(const void *kernel, int bytes);

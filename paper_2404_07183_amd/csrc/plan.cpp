@@ -8,10 +8,10 @@ namespace pcf {
 
 int64_t lds_record_capacity(int rec_bytes, bool backward)
 {
-    // the adjoint (FP64) keeps two FP64 gradient accumulators per record
-    // slot, at a fixed distance from the records
+    // the adjoint keeps two 64-bit gradient accumulators per record slot,
+    // at a fixed distance from the records
     if (backward)
-        return kAdjLdsRecords;
+        return adj_lds_records(rec_bytes);
     return kLdsRecordBytes / rec_bytes;
 }
 

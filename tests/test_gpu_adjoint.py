@@ -180,6 +180,131 @@ def test_deterministic_through_autograd():
     assert _close(grads[0][0], gt) and _close(grads[0][1], gv)
 
 
+def _f32(o, t, v):
+    """The set rounded to FP32 (a time that rounds onto its predecessor moves
+    up to the next float, so that times still strictly increase, as the data
+    contract asks), and the same values in FP64 for the oracle."""
+    t32, v32 = t.astype(np.float32), v.astype(np.float32)
+    for i in range(len(o) - 1):
+        for k in range(o[i] + 1, o[i + 1]):
+            if t32[k] <= t32[k - 1]:
+                t32[k] = np.nextafter(t32[k - 1], np.float32(np.inf))
+    return t32, v32, t32.astype(np.float64), v32.astype(np.float64)
+
+
+@pytest.mark.parametrize("seed,N,nmin,nmax", [(2, 40, 2, 60), (3, 120, 1, 90)])
+def test_adjoint_fp32_matches_oracle(seed, N, nmin, nmax):
+    # FP32 sets: the merge and the gradient terms in FP32, the tile sums in
+    # fixed point, FP32 atomics into the result; the oracle takes the same
+    # FP32-rounded inputs in FP64. Bar: 1e-5 of the largest |gradient|.
+    o, t, v = _set(seed, N, nmin, nmax)
+    t32, v32, t64, v64 = _f32(o, t, v)
+    rng = np.random.default_rng(seed + 300)
+    G = rng.uniform(-1, 1, size=(N, N))
+    X = api.PcfSet(o, t32, v32, device=DEV)
+    for name, kind, p, okind in CASES:
+        fwd = api.pdist(X, p).to(torch.float64) if (kind == api.PCF_LP and p != 1.0) else None
+        gt, gv = api.pairwise_backward(X, kind, p, torch.as_tensor(G, device=DEV), fwd)
+        assert gt.dtype == torch.float32 and gv.dtype == torch.float32
+        gt, gv = gt.cpu().numpy().astype(np.float64), gv.cpu().numpy().astype(np.float64)
+        # (the GPU's chain factor takes the FP32 forward values, the
+        # oracle's its own FP64 ones: a relative difference near 1e-7)
+        rt, rv = oracle.backward(okind, p, o, t64, v64, G)
+        assert _close(gt, rt, 1e-5), (name, np.max(np.abs(gt - rt)), np.max(np.abs(rt)))
+        assert _close(gv, rv, 1e-5), (name, np.max(np.abs(gv - rv)), np.max(np.abs(rv)))
+        assert np.all(gt[o[:-1]] == 0) and np.all(gv[o[1:] - 1] == 0)
+
+
+def test_adjoint_fp32_global_path_and_autograd():
+    # FP32 long PCFs (records read from HBM, terms taken in FP64, FP32
+    # atomics), and the autograd function on FP32 tensors
+    rng = np.random.default_rng(14)
+    counts = np.array([20, 6000, 15, 5000, 30])
+    o = np.concatenate([[0], np.cumsum(counts)])
+    t = np.empty(o[-1])
+    v = rng.standard_normal(o[-1])
+    for i in range(len(counts)):
+        a, b = o[i], o[i + 1]
+        t[a:b] = np.concatenate([[0.0], np.cumsum(rng.exponential(0.01, b - a - 1))])
+        v[b - 1] = 0.0
+    t32, v32, t64, v64 = _f32(o, t, v)
+    G = rng.uniform(0, 1, size=(5, 5))
+    X = api.PcfSet(o, t32, v32, device=DEV)
+    for name, kind, p, okind in (CASES[0], CASES[2], CASES[3]):
+        gt, gv = api.pairwise_backward(X, kind, p, torch.as_tensor(G, device=DEV))
+        rt, rv = oracle.backward(okind, p, o, t64, v64, G)
+        assert _close(gt.cpu().numpy().astype(np.float64), rt, 1e-5), name
+        assert _close(gv.cpu().numpy().astype(np.float64), rv, 1e-5), name
+    o2, t2, v2 = _set(21, 30, 2, 40)
+    t32, v32, t64, v64 = _f32(o2, t2, v2)
+    X2 = api.PcfSet(o2, t32, v32, device=DEV)
+    W = np.random.default_rng(22).uniform(0, 1, size=(30, 30))
+    W = np.triu(W) + np.triu(W, 1).T
+    tt = torch.as_tensor(t32, device=DEV).clone().requires_grad_(True)
+    vv = torch.as_tensor(v32, device=DEV).clone().requires_grad_(True)
+    M = api.pairwise_matrix(X2, tt, vv, api.PCF_LP_POW, 2.0)
+    (torch.as_tensor(W, device=DEV, dtype=torch.float32) * M).sum().backward()
+    assert tt.grad.dtype == torch.float32 and vv.grad.dtype == torch.float32
+    rt, rv = oracle.backward(oracle.LP_POW, 2.0, o2, t64, v64, W)
+    assert _close(tt.grad.cpu().numpy().astype(np.float64), rt, 1e-5)
+    assert _close(vv.grad.cpu().numpy().astype(np.float64), rv, 1e-5)
+
+
+def test_grad_config_fp32_full_size():
+    # the N = 4,096 configuration in FP32: Euler's identities and exact
+    # per-PCF gradients of two PCFs from the oracle, at the FP32 bar
+    o, t, v, W, U = workloads.config_grad()
+    t32, v32, t64, v64 = _f32(o, t, v)
+    X = api.PcfSet(o, t32, v32, device=DEV)
+    Wt, Ut = torch.as_tensor(W, device=DEV), torch.as_tensor(U, device=DEV)
+    gt1, gv1 = api.pairwise_backward(X, api.PCF_LP_POW, 2.0, Wt)
+    gt2, gv2 = api.pairwise_backward(X, api.PCF_GRAM, 0.0, Ut)
+    gt = (gt1.double() + gt2.double()).cpu().numpy()
+    gv = (gv1.double() + gv2.double()).cpu().numpy()
+    M1 = api.pdist(X, 2.0, power=True).double()
+    M2 = api.gram(X).double()
+    Lv = float(((Wt * M1).sum() + (Ut * M2).sum()).item())
+    assert abs(float(np.dot(t64, gt)) - Lv) <= 2e-5 * abs(Lv)
+    assert abs(float(np.dot(v64, gv)) - 2 * Lv) <= 2e-5 * abs(Lv)
+    for i in (7, 3001):
+        mask = np.zeros_like(W)
+        mask[i, :] = 1
+        mask[:, i] = 1
+        rt1, rv1 = oracle.backward(oracle.LP_POW, 2.0, o, t64, v64, W * mask)
+        rt2, rv2 = oracle.backward(oracle.GRAM, 0.0, o, t64, v64, U * mask)
+        a, b = o[i], o[i + 1]
+        assert _close(gt[a:b], (rt1 + rt2)[a:b], 1e-5)
+        assert _close(gv[a:b], (rv1 + rv2)[a:b], 1e-5)
+
+
+def test_adjoint_global_path_ties():
+    # long PCFs (tiles whose records stay in HBM) whose breakpoints share
+    # many times on a dyadic grid: the mean one-sided derivatives there, in
+    # FP64, FP64 with PCF_DETERMINISTIC, and FP32 (dyadic data are exact)
+    rng = np.random.default_rng(31)
+    pcfs = []
+    for n in (3000, 12, 2500, 9):
+        ticks = np.sort(rng.choice(np.arange(1, 8000), size=n - 1, replace=False)) / 8.0
+        vv = rng.integers(-8, 9, size=n) / 4.0
+        vv[-1] = 0.0
+        pcfs.append((np.concatenate([[0.0], ticks]), vv))
+    o = np.concatenate([[0], np.cumsum([len(a) for a, _ in pcfs])])
+    t = np.concatenate([a for a, _ in pcfs])
+    v = np.concatenate([b for _, b in pcfs])
+    G = rng.integers(-3, 4, size=(4, 4)).astype(float)
+    for name, kind, p, okind in CASES[:4]:
+        rt, rv = oracle.backward(okind, p, o, t, v, G)
+        gt, gv = _gpu_grad(o, t, v, kind, p, G)
+        assert _close(gt, rt, 1e-10) and _close(gv, rv, 1e-10), name
+        gt, gv = _gpu_grad_det(o, t, v, kind, p, G)
+        assert _close(gt, rt, 1e-10) and _close(gv, rv, 1e-10), name
+        X = api.PcfSet(o, t.astype(np.float32), v.astype(np.float32), device=DEV)
+        fwd = api.pdist(X, p).to(torch.float64) if (kind == api.PCF_LP and p != 1.0) else None
+        gt, gv = api.pairwise_backward(X, kind, p, torch.as_tensor(G, device=DEV), fwd)
+        assert _close(gt.cpu().numpy().astype(np.float64), rt, 1e-5), name
+        assert _close(gv.cpu().numpy().astype(np.float64), rv, 1e-5), name
+
+
 def test_adjoint_long_pcfs_global_path():
     rng = np.random.default_rng(4)
     counts = np.array([20, 6000, 15, 5000, 30])
