@@ -609,6 +609,20 @@ def run_grad(steps, warmup, plain_steps_per_s=None):
                      "merge_steps": one_steps + extra, "ops_per_step": k_ops,
                      "achieved": ops / (k_ms * 1e-3) / 1e12,
                      "frac": ops / (k_ms * 1e-3) / PEAK_FP64_LANE_OPS}
+    # the same adjoint calls on the set rounded to FP32 (merge and terms in
+    # FP32, fixed-point tile sums, FP32 atomics)
+    t32 = t.astype(np.float32)
+    for i in range(N):  # (times kept strictly increasing after rounding)
+        for k in range(o[i] + 1, o[i + 1]):
+            if t32[k] <= t32[k - 1]:
+                t32[k] = np.nextafter(t32[k - 1], np.float32(np.inf))
+    X32 = api.PcfSet(o, t32, v.astype(np.float32), device="cuda:0")
+    for name, kind, p, G in (("l2sq", api.PCF_LP_POW, 2.0, Wt), ("gram", api.PCF_GRAM, 0.0, Ut)):
+        ws = api.Workspace(device="cuda:0")
+        api.pairwise_backward(X32, kind, p, G, workspace=ws)
+        adj[name]["call_ms_fp32"] = _events_ms(
+            lambda: api.pairwise_backward(X32, kind, p, G, workspace=ws, packed=True), steps,
+            stream)
     tot_ops = sum(a["merge_steps"] * a["ops_per_step"] for a in adj.values())
     tot_ms = sum(a["kernel_ms"] for a in adj.values())
     res["roofline"] = {"bound": "alu", "achieved": tot_ops / (tot_ms * 1e-3) / 1e12,
