@@ -460,3 +460,61 @@ def test_gradients_through_range_and_weight(bounds, weight):
             for k in range(o[i], o[i + 1]):
                 if t[k] >= b or (k + 1 < o[i + 1] and t[k + 1] <= a):
                     assert gt[k] == 0.0 and gv[k] == 0.0, k
+
+
+@pytest.mark.parametrize("bounds,weight", [((0.7, 3.1), None), (None, ("exp", 0.3)),
+                                           ((0.5, np.inf), ("pow", -0.4))])
+def test_fp32_gradients_through_range_and_weight(bounds, weight):
+    # the same loss on an FP32 set: FP32 gradients (restriction, warp and
+    # adjoint in FP32, the maps back in FP64, returned in FP32) against
+    # central differences of the oracle's loss at the FP32-rounded inputs
+    o, t, v = _set(15, 10, 2, 14)
+    t32, v32, t64, v64 = _f32(o, t, v)
+    N = len(o) - 1
+    rng = np.random.default_rng(16)
+    W = rng.uniform(0, 1, size=(N, N))
+    W = np.triu(W) + np.triu(W, 1).T
+    a, b = bounds if bounds is not None else (0.0, np.inf)
+    wk, c = weight if weight is not None else (None, 0.0)
+    I, J = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+
+    def oracle_loss(tt, vv):
+        if weight is None:
+            m1 = oracle.entries_ab(oracle.LP_POW, 2.0, a, b, o, tt, vv, I, J)
+        else:
+            code = oracle.W_EXP if wk == "exp" else oracle.W_POW
+            m1 = oracle.entries_w(oracle.LP_POW, 2.0, code, c, o, tt, vv, I, J, a, b)
+        return float((W.ravel() * m1).sum())
+
+    X = api.PcfSet(o, t32, v32, device=DEV)
+    tt = torch.as_tensor(t32, device=DEV).clone().requires_grad_(True)
+    vv = torch.as_tensor(v32, device=DEV).clone().requires_grad_(True)
+    M1 = api.pairwise_matrix(X, tt, vv, api.PCF_LP_POW, 2.0, bounds=bounds, weight=weight)
+    L = (torch.as_tensor(W, device=DEV) * M1.double()).sum()
+    assert abs(L.item() - oracle_loss(t64, v64)) <= 1e-5 * max(1.0, abs(L.item()))
+    L.backward()
+    assert tt.grad.dtype == torch.float32 and vv.grad.dtype == torch.float32
+    gt = tt.grad.cpu().numpy().astype(np.float64)
+    gv = vv.grad.cpu().numpy().astype(np.float64)
+    scale = max(1.0, float(np.max(np.abs(gt))), float(np.max(np.abs(gv))))
+    h = 1e-6
+    checked = 0
+    for k in range(len(t64)):
+        if np.isfinite(b) and abs(t64[k] - b) < 1e-4 or a > 0 and abs(t64[k] - a) < 1e-4:
+            continue
+        for arr, g in ((t64, gt), (v64, gv)):
+            x = arr.copy()
+            x[k] += h
+            lp = oracle_loss(x, v64) if arr is t64 else oracle_loss(t64, x)
+            x[k] -= 2 * h
+            lm = oracle_loss(x, v64) if arr is t64 else oracle_loss(t64, x)
+            fd = (lp - lm) / (2 * h)
+            fixed = (arr is t64 and k in set(o[:-1].tolist())) or \
+                    (arr is v64 and k in set((o[1:] - 1).tolist()))
+            if fixed:
+                assert g[k] == 0.0, (k, g[k])
+            else:
+                assert abs(g[k] - fd) <= 2e-5 * scale, (k, arr is t64, g[k], fd)
+                checked += 1
+    assert checked > 60
