@@ -292,6 +292,14 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) long long lds_i64;
 
+// The adjoint's tile state: its partial-sum slots hold the pair weights.
+using AdjShared = TileSharedT<kMaxPairs>;
+static_assert(sizeof(AdjShared) + kAdjLdsBytes <= 160 * 1024 / kWgPerCu,
+              "the adjoint's tile state and records must fit a CU's LDS");
+static_assert((int64_t)kMaxBlock * (kAdjLdsBytes / 8) + 8 * (int64_t)kMaxPairs <
+                  ((int64_t)1 << 30),
+              "adjoint LDS tiles scan in 32 bits");
+
 // The adjoint's LDS layout for records of type T.
 template <typename T> struct AdjLayout {
     static constexpr int kRecBytes = (int)sizeof(Rec<T>);
@@ -473,7 +481,7 @@ __device__ __forceinline__ void adj_load(AdjChain<T> &ch, const Rec<T> *lrec, in
 // Starting state at step d of pair k (merge-path split), weights from
 // sh.part.
 template <typename T, int HK>
-__device__ __forceinline__ void adj_begin(AdjChain<T> &ch, const TileShared &sh,
+__device__ __forceinline__ void adj_begin(AdjChain<T> &ch, const AdjShared &sh,
                                           const Rec<T> *lrec, int32_t k, int64_t d,
                                           int32_t C, T p)
 {
@@ -512,7 +520,7 @@ __device__ __forceinline__ void adj_begin(AdjChain<T> &ch, const TileShared &sh,
 
 // Next pair with steps (row-major pair order, as the forward chain).
 template <typename T, int HK>
-__device__ __forceinline__ void adj_next_pair(AdjChain<T> &ch, const TileShared &sh,
+__device__ __forceinline__ void adj_next_pair(AdjChain<T> &ch, const AdjShared &sh,
                                               const Rec<T> *lrec, int32_t C, bool diag,
                                               int gram, T p)
 {
@@ -548,7 +556,7 @@ __device__ __forceinline__ void adj_next_pair(AdjChain<T> &ch, const TileShared 
 }
 
 template <typename T, int HK>
-__device__ __forceinline__ void adj_lane_chain(const TileShared &sh, const Rec<T> *lrec,
+__device__ __forceinline__ void adj_lane_chain(const AdjShared &sh, const Rec<T> *lrec,
                                                uint32_t gb, double sv, double st, int64_t s,
                                                int64_t e, int32_t k, int32_t C, bool diag,
                                                int gram, T p)
@@ -578,7 +586,7 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     // tile state in static LDS, records (and the adjoint's accumulators)
     // in the dynamic part: distinct objects, so the compiler knows that the
     // direct record loads into the latter never touch the former
-    __shared__ TileShared sh;
+    __shared__ AdjShared sh;
     extern __shared__ __align__(16) unsigned char smem[];
     const WsHeader &h = hdr_of(args.ws);
     Rec<T> *lrec = reinterpret_cast<Rec<T> *>(smem);

@@ -27,6 +27,10 @@ constexpr int kMaxPairs = kMaxBlock * kMaxBlock;
 #define PCF_LDSREC (136 * 1024)
 #endif
 constexpr int kLdsRecordBytes = PCF_LDSREC;
+// The adjoint's LDS bytes for records and gradient slots: its tile state
+// holds partial-sum slots for one value a pair only (the pair weights), 8 KiB
+// less than the forward's, which go to the records.
+constexpr int kAdjLdsBytes = kLdsRecordBytes + 8 * 1024;
 // The adjoint keeps two 64-bit gradient slots per record in two arrays after
 // its records, dL/dv then dL/dt (8-byte strides, so that random slots spread
 // over the LDS banks): adj_lds_records(rec_bytes) records a tile (a multiple
@@ -34,7 +38,7 @@ constexpr int kLdsRecordBytes = PCF_LDSREC;
 // its dL/dt slot (a constant offset of the LDS atomics, which holds 16 bits).
 constexpr int adj_lds_records(int rec_bytes)
 {
-    return kLdsRecordBytes / (rec_bytes + 16) / 64 * 64;
+    return kAdjLdsBytes / (rec_bytes + 16) / 64 * 64;
 }
 constexpr uint32_t adj_gt_offset(int rec_bytes)
 {
@@ -47,8 +51,8 @@ constexpr int adj_stage_unroll(int rec_bytes)
 }
 static_assert(adj_gt_offset(16) + 8 * 8 <= 65535 && adj_gt_offset(8) + 8 * 8 <= 65535,
               "adjoint LDS layout");
-static_assert(adj_lds_records(16) * (16 + 16) <= kLdsRecordBytes &&
-                  adj_lds_records(8) * (8 + 16) <= kLdsRecordBytes,
+static_assert(adj_lds_records(16) * (16 + 16) <= kAdjLdsBytes &&
+                  adj_lds_records(8) * (8 + 16) <= kAdjLdsBytes,
               "adjoint LDS capacity");
 
 // Rows a PCF may have (exclusive): keeps a pair's merge steps below 2^31.

@@ -182,7 +182,7 @@ struct TileDesc {
     int32_t cmag;          // floor(2^16 / C) + 1 (see div_by_c)
 };
 
-struct TileShared {
+template <int PartSlots> struct TileSharedT {
     // exclusive prefix of padded pair steps, 32-bit; a tile whose step
     // total may reach 2^30 (only global-mode tiles) keeps it in 64 bits at
     // the start of the LDS record area instead (pw_wide; see pw_at)
@@ -192,7 +192,7 @@ struct TileShared {
     // ordered); each pair then adds its slots in lane order, from the lane
     // of its first step to the lane of its last (lane_of), so the result
     // does not depend on timing
-    double part[kMaxPairs + kThreads];
+    double part[PartSlots];
     int16_t pairof[kThreads];  // pair holding the first step of each lane
     int32_t rn[kMaxBlock], rb[kMaxBlock];  // row PCF rows / record base
     int32_t cn[kMaxBlock], cb[kMaxBlock];  // column PCF rows / record base
@@ -205,6 +205,9 @@ struct TileShared {
     int32_t cmag;      // the current tile's cmag (see div_by_c)
     int32_t pw_wide;   // the step prefix is the 64-bit one in the record area
 };
+// The forward kernels' tile state: partial-sum slots for every (pair, lane)
+// combination a tile can produce (see part).
+using TileShared = TileSharedT<kMaxPairs + kThreads>;
 
 constexpr int kSharedHead = (int)((sizeof(TileShared) + 255) / 256 * 256);
 static_assert(kSharedHead + kLdsRecordBytes <= 160 * 1024 / kWgPerCu,
@@ -585,8 +588,8 @@ __device__ __forceinline__ void stage_load(StageRegs<T, Direct, U> &g, const Til
 }
 
 // LDS stores of tile d's staging (after stage_load on the same thread).
-template <typename T, bool Direct, int U = stage_unroll<T>()>
-__device__ __forceinline__ void stage_store(TileShared &sh, const StageRegs<T, Direct, U> &g,
+template <typename T, bool Direct, int U = stage_unroll<T>(), typename Sh>
+__device__ __forceinline__ void stage_store(Sh &sh, const StageRegs<T, Direct, U> &g,
                                             const TileDesc &d, Rec<T> *lrec)
 {
     const int tid = threadIdx.x;
@@ -732,14 +735,16 @@ struct LaneSplit {
 };
 
 // Entry k of the tile's step prefix (pw64: the LDS record area).
-__device__ __forceinline__ int64_t pw_at(const TileShared &sh, const int64_t *pw64, int k)
+template <typename Sh>
+__device__ __forceinline__ int64_t pw_at(const Sh &sh, const int64_t *pw64, int k)
 {
     return sh.pw_wide ? pw64[k] : (int64_t)sh.pw[k];
 }
 
 // The lane whose run holds step `step` of the tile (the inverse of
 // lane_steps).
-__device__ __forceinline__ int32_t lane_of(const TileShared &sh, int64_t step)
+template <typename Sh>
+__device__ __forceinline__ int32_t lane_of(const Sh &sh, int64_t step)
 {
     const int g = (step >= sh.gbase[1] ? 1 : 0) + (step >= sh.gbase[2] ? 1 : 0) +
                   (step >= sh.gbase[3] ? 1 : 0);
@@ -753,7 +758,8 @@ __device__ __forceinline__ int32_t lane_of(const TileShared &sh, int64_t step)
 }
 
 // Steps [s, e) of lane `lane` (e <= s when it has none).
-__device__ __forceinline__ void lane_steps(const TileShared &sh, int lane,
+template <typename Sh>
+__device__ __forceinline__ void lane_steps(const Sh &sh, int lane,
                                            int64_t total, int64_t &s, int64_t &e)
 {
     const int g = lane / kGroupLanes;
@@ -778,8 +784,8 @@ static_assert((int64_t)kMaxBlock * (kLdsRecordBytes / 8) + 8 * (int64_t)kMaxPair
 // of every PCF of the tile (sh.rlast, clast),
 // read from `src` (the LDS records, or the packed records in global mode).
 // Needs the staged tile; ends with a barrier.
-template <typename T, int WS = forward_weights<T>()>
-__device__ __forceinline__ void tile_scan(TileShared &sh, const TileDesc &d,
+template <typename T, int WS = forward_weights<T>(), typename Sh>
+__device__ __forceinline__ void tile_scan(Sh &sh, const TileDesc &d,
                                           int gram, const Rec<T> *src, int64_t *pw64,
                                           PhaseClock &pc)
 {
@@ -884,8 +890,8 @@ struct TileLoop {
     __device__ __forceinline__ int aft() const { return cur == 0 ? 2 : cur - 1; }
 
     // decode the first two tiles, stage the first one
-    template <typename T, bool Direct>
-    __device__ __forceinline__ void start(TileShared &sh, const unsigned char *ws,
+    template <typename T, bool Direct, typename Sh>
+    __device__ __forceinline__ void start(Sh &sh, const unsigned char *ws,
                                           const int64_t *offsets, Rec<T> *lrec,
                                           const Rec<T> *grec)
     {
@@ -901,7 +907,8 @@ struct TileLoop {
         }
         sync_lds();
     }
-    __device__ __forceinline__ bool live(const TileShared &sh,
+    template <typename Sh>
+    __device__ __forceinline__ bool live(const Sh &sh,
                                          const unsigned char *ws) const
     {
         return sh.desc[cur].tile < hdr_of(ws).ntiles;
@@ -913,7 +920,8 @@ struct TileLoop {
             ticket = tile_ticket(ws);
     }
     // after the merge work (and its barrier), before finishing
-    __device__ __forceinline__ void decode_next(TileShared &sh,
+    template <typename Sh>
+    __device__ __forceinline__ void decode_next(Sh &sh,
                                                 const unsigned char *ws,
                                                 const int64_t *offsets)
     {
@@ -921,7 +929,8 @@ struct TileLoop {
             tile_decode(sh.desc[aft()], ticket, ws, offsets);
     }
     // whether there is a next tile (its descriptor, decoded one tile ago)
-    __device__ __forceinline__ bool has_next(const TileShared &sh,
+    template <typename Sh>
+    __device__ __forceinline__ bool has_next(const Sh &sh,
                                              const unsigned char *ws) const
     {
         return sh.desc[nxt()].tile < hdr_of(ws).ntiles;
@@ -929,8 +938,8 @@ struct TileLoop {
     // staging of the next tile, after finishing the current one; `barrier`
     // when the finishing code reads records or block metadata (otherwise a
     // wave stages as soon as its own finishing work is done)
-    template <typename T, bool Direct>
-    __device__ __forceinline__ void stage_next(TileShared &sh, const unsigned char *ws,
+    template <typename T, bool Direct, typename Sh>
+    __device__ __forceinline__ void stage_next(Sh &sh, const unsigned char *ws,
                                                const Rec<T> *grec,
                                                const int64_t *offsets,
                                                Rec<T> *lrec, bool barrier) const

@@ -97,11 +97,12 @@ def test_planner_full_matrix_blocks():
     counts = rng.integers(1, 600, size=500)
     o = np.concatenate([[0], np.cumsum(counts)])
     for dtype, rec, bwd in [(_lib.PCF_F64, 16, False), (_lib.PCF_F32, 8, False),
-                            (_lib.PCF_F64, 16, True)]:
+                            (_lib.PCF_F64, 16, True), (_lib.PCF_F32, 8, True)]:
         nb, ns, nt, blocks = _inspect(o, dtype, backward=bwd)
         # LDS record area of a tile: half the records that fit (the adjoint's
-        # records each come with 16 bytes of gradient slots)
-        budget = (136 * 1024 // 32 if bwd else 136 * 1024 // rec) // 2
+        # 144 KiB hold records with 16 bytes of gradient slots each, in
+        # multiples of 64 records)
+        budget = ((144 * 1024 // (rec + 16)) // 64 * 64 if bwd else 136 * 1024 // rec) // 2
         assert blocks[0] == 0 and blocks[-1] == 500
         assert np.all(np.diff(blocks) >= 1) and np.all(np.diff(blocks) <= 32)
         for a, b in zip(blocks[:-1], blocks[1:]):
