@@ -19,8 +19,13 @@
 // forward kernel -- so nothing is stored between forward and backward. A
 // lane keeps the value gradient of its current two pieces in registers and
 // adds it to an LDS accumulator (one per breakpoint record of the tile) when
-// the piece ends; time gradients go to LDS at each breakpoint. The tile then
-// adds its LDS accumulators to dL/dt, dL/dv in HBM with atomics.
+// the piece ends; time gradients go to LDS at each breakpoint. The
+// accumulators are 64-bit fixed point at power-of-two scales bounded per
+// tile, so a tile's sums do not depend on the order of its adds. The tile
+// then adds them to dL/dt, dL/dv in HBM with atomics of the set's dtype, or,
+// for bit-identical results (FP64 only), as 64-bit integers at scales
+// bounded over the whole set, converted by a last pass. FP64 and FP32 sets
+// run the same kernel on their own record type.
 #include <hip/hip_runtime.h>
 
 #include <float.h>
