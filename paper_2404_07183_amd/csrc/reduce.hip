@@ -109,50 +109,6 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// A's share of the first q positions of the merge of sorted lists A (nA
-// rows) and B (nB rows), ties first from A: the smallest i in
-// [max(0, q - nB), min(q, nA)] with A[i] > B[q - 1 - i] (that bound if
-// none), as the binary search in red_level finds it; for two positions at
-// once, q0 by lanes 0-31 and q1 by lanes 32-63 (i0, i1 returned to every
-// lane). Each round a half tests 32 evenly spaced candidates and keeps the
-// interval between the last that holds A[i] <= B[q - 1 - i] and the first
-// that does not, so a list of n rows takes about log_33(n) rounds of
-// dependent loads instead of log_2(n).
-template <typename T>
-__device__ __forceinline__ void wave_split2(const T *tA, int64_t nA, const T *tB, int64_t nB,
-                                            int64_t q0, int64_t q1, int lane, int64_t &i0,
-                                            int64_t &i1)
-{
-    const int half = lane >> 5, sub = lane & 31;
-    const int64_t q = half ? q1 : q0;
-    int64_t lo = q - nB > 0 ? q - nB : 0, hi = q < nA ? q : nA;
-    while (__ballot(hi > lo) != 0) {
-        const int64_t w = hi - lo;
-        // candidates m_0 < m_1 < ... in [lo, hi): all of [lo, hi) when it
-        // holds at most 32 rows
-        const int64_t m = w <= 32 ? lo + sub : lo + (w * (sub + 1)) / 33;
-        const bool valid = w > 32 ? true : sub < w;
-        const bool holds = valid && tA[m] <= tB[q - 1 - m];
-        const unsigned long long bal = __ballot(holds);
-        // the predicate holds below a point: its count in this half
-        const int t = __popc((unsigned)(half ? bal >> 32 : bal));
-        if (w <= 0) {
-            // (this half is done)
-        } else if (w <= 32) {
-            lo = hi = lo + t;
-        } else if (t == 0) {
-            hi = lo + w / 33;  // m_0: the answer is at most m_0
-        } else {
-            const int64_t mt1 = lo + (w * t) / 33;  // m_{t-1}
-            if (t < 32)
-                hi = lo + (w * (t + 1)) / 33;       // m_t
-            lo = mt1 + 1;
-        }
-    }
-    i0 = __shfl(lo, 0, 64);
-    i1 = __shfl(lo, 32, 64);
-}
-
 // A wave takes 64 * kMergeK consecutive rows; lane l walks rows
 // l * kMergeK .. of them. The results go through a wave-private LDS buffer
 // so that the stores to memory are coalesced.
@@ -170,78 +126,30 @@ __global__ __launch_bounds__(256) void red_level(RedLevelArgs a)
     const int64_t r0g = a.offsets[a.groups[0]], r1g = a.offsets[a.groups[a.B]];
     for (int64_t wb = r0g + ((int64_t)blockIdx.x * 4 + wv) * kPerWave; wb < r1g;
          wb += (int64_t)gridDim.x * 4 * kPerWave) {
-        // the pair holding the wave's first row; when all the wave's rows lie
-        // in that pair (and it merges two lists), the merge-path splits at
-        // the window's two ends, found by the whole wave, bound every lane's
-        // search to the window
-        const int64_t we = wb + kPerWave < r1g ? wb + kPerWave : r1g;
-        PairAt pw;
-        {
-            const int64_t pcf = a.row_pcf[wb];
-            const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
-            pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span),
-                      span, pw);
-        }
-        const int64_t qw0 = wb - pw.sA, qw1 = we - pw.sA;
-        const bool inside = pw.nB > 0 && qw1 <= pw.nA + pw.nB;
-        int64_t iw0 = 0, iw1 = 0;
-        if (inside) {
-            wave_split2(tin + pw.sA, pw.nA, tin + pw.sB, pw.nB, qw0, qw1, lane, iw0, iw1);
-            // the window's rows of A and B (at most kPerWave of each) into
-            // the wave's staging buffers, for the lanes' own searches
-            const int64_t jw0 = qw0 - iw0, jw1 = qw1 - iw1;
-            for (int64_t k = lane; k < iw1 - iw0; k += 64)
-                st_t[wv][k] = tin[pw.sA + iw0 + k];
-            for (int64_t k = lane; k < jw1 - jw0; k += 64)
-                st_v[wv][k] = tin[pw.sB + jw0 + k];
-            wave_sync_lds();
-        }
         const int64_t r0 = wb + (int64_t)lane * kMergeK;
         if (r0 < r1g) {
             const int64_t r1 = r0 + kMergeK < r1g ? r0 + kMergeK : r1g;
             // the pair holding row r0, and the merge state at its position
-            PairAt p = pw;
-            if (!inside) {
-                const int64_t pcf = a.row_pcf[r0];
-                const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
-                pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span),
-                          span, p);
-            }
+            const int64_t pcf = a.row_pcf[r0];
+            const int64_t b = last_le(a.groups, (int64_t)a.B + 1, pcf);
+            PairAt p;
+            pair_from(a, b, a.groups[b] + ((pcf - a.groups[b]) / (2 * span)) * (2 * span), span,
+                      p);
             int64_t q = r0 - p.sA;
             int64_t i, j;
             {
                 int64_t lo = q - p.nB > 0 ? q - p.nB : 0, hi = q < p.nA ? q : p.nA;
-                if (inside) {
-                    // i(q) is nondecreasing in q, and so is q - i(q): the
-                    // search stays in the staged window (A's rows iw0.., B's
-                    // rows jw0..)
-                    const int64_t jw0 = qw0 - iw0, jw1 = qw1 - iw1;
-                    lo = lo > iw0 ? lo : iw0;
-                    lo = lo > q - jw1 ? lo : q - jw1;
-                    hi = hi < iw1 ? hi : iw1;
-                    hi = hi < q - jw0 ? hi : q - jw0;
-                    while (lo < hi) {
-                        const int64_t mid = (lo + hi) >> 1;
-                        if (st_t[wv][mid - iw0] <= st_v[wv][q - 1 - mid - jw0])
-                            lo = mid + 1;
-                        else
-                            hi = mid;
-                    }
-                } else {
-                    const T *tA = tin + p.sA, *tB = tin + p.sB;
-                    while (lo < hi) {  // A's share of the first q merged positions
-                        const int64_t mid = (lo + hi) >> 1;
-                        if (tA[mid] <= tB[q - 1 - mid])
-                            lo = mid + 1;
-                        else
-                            hi = mid;
-                    }
+                const T *tA = tin + p.sA, *tB = tin + p.sB;
+                while (lo < hi) {  // A's share of the first q merged positions
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (tA[mid] <= tB[q - 1 - mid])
+                        lo = mid + 1;
+                    else
+                        hi = mid;
                 }
                 i = lo;
                 j = q - lo;
             }
-            // (the staged window is read before the results overwrite it)
-            wave_sync_lds();
             for (int64_t r = r0; r < r1; ++r) {
                 if (q == p.nA + p.nB) {  // crossed into the next pair (or group)
                     int64_t nb = p.b, ni = p.iE;
