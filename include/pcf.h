@@ -182,12 +182,12 @@ pcf_status pcf_pairwise_lp_noalloc(const pcf_set *X, pcf_kind kind, double p,
  * scales bounded from its own weights, values and piece lengths
  * (order-independent), and adds the sums to grad_t, grad_v with atomics of
  * the set's dtype, whose order, and so the last bits, may vary between runs.
- * With PCF_DETERMINISTIC (FP64 sets only: PCF_EUNSUPPORTED for FP32, whose
- * gradient arrays cannot hold the 64-bit sums) the sums in HBM are 64-bit
- * fixed point too, at
+ * With PCF_DETERMINISTIC the sums in HBM are 64-bit fixed point too (for
+ * FP32 sets in the workspace, which pcf_workspace_bytes with backward = 1
+ * sizes for it), at
  * scales bounded from the whole set (largest |w_ij|, |v| and piece length,
- * found by two extra passes over grad_out, fwd_out and the records): grad_t
- * and grad_v hold the integer sums until a last pass converts them in place,
+ * found by two extra passes over grad_out, fwd_out and the records), until a
+ * last pass converts them into grad_t and grad_v,
  * and the result is bit-identical run to run for a given plan and tile
  * shape. Each term is then rounded to a unit of about 2^-61 (n + 1) times
  * the set's largest possible term, so gradients far below that lose

@@ -965,9 +965,6 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
         return fail(PCF_EINVAL, "p must be finite and >= 1");
     const bool f64 = X->dtype == PCF_F64;
     const bool fixed = (flags & PCF_DETERMINISTIC) != 0;
-    if (fixed && !f64)
-        return fail(PCF_EUNSUPPORTED, "PCF_DETERMINISTIC: the adjoint's integer sums in HBM "
-                                      "need FP64 gradient arrays");
     if (X->n == 0)
         return PCF_OK;
     const bool chain = kind == PCF_LP && p != 1.0;
@@ -1024,7 +1021,9 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
     const int hk = kind == PCF_GRAM ? HK_PROD
                                     : (p == 1.0 ? HK_ABS : (p == 2.0 ? HK_SQR : HK_POW));
     if (fixed) {
-        e = launch_adj_bounds(a, s);
+        e = launch_adj_bounds(f64, a, s);
+        if (e == hipSuccess && !f64)
+            e = launch_adj_acc(a, P, s);
         if (e != hipSuccess)
             return hip_fail(e, "adjoint bounds launch");
     }
@@ -1032,7 +1031,7 @@ pcf_status pcf_pairwise_backward(const pcf_set *X, pcf_kind kind, double p,
     if (e != hipSuccess)
         return hip_fail(e, "adjoint kernel launch");
     if (fixed) {
-        e = launch_adj_finish(hk, a, P, s);
+        e = launch_adj_finish(hk, f64, a, P, s);
         if (e != hipSuccess)
             return hip_fail(e, "adjoint finish launch");
     }

@@ -23,9 +23,10 @@
 // accumulators are 64-bit fixed point at power-of-two scales bounded per
 // tile, so a tile's sums do not depend on the order of its adds. The tile
 // then adds them to dL/dt, dL/dv in HBM with atomics of the set's dtype, or,
-// for bit-identical results (FP64 only), as 64-bit integers at scales
-// bounded over the whole set, converted by a last pass. FP64 and FP32 sets
-// run the same kernel on their own record type.
+// for bit-identical results, as 64-bit integers at scales bounded over the
+// whole set (in the gradient arrays themselves for FP64, in the workspace
+// for FP32), converted by a last pass. FP64 and FP32 sets run the same
+// kernel on their own record type.
 #include <hip/hip_runtime.h>
 
 #include <float.h>
@@ -159,36 +160,29 @@ __device__ __forceinline__ long long fixed_rescale(long long v, int k)
 template <typename T> struct GradSink {
     T *gt;  // indexed by record index
     T *gv;
+    unsigned long long *at, *av;  // fixed-point sums, indexed alike
     int32_t last;  // record index of the PCF's last row (fixed value)
-    int fixed;     // 1: the arrays hold fixed-point sums at scales st, sv (FP64)
+    int fixed;     // 1: add to at, av at scales st, sv instead
     double st, sv;
 };
 
 template <typename T>
 __device__ __forceinline__ void sink_add_t(const GradSink<T> &s, int32_t q, double x)
 {
-    if constexpr (sizeof(T) == 8) {
-        if (s.fixed) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s.gt[q]),
-                      (unsigned long long)fixed_of(x, s.st));
-            return;
-        }
-    }
-    atomicAdd(&s.gt[q], (T)x);
+    if (s.fixed)
+        atomicAdd(&s.at[q], (unsigned long long)fixed_of(x, s.st));
+    else
+        atomicAdd(&s.gt[q], (T)x);
 }
 template <typename T>
 __device__ __forceinline__ void sink_add_v(const GradSink<T> &s, int32_t q, double x)
 {
     if (q >= s.last)
         return;
-    if constexpr (sizeof(T) == 8) {
-        if (s.fixed) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(&s.gv[q]),
-                      (unsigned long long)fixed_of(x, s.sv));
-            return;
-        }
-    }
-    atomicAdd(&s.gv[q], (T)x);
+    if (s.fixed)
+        atomicAdd(&s.av[q], (unsigned long long)fixed_of(x, s.sv));
+    else
+        atomicAdd(&s.gv[q], (T)x);
 }
 
 // The record at src[i] in FP64 (the sentinel time becomes DBL_MAX).
@@ -607,6 +601,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
     const double p = args.p;
     T *const grad_t = reinterpret_cast<T *>(args.grad_t);
     T *const grad_v = reinterpret_cast<T *>(args.grad_v);
+    // deterministic mode's 64-bit sums: FP64 gradients hold them in place,
+    // FP32 ones in the workspace (dL/dt rows, then dL/dv rows)
+    unsigned long long *const acc_t =
+        sizeof(T) == 8 ? reinterpret_cast<unsigned long long *>(args.grad_t)
+                       : reinterpret_cast<unsigned long long *>(args.ws + h.off_acc);
+    unsigned long long *const acc_v =
+        sizeof(T) == 8 ? reinterpret_cast<unsigned long long *>(args.grad_v)
+                       : acc_t + (h.rec_count - h.npcf * kPad);
     // deterministic mode: the set's scales of the sums in HBM
     int gev = 0, get = 0;
     if (args.fixed)
@@ -727,6 +729,10 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 sa.gv = grad_v - i * kPad;
                 sb.gt = grad_t - j * kPad;
                 sb.gv = grad_v - j * kPad;
+                sa.at = acc_t - i * kPad;
+                sa.av = acc_v - i * kPad;
+                sb.at = acc_t - j * kPad;
+                sb.av = acc_v - j * kPad;
                 sa.fixed = sb.fixed = args.fixed;
                 sa.st = sb.st = gst;
                 sa.sv = sb.sv = gsv;
@@ -808,19 +814,14 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
         for (int u = 0; u < L::kUnroll; ++u) {
             if (frow[u] < 0)
                 continue;
-            if constexpr (sizeof(T) == 8) {
-                if (args.fixed) {
-                    const unsigned long long bv =
-                        (unsigned long long)__double_as_longlong(fv[u]);
-                    const unsigned long long bt =
-                        (unsigned long long)__double_as_longlong(ft[u]);
-                    if (bv != 0)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&grad_v[frow[u]]), bv);
-                    if (bt != 0)
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&grad_t[frow[u] + 1]),
-                                  bt);
-                    continue;
-                }
+            if (args.fixed) {
+                const unsigned long long bv = (unsigned long long)__double_as_longlong(fv[u]);
+                const unsigned long long bt = (unsigned long long)__double_as_longlong(ft[u]);
+                if (bv != 0)
+                    atomicAdd(&acc_v[frow[u]], bv);
+                if (bt != 0)
+                    atomicAdd(&acc_t[frow[u] + 1], bt);
+                continue;
             }
             if (fv[u] != 0.0)
                 atomicAdd(&grad_v[frow[u]], (T)fv[u]);
@@ -937,21 +938,22 @@ __global__ __launch_bounds__(256) void adj_bounds_pairs(BwdArgs a)
 
 // The largest |v| and piece length of the packed records (a piece starts
 // at the previous record's end time, or at 0 after a sentinel).
+template <typename T>
 __global__ __launch_bounds__(256) void adj_bounds_records(BwdArgs a)
 {
     __shared__ double red[4];
     WsHeader *h = reinterpret_cast<WsHeader *>(a.ws);
-    const Rec<double> *rec = reinterpret_cast<const Rec<double> *>(a.ws + h->off_rec);
+    const Rec<T> *rec = reinterpret_cast<const Rec<T> *>(a.ws + h->off_rec);
     const int64_t count = h->rec_count;
-    const double S = sentinel<double>();
+    const T S = sentinel<T>();
     double mv = 0.0, ml = 0.0;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const Rec<double> r = rec[q];
-        mv = fmax(mv, fabs(r.v));
+        const Rec<T> r = rec[q];
+        mv = fmax(mv, fabs((double)r.v));
         if (r.t < S) {
-            const double t0 = q > 0 ? rec[q - 1].t : 0.0;
-            ml = fmax(ml, r.t - (t0 < S ? t0 : 0.0));
+            const T t0 = q > 0 ? rec[q - 1].t : T(0);
+            ml = fmax(ml, (double)r.t - (t0 < S ? (double)t0 : 0.0));
         }
     }
     block_max_to(mv, &h->adj_max[1], red);
@@ -959,7 +961,17 @@ __global__ __launch_bounds__(256) void adj_bounds_records(BwdArgs a)
     block_max_to(ml, &h->adj_max[2], red);
 }
 
-hipError_t launch_adj_bounds(const BwdArgs &a, hipStream_t s)
+// Clears an FP32 plan's 64-bit sums (n words at the header's off_acc).
+__global__ __launch_bounds__(256) void adj_zero_acc(unsigned char *ws, int64_t n)
+{
+    const WsHeader *h = reinterpret_cast<const WsHeader *>(ws);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(ws + h->off_acc);
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        acc[k] = 0ull;
+}
+
+hipError_t launch_adj_bounds(bool f64, const BwdArgs &a, hipStream_t s)
 {
     hipError_t e = launch_zero(reinterpret_cast<double *>(
                                    a.ws + offsetof(WsHeader, adj_max)),
@@ -973,29 +985,49 @@ hipError_t launch_adj_bounds(const BwdArgs &a, hipStream_t s)
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(adj_bounds_records, dim3(1024), dim3(256), 0, s, a);
+    if (f64)
+        hipLaunchKernelGGL(adj_bounds_records<double>, dim3(1024), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(adj_bounds_records<float>, dim3(1024), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-// The fixed-point sums in grad_t, grad_v (P entries each) to FP64, in place.
-template <int HK>
+// The fixed-point sums (P rows each; FP64 gradients hold them in place,
+// FP32 ones in the workspace) to the gradients' type.
+template <typename T, int HK>
 __global__ __launch_bounds__(256) void adj_finish(BwdArgs a, int64_t P)
 {
+    const WsHeader &h = *reinterpret_cast<const WsHeader *>(a.ws);
     int ev, et;
-    set_exps<HK>(*reinterpret_cast<const WsHeader *>(a.ws), a.n, a.p, ev, et);
+    set_exps<HK>(h, a.n, a.p, ev, et);
     const double iv = ldexp(1.0, -ev), it = ldexp(1.0, -et);
-    long long *gt = reinterpret_cast<long long *>(a.grad_t);
-    long long *gv = reinterpret_cast<long long *>(a.grad_v);
-    double *ot = reinterpret_cast<double *>(a.grad_t);
-    double *ov = reinterpret_cast<double *>(a.grad_v);
+    const long long *gt = reinterpret_cast<const long long *>(
+        sizeof(T) == 8 ? (const unsigned char *)a.grad_t : a.ws + h.off_acc);
+    const long long *gv = reinterpret_cast<const long long *>(
+        sizeof(T) == 8 ? (const unsigned char *)a.grad_v : a.ws + h.off_acc + 8 * P);
+    T *ot = reinterpret_cast<T *>(a.grad_t);
+    T *ov = reinterpret_cast<T *>(a.grad_v);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < P;
          k += (int64_t)gridDim.x * blockDim.x) {
-        ot[k] = (double)gt[k] * it;
-        ov[k] = (double)gv[k] * iv;
+        // (read both sums before writing: FP64 converts in place)
+        const long long xt = gt[k], xv = gv[k];
+        ot[k] = (T)((double)xt * it);
+        ov[k] = (T)((double)xv * iv);
     }
 }
 
-hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s)
+template <typename T>
+static void launch_finish_t(int hk, const BwdArgs &a, int64_t P, dim3 g, dim3 b, hipStream_t s)
+{
+    switch (hk) {
+    case kAbs: hipLaunchKernelGGL((adj_finish<T, kAbs>), g, b, 0, s, a, P); break;
+    case kSqr: hipLaunchKernelGGL((adj_finish<T, kSqr>), g, b, 0, s, a, P); break;
+    case kProd: hipLaunchKernelGGL((adj_finish<T, kProd>), g, b, 0, s, a, P); break;
+    default: hipLaunchKernelGGL((adj_finish<T, kPow>), g, b, 0, s, a, P); break;
+    }
+}
+
+hipError_t launch_adj_finish(int hk, bool f64, const BwdArgs &a, int64_t P, hipStream_t s)
 {
     if (P <= 0)
         return hipSuccess;
@@ -1003,12 +1035,23 @@ hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s)
     if (blocks > 4096)
         blocks = 4096;
     const dim3 g((unsigned)blocks), b(256);
-    switch (hk) {
-    case kAbs: hipLaunchKernelGGL(adj_finish<kAbs>, g, b, 0, s, a, P); break;
-    case kSqr: hipLaunchKernelGGL(adj_finish<kSqr>, g, b, 0, s, a, P); break;
-    case kProd: hipLaunchKernelGGL(adj_finish<kProd>, g, b, 0, s, a, P); break;
-    default: hipLaunchKernelGGL(adj_finish<kPow>, g, b, 0, s, a, P); break;
+    if (f64) {
+        launch_finish_t<double>(hk, a, P, g, b, s);
+    } else {
+        // the FP32 plan's sums are cleared before the adjoint (launch_adj_acc)
+        launch_finish_t<float>(hk, a, P, g, b, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_acc(const BwdArgs &a, int64_t P, hipStream_t s)
+{
+    if (P <= 0)
+        return hipSuccess;
+    int64_t blocks = (2 * P + 255) / 256;
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(adj_zero_acc, dim3((unsigned)blocks), dim3(256), 0, s, a.ws, 2 * P);
     return hipGetLastError();
 }
 

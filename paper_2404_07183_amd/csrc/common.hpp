@@ -94,7 +94,9 @@ struct WsHeader {
     // deterministic adjoint: the largest |W|, |v| and piece length, as bit
     // patterns (non-negative doubles order like their patterns)
     unsigned long long adj_max[3];
-    int64_t reserved[2];
+    int64_t off_acc;      // FP32 adjoint plans: 64-bit sums of dL/dt, dL/dv (2 x 8 bytes
+                          // a row) for PCF_DETERMINISTIC; else 0
+    int64_t reserved[1];
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 

@@ -42,8 +42,9 @@ struct BwdArgs {
     int chain;               // 1: scale by dF/dI = (1/p) I^(1/p - 1)
     int gram;                // 1: diagonal pairs carry work (Gram)
     int64_t n;               // PCFs in the set
-    int fixed;               // 1: deterministic: grad_t, grad_v hold 64-bit
-                             // fixed-point sums at the set's scales until
+    int fixed;               // 1: deterministic: 64-bit fixed-point sums at
+                             // the set's scales (FP64: in grad_t, grad_v; FP32:
+                             // in the workspace, off_acc) until
                              // launch_adj_finish (needs launch_adj_bounds first)
 };
 
@@ -101,8 +102,10 @@ hipError_t launch_backward(int hk, bool f64, const BwdArgs &a, int grid, hipStre
 // Deterministic adjoint: the set's largest pair weight, |v| and piece length
 // into the workspace header (before launch_backward with a.fixed), and the
 // fixed-point sums converted to FP64 in place (after it).
-hipError_t launch_adj_bounds(const BwdArgs &a, hipStream_t s);
-hipError_t launch_adj_finish(int hk, const BwdArgs &a, int64_t P, hipStream_t s);
+hipError_t launch_adj_bounds(bool f64, const BwdArgs &a, hipStream_t s);
+hipError_t launch_adj_finish(int hk, bool f64, const BwdArgs &a, int64_t P, hipStream_t s);
+// Clears an FP32 plan's deterministic sums (2 P words in the workspace).
+hipError_t launch_adj_acc(const BwdArgs &a, int64_t P, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
 // Raises a kernel's dynamic-LDS limit to `bytes` once per device (thread

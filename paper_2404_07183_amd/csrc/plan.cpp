@@ -123,6 +123,7 @@ bool plan_matrix(int64_t n, const int64_t *offsets, int rec_bytes,
     plan.npcf = n;
     plan.rec_count = (n > 0 ? offsets[n] : 0) + n * kPad;
     plan.lds_records = lds_record_capacity(rec_bytes, backward);
+    plan.backward = backward;
     if (r1 == r0 || c1 == c0)
         return true;
 
@@ -248,12 +249,23 @@ bool plan_batched(int32_t B, const int64_t *set_offsets,
     return true;
 }
 
+// FP32 adjoint plans: two 64-bit sums a row for PCF_DETERMINISTIC (FP64
+// plans keep them in the gradient arrays themselves).
+int64_t adj_acc_bytes(const Plan &plan, int rec_bytes)
+{
+    if (!plan.backward || rec_bytes == 16)
+        return 0;
+    const int64_t rows = plan.rec_count - plan.npcf * kPad;
+    return align_up(rows * 16, 256);
+}
+
 int64_t plan_workspace_bytes(const Plan &plan, int rec_bytes)
 {
     int64_t off = kHeaderBytes;
     off += align_up((int64_t)plan.blocks.size() * 4, 256);
     off += align_up((int64_t)plan.segs.size() * (int64_t)sizeof(Segment), 256);
     off += align_up(plan.rec_count * rec_bytes, 256);
+    off += adj_acc_bytes(plan, rec_bytes);
     return off;
 }
 
@@ -263,6 +275,7 @@ int64_t plan_workspace_bound(const Plan &plan, int rec_bytes)
     off += align_up((plan.npcf + 1) * 4, 256);
     off += align_up((int64_t)plan.segs.size() * (int64_t)sizeof(Segment), 256);
     off += align_up(plan.rec_count * rec_bytes, 256);
+    off += adj_acc_bytes(plan, rec_bytes);
     return off;
 }
 
@@ -282,6 +295,9 @@ void plan_serialise(const Plan &plan, int rec_bytes,
     hdr.rec_bytes = rec_bytes;
     hdr.first_bad = -1;
     hdr.lds_records = plan.lds_records;
+    hdr.off_acc = adj_acc_bytes(plan, rec_bytes) > 0
+                      ? hdr.off_rec + align_up(plan.rec_count * rec_bytes, 256)
+                      : 0;
     buf.assign((size_t)hdr.off_rec, 0);
     std::memcpy(buf.data(), &hdr, sizeof(hdr));
     if (!plan.blocks.empty())

@@ -25,6 +25,7 @@ struct Plan {
     int64_t npcf = 0;
     int64_t rec_count = 0;        // offsets[n] + n * kPad
     int64_t lds_records = 0;
+    bool backward = false;        // an adjoint plan
 };
 
 // Tile shape: at most `max_block` PCFs per block and at most 1/`budget_div`
@@ -59,6 +60,8 @@ bool plan_batched(int32_t B, const int64_t *set_offsets,
                   const TileShape &shape, Plan &plan, std::string &err);
 
 // Bytes of workspace a plan needs (header, blocks, segments, records).
+// Bytes of an FP32 adjoint plan's 64-bit gradient sums (0 otherwise).
+int64_t adj_acc_bytes(const Plan &plan, int rec_bytes);
 int64_t plan_workspace_bytes(const Plan &plan, int rec_bytes);
 // Upper bound of plan_workspace_bytes over all tile shapes (every PCF its
 // own block).

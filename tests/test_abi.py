@@ -285,19 +285,6 @@ def test_backward_deterministic_size_limit():
     assert "DETERMINISTIC" in _lib.last_error()
 
 
-def test_backward_deterministic_refused_for_fp32():
-    """PCF_DETERMINISTIC keeps its integer sums in the gradient arrays, which
-    need 8 bytes an entry: FP32 sets are refused before any device work."""
-    lib = _lib.load()
-    off = np.array([0, 2, 4], dtype=np.int64)
-    fake = ctypes.c_void_p(0x1000)
-    X = _lib.pcf_set(2, fake, fake, fake, _lib.PCF_F32, off.ctypes.data)
-    st = lib.pcf_pairwise_backward(ctypes.byref(X), _lib.PCF_LP, 1.0, fake, 2, None, 0, fake,
-                                   fake, fake, 1 << 20, _lib.PCF_DETERMINISTIC, None)
-    assert st == _lib.PCF_EUNSUPPORTED
-    assert "DETERMINISTIC" in _lib.last_error()
-
-
 def test_plan_reuse_refused_without_a_matching_plan():
     """PCF_REUSE_PLAN on a workspace this library never planned into is
     refused before any device work."""

@@ -126,6 +126,44 @@ def test_deterministic_adjoint_bitwise_and_oracle(seed, N, nmin, nmax):
         assert np.all(gt1[o[:-1]] == 0) and np.all(gv1[o[1:] - 1] == 0)
 
 
+def test_deterministic_adjoint_fp32():
+    # FP32 sets under PCF_DETERMINISTIC: the 64-bit sums live in the
+    # workspace; two runs give the same bits and meet the FP32 bar
+    o, t, v = _set(17, 200, 1, 90)
+    t32, v32, t64, v64 = _f32(o, t, v)
+    G = np.random.default_rng(18).uniform(-1, 1, size=(200, 200))
+    X = api.PcfSet(o, t32, v32, device=DEV)
+    Gt = torch.as_tensor(G, device=DEV)
+    for name, kind, p, okind in CASES:
+        fwd = api.pdist(X, p).to(torch.float64) if (kind == api.PCF_LP and p != 1.0) else None
+        g1 = api.pairwise_backward(X, kind, p, Gt, fwd, deterministic=True)
+        g2 = api.pairwise_backward(X, kind, p, Gt, fwd, deterministic=True)
+        for a, b in zip(g1, g2):
+            assert a.dtype == torch.float32
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32)), name
+        rt, rv = oracle.backward(okind, p, o, t64, v64, G)
+        assert _close(g1[0].cpu().numpy().astype(np.float64), rt, 1e-5), name
+        assert _close(g1[1].cpu().numpy().astype(np.float64), rv, 1e-5), name
+
+
+def test_deterministic_adjoint_workspace_reuse():
+    # the set's bounds live in the workspace header and are recomputed by
+    # every call: calls that reuse the plan (and the packed records) give the
+    # same bits as a fresh call, also after a call on other gradients
+    o, t, v = _set(13, 90, 1, 70)
+    rng = np.random.default_rng(14)
+    G1 = torch.as_tensor(rng.uniform(-1, 1, size=(90, 90)), device=DEV)
+    G2 = torch.as_tensor(rng.uniform(-1e3, 1e3, size=(90, 90)), device=DEV)
+    X = api.PcfSet(o, t, v, device=DEV)
+    fresh = api.pairwise_backward(X, api.PCF_LP_POW, 2.0, G1, deterministic=True)
+    ws = api.Workspace(device=DEV)
+    api.pairwise_backward(X, api.PCF_LP_POW, 2.0, G2, workspace=ws, deterministic=True)
+    again = api.pairwise_backward(X, api.PCF_LP_POW, 2.0, G1, workspace=ws, packed=True,
+                                  deterministic=True)
+    for a, b in zip(fresh, again):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+
+
 def test_deterministic_adjoint_global_path_and_ties():
     # long PCFs (tiles whose records stay in HBM add each term to the
     # fixed-point sums directly) and exact ties on a dyadic grid
@@ -300,9 +338,11 @@ def test_adjoint_global_path_ties():
         assert _close(gt, rt, 1e-10) and _close(gv, rv, 1e-10), name
         X = api.PcfSet(o, t.astype(np.float32), v.astype(np.float32), device=DEV)
         fwd = api.pdist(X, p).to(torch.float64) if (kind == api.PCF_LP and p != 1.0) else None
-        gt, gv = api.pairwise_backward(X, kind, p, torch.as_tensor(G, device=DEV), fwd)
-        assert _close(gt.cpu().numpy().astype(np.float64), rt, 1e-5), name
-        assert _close(gv.cpu().numpy().astype(np.float64), rv, 1e-5), name
+        for det in (False, True):
+            gt, gv = api.pairwise_backward(X, kind, p, torch.as_tensor(G, device=DEV), fwd,
+                                           deterministic=det)
+            assert _close(gt.cpu().numpy().astype(np.float64), rt, 1e-5), (name, det)
+            assert _close(gv.cpu().numpy().astype(np.float64), rv, 1e-5), (name, det)
 
 
 def test_adjoint_long_pcfs_global_path():
