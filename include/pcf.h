@@ -177,8 +177,10 @@ pcf_status pcf_pairwise_lp_noalloc(const pcf_set *X, pcf_kind kind, double p,
  * entries are 0. At an exact tie of two PCFs' breakpoint times the mean of
  * the one-sided time derivatives is used. Each pair's merge is recomputed;
  * nothing is stored between forward and backward. grad_out and fwd_out are
- * FP64 for either dtype; an FP32 set merges and forms its gradient terms in
- * FP32. A tile sums its gradient terms in 64-bit fixed point at power-of-two
+ * FP64 for either dtype, and finite (the fixed-point sums below are scaled
+ * from their magnitudes; a NaN or infinite weight gives undefined
+ * gradients rather than NaN ones); an FP32 set merges and forms its gradient
+ * terms in FP32. A tile sums its gradient terms in 64-bit fixed point at power-of-two
  * scales bounded from its own weights, values and piece lengths
  * (order-independent), and adds the sums to grad_t, grad_v with atomics of
  * the set's dtype, whose order, and so the last bits, may vary between runs.
