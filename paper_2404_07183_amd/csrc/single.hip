@@ -55,6 +55,12 @@ __device__ __forceinline__ double wave_max(double x)
     return x;
 }
 
+// Rows a lane loads per round: lane j takes rows j, j + 64, ..., j + 64 (kRound
+// - 1) of the round, all loads issued before any is used, so a PCF of up to
+// 64 kRound rows costs one memory round trip instead of one per 64 rows. The
+// lane adds its rows in increasing order, as one row at a time would.
+constexpr int kRound = 4;
+
 template <typename T, int SK>
 __global__ void single_functional(SingleArgs a)
 {
@@ -63,26 +69,51 @@ __global__ void single_functional(SingleArgs a)
     T *__restrict__ out = reinterpret_cast<T *>(a.out);
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < a.n;
-         i += nwaves) {
-        const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+    int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    // this wave's PCF row range, loaded one PCF ahead
+    int64_t o0 = 0, o1 = 0;
+    if (i < a.n) {
+        o0 = a.offsets[i];
+        o1 = a.offsets[i + 1];
+    }
+    for (; i < a.n; i += nwaves) {
+        const int64_t in = i + nwaves;
+        int64_t n0 = 0, n1 = 0;
+        if (in < a.n) {
+            n0 = a.offsets[in];
+            n1 = a.offsets[in + 1];
+        }
         double acc = 0.0;
         int tail = 0;  // sign of h on an unbounded last piece
-        for (int64_t k = o0 + lane; k < o1; k += 64) {
-            const double tk = (double)t[k];
-            const double tn = k + 1 < o1 ? (double)t[k + 1] : INFINITY;
-            const double l = tk > a.a ? tk : a.a;
-            const double r = tn < a.b ? tn : a.b;
-            if (r > l) {
-                if constexpr (SK == SK_SUP) {
-                    const double av = fabs((double)v[k]);
-                    acc = av > acc ? av : acc;
-                } else {
-                    const double hv = h_single<SK>((double)v[k], a.p);
-                    if (r == INFINITY)
-                        tail = hv > 0.0 ? 1 : (hv < 0.0 ? -1 : 0);
-                    else
-                        acc += (r - l) * hv;
+        for (int64_t base = o0 + lane; base < o1; base += 64 * kRound) {
+            double tk[kRound], tn[kRound], vk[kRound];
+#pragma unroll
+            for (int u = 0; u < kRound; ++u) {
+                const int64_t k = base + 64 * u;
+                tk[u] = tn[u] = vk[u] = 0.0;
+                if (k < o1) {
+                    tk[u] = (double)t[k];
+                    tn[u] = k + 1 < o1 ? (double)t[k + 1] : INFINITY;
+                    vk[u] = (double)v[k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kRound; ++u) {
+                if (base + 64 * u >= o1)
+                    break;
+                const double l = tk[u] > a.a ? tk[u] : a.a;
+                const double r = tn[u] < a.b ? tn[u] : a.b;
+                if (r > l) {
+                    if constexpr (SK == SK_SUP) {
+                        const double av = fabs(vk[u]);
+                        acc = av > acc ? av : acc;
+                    } else {
+                        const double hv = h_single<SK>(vk[u], a.p);
+                        if (r == INFINITY)
+                            tail = hv > 0.0 ? 1 : (hv < 0.0 ? -1 : 0);
+                        else
+                            acc += (r - l) * hv;
+                    }
                 }
             }
         }
@@ -103,16 +134,20 @@ __global__ void single_functional(SingleArgs a)
                 res = pow(res, 1.0 / a.p);
             out[i] = (T)res;
         }
+        o0 = n0;
+        o1 = n1;
     }
 }
 
 template <typename T, int SK>
 static hipError_t launch_single_t(const SingleArgs &a, hipStream_t s)
 {
-    int64_t blocks = (a.n + 3) / 4;  // 4 waves of 64 per block
-    if (blocks > 8192)
-        blocks = 8192;
-    hipLaunchKernelGGL((single_functional<T, SK>), dim3((unsigned)blocks), dim3(256), 0,
+    // one wave a workgroup (4 % faster than four: a finished wave frees its
+    // slot without waiting for the others of its group)
+    int64_t blocks = a.n;
+    if (blocks > 32768)
+        blocks = 32768;
+    hipLaunchKernelGGL((single_functional<T, SK>), dim3((unsigned)blocks), dim3(64), 0,
                        s, a);
     return hipGetLastError();
 }
