@@ -142,8 +142,7 @@ __global__ void single_functional(SingleArgs a)
 template <typename T, int SK>
 static hipError_t launch_single_t(const SingleArgs &a, hipStream_t s)
 {
-    // one wave a workgroup (4 % faster than four: a finished wave frees its
-    // slot without waiting for the others of its group)
+    // one wave a workgroup (measured 4 % faster than four waves)
     int64_t blocks = a.n;
     if (blocks > 32768)
         blocks = 32768;
