@@ -53,6 +53,26 @@ def test_single_fp32():
     _check(o, t, v, np.float32, 1e-5)
 
 
+def test_single_round_boundaries():
+    # a lane loads four 64-row rounds before adding: PCFs whose row counts
+    # sit on either side of 64, 128, 256 and 512 rows, in mixed order
+    counts = np.array([1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513,
+                       1000] * 3)
+    rng = np.random.default_rng(54)
+    counts = counts[rng.permutation(len(counts))]
+    P = int(counts.sum())
+    o, t, v = workloads._assemble(counts, rng.exponential(1.0, P), rng.standard_normal(P))
+    _check(o, t, v, np.float64, 1e-12)
+    _check(*workloads.to_dtype(o, t, v, np.float32), np.float32, 1e-5)
+
+
+def test_single_more_pcfs_than_waves():
+    # 40,000 PCFs: more than the launch's 32,768 waves, so waves take a
+    # second PCF (whose offsets were loaded while the first was summed)
+    o, t, v = workloads.uniform_counts(40000, 1, 12, seed=55)
+    _check(o, t, v, np.float64, 1e-12)
+
+
 def test_single_full_size_against_pairwise():
     # on the plain 20,000-PCF set: int f^2 equals the Gram diagonal computed
     # by the pairwise kernel, and the norms match the oracle on a sample
