@@ -323,6 +323,7 @@ constexpr int kStdThreads = 512;
 constexpr int kStdRowsPerThread = kChunkRows / kStdThreads;
 constexpr int kStdWindow = kChunkRows + 2 * (int)kStdSmall;
 constexpr int kStdHeights = 7;  // subtree heights 0 .. 6: up to 127 >= kStdSmall terms
+constexpr int kStdBatch = 4;  // PCFs whose bisections run together
 static_assert(kChunkRows % kStdThreads == 0 && kStdSmall == 64 && (1 << kStdHeights) > kStdSmall,
               "red_std_small's layout");
 
@@ -460,47 +461,70 @@ __global__ __launch_bounds__(kStdThreads) void red_std_small(RedStdArgs a)
             for (int h = 0; h < kStdHeights; ++h)
                 st[k][h] = T(0);
         if (ok) {
-            for (int i = 0; i < m; ++i) {
-                const int32_t lo = __builtin_amdgcn_readfirstlane(wbase[i]);
-                const int32_t end = __builtin_amdgcn_readfirstlane(wbase[i + 1]);
-                // last record of PCF i at or before x[0] (rec[lo].t <= x[0])
-                int32_t p = lo;
+            // kStdBatch PCFs at a time: their bisections are independent
+            // chains of LDS reads, interleaved; their terms then join the
+            // counter in PCF order, as one PCF at a time would
+            for (int i0 = 0; i0 < m; i0 += kStdBatch) {
+                int32_t lo[kStdBatch], end[kStdBatch], p[kStdBatch];
+                int32_t span = 1;
+#pragma unroll
+                for (int u = 0; u < kStdBatch; ++u) {
+                    // (past the group: the last PCF again, its terms unused)
+                    const int i = i0 + u < m ? i0 + u : m - 1;
+                    lo[u] = __builtin_amdgcn_readfirstlane(wbase[i]);
+                    end[u] = __builtin_amdgcn_readfirstlane(wbase[i + 1]);
+                    p[u] = lo[u];
+                    span = end[u] - lo[u] > span ? end[u] - lo[u] : span;
+                }
+                // last record of each PCF at or before x[0] (rec[lo].t <=
+                // x[0]); steps of one power of two for all, whose sum
+                // covers the widest window
                 int32_t step = 1;
-                while (2 * step <= end - lo - 1)
+                while (2 * step <= span - 1)
                     step <<= 1;
-                for (int32_t s = end - lo > 1 ? step : 0; s > 0; s >>= 1) {
-                    const int32_t j = p + s < end ? p + s : end - 1;
-                    if (p + s < end && rec[j].t <= x[0])
-                        p = j;
-                }
-                T val[R];
-                val[0] = rec[p].v;
-                T nt = p + 1 < end ? rec[p + 1].t : inf;
+                for (int32_t s = span > 1 ? step : 0; s > 0; s >>= 1) {
 #pragma unroll
-                for (int k = 1; k < R; ++k) {
-                    while (nt <= x[k]) {
-                        ++p;
-                        nt = p + 1 < end ? rec[p + 1].t : inf;
+                    for (int u = 0; u < kStdBatch; ++u) {
+                        const int32_t j = p[u] + s;
+                        if (j < end[u] && rec[j].t <= x[0])
+                            p[u] = j;
                     }
-                    val[k] = rec[p].v;
                 }
-                T s[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const T d = val[k] - mean[k];
-                    s[k] = d * d;
-                }
-                // binary counter: after i + 1 terms st[k][h] holds a complete
-                // subtree of 2^h terms for every set bit h of i + 1; term i
-                // joins the subtrees below the lowest clear bit of i
-                switch (__builtin_ctz(~(unsigned)i)) {
-                case 0: std_counter_add<T, R, 0>(st, s); break;
-                case 1: std_counter_add<T, R, 1>(st, s); break;
-                case 2: std_counter_add<T, R, 2>(st, s); break;
-                case 3: std_counter_add<T, R, 3>(st, s); break;
-                case 4: std_counter_add<T, R, 4>(st, s); break;
-                case 5: std_counter_add<T, R, 5>(st, s); break;
-                default: std_counter_add<T, R, 6>(st, s); break;
+                for (int u = 0; u < kStdBatch; ++u) {
+                    if (i0 + u >= m)
+                        break;
+                    int32_t pr = p[u];
+                    T val[R];
+                    val[0] = rec[pr].v;
+                    T nt = pr + 1 < end[u] ? rec[pr + 1].t : inf;
+#pragma unroll
+                    for (int k = 1; k < R; ++k) {
+                        while (nt <= x[k]) {
+                            ++pr;
+                            nt = pr + 1 < end[u] ? rec[pr + 1].t : inf;
+                        }
+                        val[k] = rec[pr].v;
+                    }
+                    T s[R];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T d = val[k] - mean[k];
+                        s[k] = d * d;
+                    }
+                    // binary counter: after i + 1 terms st[k][h] holds a
+                    // complete subtree of 2^h terms for every set bit h of
+                    // i + 1; term i joins the subtrees below the lowest
+                    // clear bit of i
+                    switch (__builtin_ctz(~(unsigned)(i0 + u))) {
+                    case 0: std_counter_add<T, R, 0>(st, s); break;
+                    case 1: std_counter_add<T, R, 1>(st, s); break;
+                    case 2: std_counter_add<T, R, 2>(st, s); break;
+                    case 3: std_counter_add<T, R, 3>(st, s); break;
+                    case 4: std_counter_add<T, R, 4>(st, s); break;
+                    case 5: std_counter_add<T, R, 5>(st, s); break;
+                    default: std_counter_add<T, R, 6>(st, s); break;
+                    }
                 }
             }
         }
