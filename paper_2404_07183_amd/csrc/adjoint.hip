@@ -37,6 +37,10 @@
 #include "launch.hpp"
 #include "tile.hpp"
 
+// The device library's maximum over the active lanes of a wave (declared
+// here: HIP declares it only with its warp-sync builtins enabled).
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_max_f64(double);
+
 namespace pcf {
 
 // dh/da at (a, b) for h in {|a-b|, (a-b)^2, ab, |a-b|^p}; sign(0) = 0.
@@ -667,12 +671,21 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
                 if (rq.t < S)
                     ml = fmax(ml, (double)rq.t - (t0 < S ? (double)t0 : 0.0));
             }
-            // the tile's maxima through the wave's lanes, then one slot per
-            // wave (the tail-rule values of the scan, unused by the adjoint)
-            for (int h = 32; h >= 1; h >>= 1) {
-                mw = fmax(mw, __shfl_xor(mw, h, 64));
-                mv = fmax(mv, __shfl_xor(mv, h, 64));
-                ml = fmax(ml, __shfl_xor(ml, h, 64));
+            // the tile's maxima through the wave's lanes (every lane is
+            // active here), then one slot per wave (the tail-rule values of
+            // the scan, unused by the adjoint). The general-p kernel keeps the
+            // shuffle butterfly: it is the most register-bound instantiation,
+            // and its code stays as tested.
+            if constexpr (HK == kPow) {
+                for (int h = 32; h >= 1; h >>= 1) {
+                    mw = fmax(mw, __shfl_xor(mw, h, 64));
+                    mv = fmax(mv, __shfl_xor(mv, h, 64));
+                    ml = fmax(ml, __shfl_xor(ml, h, 64));
+                }
+            } else {
+                mw = __ockl_wfred_max_f64(mw);
+                mv = __ockl_wfred_max_f64(mv);
+                ml = __ockl_wfred_max_f64(ml);
             }
             if ((tid & 63) == 0) {
                 sh.rlast[tid >> 6] = mw;
