@@ -795,13 +795,27 @@ __global__ __launch_bounds__(kThreads) void pairwise_adjoint_tiles(BwdArgs args)
             const int32_t *bs = in_rows ? sh.rb : sh.cb;
             const int32_t *ns = in_rows ? sh.rn : sh.cn;
             const int64_t pcf0 = in_rows ? D.r_lo : D.c_lo;
-            int32_t which = 0, hi = nb - 1;
-            while (which < hi) {
-                const int32_t mid = (which + hi + 1) >> 1;
-                if (bs[mid] <= q)
-                    which = mid;
-                else
-                    hi = mid - 1;
+            int32_t which = 0;
+            if constexpr (HK == kPow) {
+                // (the general-p kernels keep their tested code)
+                int32_t hi = nb - 1;
+                while (which < hi) {
+                    const int32_t mid = (which + hi + 1) >> 1;
+                    if (bs[mid] <= q)
+                        which = mid;
+                    else
+                        hi = mid - 1;
+                }
+            } else {
+                // five fixed steps (nb <= 32): straight-line code, so the
+                // searches of a thread's slots overlap
+                static_assert(kMaxBlock <= 32, "lifting steps");
+#pragma unroll
+                for (int32_t st = 16; st > 0; st >>= 1) {
+                    const int32_t j = which + st;
+                    if (j < nb && bs[j] <= q)
+                        which = j;
+                }
             }
             const int64_t kk = q - bs[which];  // record within the PCF
             // padding, and the last record (fixed value, sentinel end time)
